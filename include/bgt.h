@@ -1,0 +1,163 @@
+/*
+ * bgt.h -- C ABI of the BG-Triangle rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * BG-Triangle ("Bezier Gaussian Triangle for 3D Vectorization and
+ * Rendering", CVPR 2025) renders degree-n Bezier triangles (Sec. 3.1, Eq. 1-2)
+ * by tessellating them into flat triangles and rasterizing those into an index
+ * map I_id and a coordinate map I_uv with a boundary set B (Sec. 3.2,
+ * Tessellation and Rasterization).  It then places one Gaussian per foreground
+ * pixel (Sec. 3.2, Sub-Primitive Generation, Eq. 3-5) and alpha-blends them
+ * with the boundary-aware coefficient w (Sec. 3.2, Discontinuity-Aware Alpha
+ * Blending, Eq. 6-8) using tiles with per-tile boundary lists sorted by
+ * primitive id (Sec. 3.2, Rendering Acceleration).  The backward pass follows
+ * Supplementary Sec. C.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are device memory unless marked (host).  Every call only
+ *    enqueues work on `stream` (a hipStream_t; NULL = the null stream) and
+ *    never synchronizes, except bgt_query.
+ *  - The caller owns every input, output and `state` buffer.  The library
+ *    allocates nothing per call, so calls are safe under stream capture.
+ *  - Errors are return codes.  Argument errors give BGT_E_INVALID before any
+ *    work is enqueued; bgt_last_error(ctx) has the text.
+ *  - A context is not thread-safe; use one context per host thread.
+ *
+ * Layouts (structure of arrays, float32)
+ *  - ncp = (n+1)(n+2)/2 control points, indexed in the order of Eq. 1's
+ *    double sum: i = 0..n outer, j = 0..n-i inner, k = n-i-j; u pairs with
+ *    i, v with j, w with k.
+ *  - ctrl, color_ctrl: [3][ncp][P]; log_scale: [3][T][P]; quat: [4][T][P]
+ *    as (w,x,y,z), T = R(R+1)/2 texels of the attribute map (R = attr_res);
+ *    opacity, sharpness: [P].
+ *  - Camera v: 16 floats = world-to-camera rotation R (row-major 3x3),
+ *    translation t (3), fx, fy, cx, cy.  Axes x right, y down, z forward;
+ *    pixel (i, j) has its centre at (i + 0.5, j + 0.5).
+ *  - Images: packed HWC float32, view v starting at pixel offset
+ *    sum_{u<v} W_u H_u, i.e. element 3 * (offset + y W_v + x) + channel.
+ */
+#ifndef BGT_H
+#define BGT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BGT_OK = 0,
+    BGT_E_INVALID = 1,     /* bad argument; nothing was enqueued */
+    BGT_E_NOMEM = 2,       /* state buffer too small or host allocation failed */
+    BGT_E_OVERFLOW = 3,    /* a pair capacity was exceeded (see bgt_query) */
+    BGT_E_HIP = 4,         /* a HIP runtime call failed */
+    BGT_E_UNSUPPORTED = 5  /* valid request outside what this build implements */
+} bgt_status;
+
+#define BGT_MAX_VIEWS 64
+#define BGT_MAX_DEGREE 5
+
+typedef struct bgt_ctx bgt_ctx;
+
+/* BG-Triangle parameters (Sec. 3.1 control points p_ijk; Sec. 3.2 colour
+ * control points p^c_ijk and attribute maps M_h; opacity o, Eq. 8).
+ * `sharpness` s_g sets the boundary Gaussian scale r_b = r_ref / s_g. */
+typedef struct {
+    int32_t degree;      /* n, 1..BGT_MAX_DEGREE */
+    int32_t num_prims;   /* P >= 1 */
+    int32_t attr_res;    /* R; this build implements R = 1 */
+    int32_t reserved;
+    const float *ctrl, *color_ctrl, *log_scale, *quat, *opacity, *sharpness;
+} bgt_prims;
+
+/* Gradients, same layouts as bgt_prims; every array is overwritten. */
+typedef struct {
+    float *ctrl, *color_ctrl, *log_scale, *quat, *opacity, *sharpness;
+} bgt_grads;
+
+/* A batch of views rendered together in one call. */
+typedef struct {
+    int32_t n_views;        /* 1..BGT_MAX_VIEWS */
+    int32_t reserved;
+    const int32_t *wh;      /* (host) [2 n_views]: width, height of each view */
+    const float *cams;      /* [n_views][16] cameras, see Layouts */
+} bgt_views;
+
+/* Rendering constants.  bgt_default_config fills the values this library
+ * documents for each reading of the paper. */
+typedef struct {
+    int32_t tess_level;    /* L, sub-triangles per patch L^2, 1..8 (default 4) */
+    int32_t tile;          /* blending tile side: 8, 16 or 32 (default 16) */
+    int32_t batch;         /* Gaussians staged per LDS batch: 32, 64 or 128 */
+    int32_t flags;         /* reserved, 0 */
+    float z_near;          /* cull distance along the optical axis (0.2) */
+    float g_min;           /* Gaussian support: G >= g_min (2^-15) */
+    float t_min;           /* stop once transmittance < t_min (2^-15) */
+    float alpha_max;       /* alpha clamp (0.99) */
+    float dilation;        /* 2-D low-pass added to projected covariances (0.3) */
+    float r_ref;           /* r_b = r_ref / sharpness (1e-2) */
+    float bg[3];           /* background colour (0, 0, 0) */
+    float pair_factor;     /* Gaussian-tile pair capacity per pixel (4) */
+    float bpair_factor;    /* boundary-tile pair capacity per pixel (2) */
+} bgt_config;
+
+void bgt_default_config(bgt_config *cfg);
+
+/* Host-only argument checks (no device work, no context needed). */
+bgt_status bgt_validate_config(const bgt_config *cfg);
+bgt_status bgt_validate_prims(const bgt_prims *prims, const bgt_config *cfg);
+bgt_status bgt_validate_views(const bgt_views *views);
+
+/* Create a context on HIP device `device`; device -1 gives a host-only
+ * context that can size and validate but not enqueue work.  *out is NULL on
+ * failure. */
+bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out);
+void bgt_destroy(bgt_ctx *ctx);
+/* Text of the last error on this context (never NULL). */
+const char *bgt_last_error(const bgt_ctx *ctx);
+
+/* Tessellation lattice (Sec. 3.1 Eq. 1 evaluated at the nodes of Sec. 3.2's
+ * tessellation): verts[3][VL][P], VL = (L+1)(L+2)/2, node m enumerating
+ * (a, b) with a = 0..L outer, b = 0..L-a inner at (u, v, w) = (a/L, b/L,
+ * 1-(a+b)/L).  Evaluated in FP64, stored as float32. */
+bgt_status bgt_tessellate(bgt_ctx *ctx, const bgt_prims *prims, float *verts, void *stream);
+
+/* Bytes of the caller-owned state buffer for a (prims, views) shape.  The
+ * state holds everything the backward pass reads plus the forward pass's
+ * scratch; its pair lists are sized by pair_factor and bpair_factor. */
+bgt_status bgt_state_size(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                          size_t *bytes);
+
+/* Byte offsets (host out[BGT_STATE_FIELDS]) of the state's sections, for
+ * inspection and tests.  Order: counters, zbuf(u64), I_tri(i32), I_uv(f32x2),
+ * pflags(u8), rec(f32x16), gkey(u64), T_final(f32), last(i32), verts,
+ * g_count, g_start, g_cursor, b_count, b_start, b_cursor, g_keys(u64),
+ * g_list(u32), b_keys(u64), b_list(u32), dgauss(f32x12), big_tris, scan. */
+#define BGT_STATE_FIELDS 24
+bgt_status bgt_state_layout(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                            int64_t *offsets);
+
+/* Forward pass over all views: images [sum W H][3] (overwritten). */
+bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                          float *images, void *state, size_t state_bytes, void *stream);
+
+/* Backward pass (Supplementary Sec. C with I_id, I_uv and B frozen).
+ * `images` are the forward outputs of the same call's state; grad_images is
+ * dl/dC in the same layout.  All gradient arrays are overwritten. */
+bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                          const float *images, const float *grad_images, void *state,
+                          size_t state_bytes, const bgt_grads *grads, void *stream);
+
+/* Synchronizes `stream` and reads the state's counters (host out[8]):
+ * [0] overflow flags (bit0 Gaussian pairs, bit1 boundary pairs, bit2 big
+ * triangle queue), [1] Gaussian pairs, [2] boundary pairs, [3] foreground
+ * pixels, [4] boundary pixels, [5] big triangles, [6] tiles needing the
+ * global sort, [7] tiles whose boundary list exceeded LDS.  Returns
+ * BGT_E_OVERFLOW when any overflow flag is set. */
+bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGT_H */

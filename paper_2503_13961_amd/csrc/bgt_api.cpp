@@ -1,0 +1,343 @@
+// Host side of the bgt C ABI: context, state layout and the launch sequence
+// of the forward and backward passes.  Every entry point validates its
+// arguments before enqueuing anything and never allocates device memory.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "bgt_internal.h"
+
+struct bgt_ctx {
+    bgt_config cfg;
+    int device;
+    std::string err;
+};
+
+namespace {
+
+using namespace bgt;
+
+enum Field {
+    F_COUNTERS, F_ZBUF, F_ITRI, F_IUV, F_PFLAGS, F_REC, F_GKEY, F_TFINAL, F_LAST, F_VERTS, F_GCOUNT, F_GSTART,
+    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_DGAUSS, F_BIGTRI, F_SCAN, F_END
+};
+static_assert(F_END + 1 == BGT_STATE_FIELDS, "state field count");
+
+struct Shape {
+    ViewTable vt;
+    Consts k;
+    int64_t N, NT;
+    int64_t off[BGT_STATE_FIELDS];
+    int64_t wverts_off, bigsort_off;
+};
+
+bgt_status fail(bgt_ctx *ctx, bgt_status st, const char *msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+bgt_status hip_fail(bgt_ctx *ctx, hipError_t e, const char *where) {
+    if (ctx) {
+        ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return BGT_E_HIP;
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Shape &sh) {
+    bgt_status s;
+    if ((s = bgt_validate_prims(pr, &ctx->cfg)) != BGT_OK) return fail(ctx, s, "invalid or unsupported prims");
+    if ((s = bgt_validate_views(vw)) != BGT_OK) return fail(ctx, s, "invalid views");
+    const bgt_config &c = ctx->cfg;
+    memset(&sh, 0, sizeof(sh));
+    Consts &k = sh.k;
+    k.L = c.tess_level;
+    k.L2 = k.L * k.L;
+    k.VL = (k.L + 1) * (k.L + 2) / 2;
+    k.tile = c.tile;
+    k.degree = pr->degree;
+    k.ncp = (pr->degree + 1) * (pr->degree + 2) / 2;
+    k.P = pr->num_prims;
+    k.T = pr->attr_res * (pr->attr_res + 1) / 2;
+    k.batch = c.batch;
+    k.z_near = c.z_near;
+    k.g_min = c.g_min;
+    k.t_min = c.t_min;
+    k.alpha_max = c.alpha_max;
+    k.dilation = c.dilation;
+    k.r_ref = c.r_ref;
+    for (int i = 0; i < 3; ++i) k.bg[i] = c.bg[i];
+    const double k2 = 2.0 * log(1.0 / (double)c.g_min);
+    k.kappa2 = (float)k2;
+    k.kappa = sqrt(k2);
+    ViewTable &vt = sh.vt;
+    vt.n = vw->n_views;
+    int64_t px = 0, tiles = 0, b8 = 0;
+    for (int v = 0; v < vw->n_views; ++v) {
+        ViewInfo &vi = vt.v[v];
+        vi.W = vw->wh[2 * v];
+        vi.H = vw->wh[2 * v + 1];
+        vi.tiles_x = (vi.W + c.tile - 1) / c.tile;
+        vi.tiles_y = (vi.H + c.tile - 1) / c.tile;
+        vi.px_off = (int32_t)px;
+        vi.tile_off = (int32_t)tiles;
+        px += (int64_t)vi.W * vi.H;
+        tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+        b8 += (int64_t)((vi.W + 7) / 8) * ((vi.H + 7) / 8);
+    }
+    vt.total_px = (int32_t)px;
+    vt.total_tiles = (int32_t)tiles;
+    vt.total_b8 = (int32_t)b8;
+    sh.N = px;
+    sh.NT = tiles;
+    const int64_t N = px, NT = tiles;
+    k.cap_g = (int64_t)ceil((double)c.pair_factor * (double)N) + 1024;
+    k.cap_b = (int64_t)ceil((double)c.bpair_factor * (double)N) + 1024;
+    if (k.cap_g >= ((int64_t)1 << 31) || k.cap_b >= ((int64_t)1 << 31))
+        return fail(ctx, BGT_E_INVALID, "pair capacity exceeds 2^31");
+    k.cap_big = (int64_t)vt.n * k.L2 * k.P;
+    const int64_t nb_scan = (NT + 1023) / 1024;
+    int64_t o = 0;
+    auto put = [&](int f, int64_t bytes) { sh.off[f] = o; o = align256(o + bytes); };
+    put(F_COUNTERS, C_NUM * 8);
+    put(F_ZBUF, 8 * N);
+    put(F_ITRI, 4 * N);
+    put(F_IUV, 8 * N);
+    put(F_PFLAGS, N);
+    put(F_REC, 64 * N);
+    put(F_GKEY, 8 * N);
+    put(F_TFINAL, 4 * N);
+    put(F_LAST, 4 * N);
+    {
+        const int64_t vbytes = (int64_t)sizeof(VertRec) * vt.n * k.VL * k.P;
+        const int64_t wbytes = 24 * (int64_t)k.VL * k.P;
+        sh.off[F_VERTS] = o;
+        sh.wverts_off = align256(o + vbytes);
+        o = align256(sh.wverts_off + wbytes);
+    }
+    put(F_GCOUNT, 4 * NT);
+    put(F_GSTART, 4 * NT);
+    put(F_GCURSOR, 4 * NT);
+    put(F_BCOUNT, 4 * NT);
+    put(F_BSTART, 4 * NT);
+    put(F_BCURSOR, 4 * NT);
+    put(F_GKEYS, 8 * k.cap_g);
+    put(F_GLIST, 4 * k.cap_g);
+    put(F_BKEYS, 8 * k.cap_b);
+    put(F_BLIST, 4 * k.cap_b);
+    put(F_DGAUSS, 48 * N);
+    put(F_BIGTRI, 4 * k.cap_big);
+    {
+        sh.off[F_SCAN] = o;
+        sh.bigsort_off = align256(o + 16 * nb_scan);
+        o = align256(sh.bigsort_off + 8 * NT);
+    }
+    sh.off[F_END] = o;
+    return BGT_OK;
+}
+
+StatePtrs state_ptrs(const Shape &sh, void *state) {
+    char *b = (char *)state;
+    StatePtrs p;
+    p.counters = (int64_t *)(b + sh.off[F_COUNTERS]);
+    p.zbuf = (unsigned long long *)(b + sh.off[F_ZBUF]);
+    p.I_tri = (int32_t *)(b + sh.off[F_ITRI]);
+    p.I_uv = (float2 *)(b + sh.off[F_IUV]);
+    p.pflags = (uint8_t *)(b + sh.off[F_PFLAGS]);
+    p.rec = (float4 *)(b + sh.off[F_REC]);
+    p.gkey = (unsigned long long *)(b + sh.off[F_GKEY]);
+    p.T_final = (float *)(b + sh.off[F_TFINAL]);
+    p.last = (int32_t *)(b + sh.off[F_LAST]);
+    p.verts = (VertRec *)(b + sh.off[F_VERTS]);
+    p.wverts = (double *)(b + sh.wverts_off);
+    p.g_count = (int32_t *)(b + sh.off[F_GCOUNT]);
+    p.g_start = (int32_t *)(b + sh.off[F_GSTART]);
+    p.g_cursor = (int32_t *)(b + sh.off[F_GCURSOR]);
+    p.b_count = (int32_t *)(b + sh.off[F_BCOUNT]);
+    p.b_start = (int32_t *)(b + sh.off[F_BSTART]);
+    p.b_cursor = (int32_t *)(b + sh.off[F_BCURSOR]);
+    p.g_keys = (unsigned long long *)(b + sh.off[F_GKEYS]);
+    p.g_list = (uint32_t *)(b + sh.off[F_GLIST]);
+    p.b_keys = (unsigned long long *)(b + sh.off[F_BKEYS]);
+    p.b_list = (uint32_t *)(b + sh.off[F_BLIST]);
+    p.dgauss = (float *)(b + sh.off[F_DGAUSS]);
+    p.big_tris = (int32_t *)(b + sh.off[F_BIGTRI]);
+    p.scan_tmp = (int32_t *)(b + sh.off[F_SCAN]);
+    p.bigsort_q = (int32_t *)(b + sh.bigsort_off);
+    return p;
+}
+
+PrimPtrs prim_ptrs(const bgt_prims *p) {
+    PrimPtrs r;
+    r.ctrl = p->ctrl;
+    r.color = p->color_ctrl;
+    r.log_scale = p->log_scale;
+    r.quat = p->quat;
+    r.opacity = p->opacity;
+    r.sharp = p->sharpness;
+    return r;
+}
+
+bgt_status use_device(bgt_ctx *ctx) {
+    if (ctx->device < 0) return fail(ctx, BGT_E_INVALID, "host-only context cannot enqueue work");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDevice");
+    if (cur != ctx->device) {
+        e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    }
+    return BGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out) {
+    if (!out) return BGT_E_INVALID;
+    *out = nullptr;
+    bgt_config c;
+    if (cfg) c = *cfg; else bgt_default_config(&c);
+    if (bgt_validate_config(&c) != BGT_OK) return BGT_E_INVALID;
+    if (device != -1) {  // -1: host-only context (sizing and validation, no rendering)
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BGT_E_INVALID;
+    }
+    bgt_ctx *ctx = new (std::nothrow) bgt_ctx;
+    if (!ctx) return BGT_E_NOMEM;
+    ctx->cfg = c;
+    ctx->device = device;
+    *out = ctx;
+    return BGT_OK;
+}
+
+void bgt_destroy(bgt_ctx *ctx) { delete ctx; }
+
+const char *bgt_last_error(const bgt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+bgt_status bgt_tessellate(bgt_ctx *ctx, const bgt_prims *prims, float *verts, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    bgt_status s = bgt_validate_prims(prims, &ctx->cfg);
+    if (s != BGT_OK) return fail(ctx, s, "invalid or unsupported prims");
+    if (!verts) return fail(ctx, BGT_E_INVALID, "verts is null");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    Consts k;
+    memset(&k, 0, sizeof(k));
+    k.L = ctx->cfg.tess_level;
+    k.L2 = k.L * k.L;
+    k.VL = (k.L + 1) * (k.L + 2) / 2;
+    k.degree = prims->degree;
+    k.ncp = (prims->degree + 1) * (prims->degree + 2) / 2;
+    k.P = prims->num_prims;
+    hipError_t e = launch_tessellate(k, prim_ptrs(prims), nullptr, verts, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tessellate");
+    return BGT_OK;
+}
+
+bgt_status bgt_state_size(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views, size_t *bytes) {
+    if (!ctx || !bytes) return BGT_E_INVALID;
+    Shape sh;
+    bgt_status s = make_shape(ctx, prims, views, sh);
+    if (s != BGT_OK) return s;
+    *bytes = (size_t)sh.off[F_END];
+    return BGT_OK;
+}
+
+bgt_status bgt_state_layout(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views, int64_t *offsets) {
+    if (!ctx || !offsets) return BGT_E_INVALID;
+    Shape sh;
+    bgt_status s = make_shape(ctx, prims, views, sh);
+    if (s != BGT_OK) return s;
+    for (int i = 0; i < BGT_STATE_FIELDS; ++i) offsets[i] = sh.off[i];
+    return BGT_OK;
+}
+
+bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views, float *images,
+                          void *state, size_t state_bytes, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    Shape sh;
+    bgt_status s = make_shape(ctx, prims, views, sh);
+    if (s != BGT_OK) return s;
+    if (!images || !state) return fail(ctx, BGT_E_INVALID, "images or state is null");
+    if (state_bytes < (size_t)sh.off[F_END]) return fail(ctx, BGT_E_NOMEM, "state buffer too small");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const StatePtrs sp = state_ptrs(sh, state);
+    const PrimPtrs pp = prim_ptrs(prims);
+    hipError_t e;
+    if ((e = launch_fill_u64((unsigned long long *)sp.counters, 0ull, C_NUM, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    if ((e = launch_fill_u64(sp.zbuf, 0ull, sh.N, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    if ((e = launch_fill_i32(sp.g_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    if ((e = launch_fill_i32(sp.b_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    if ((e = launch_geometry(sh.k, sh.vt, pp, views->cams, sp, st)) != hipSuccess) return hip_fail(ctx, e, "geometry");
+    if ((e = launch_binning(sh.k, sh.vt, sp, st)) != hipSuccess) return hip_fail(ctx, e, "binning");
+    if ((e = launch_blend_fwd(sh.k, sh.vt, sp, images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_fwd");
+    return BGT_OK;
+}
+
+bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views, const float *images,
+                          const float *grad_images, void *state, size_t state_bytes, const bgt_grads *grads,
+                          void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    Shape sh;
+    bgt_status s = make_shape(ctx, prims, views, sh);
+    if (s != BGT_OK) return s;
+    if (!images || !grad_images || !state || !grads) return fail(ctx, BGT_E_INVALID, "null pointer argument");
+    if (!grads->ctrl || !grads->color_ctrl || !grads->log_scale || !grads->quat || !grads->opacity ||
+        !grads->sharpness)
+        return fail(ctx, BGT_E_INVALID, "null gradient array");
+    if (state_bytes < (size_t)sh.off[F_END]) return fail(ctx, BGT_E_NOMEM, "state buffer too small");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const StatePtrs sp = state_ptrs(sh, state);
+    const PrimPtrs pp = prim_ptrs(prims);
+    GradPtrs gp;
+    gp.ctrl = grads->ctrl;
+    gp.color = grads->color_ctrl;
+    gp.log_scale = grads->log_scale;
+    gp.quat = grads->quat;
+    gp.opacity = grads->opacity;
+    gp.sharp = grads->sharpness;
+    const Consts &k = sh.k;
+    hipError_t e = hipSuccess;
+    const int64_t nc = 3LL * k.ncp * k.P;
+    if ((e = launch_fill_f32(gp.ctrl, 0.f, nc, st)) != hipSuccess ||
+        (e = launch_fill_f32(gp.color, 0.f, nc, st)) != hipSuccess ||
+        (e = launch_fill_f32(gp.log_scale, 0.f, 3LL * k.T * k.P, st)) != hipSuccess ||
+        (e = launch_fill_f32(gp.quat, 0.f, 4LL * k.T * k.P, st)) != hipSuccess ||
+        (e = launch_fill_f32(gp.opacity, 0.f, k.P, st)) != hipSuccess ||
+        (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess ||
+        (e = launch_fill_f32(sp.dgauss, 0.f, 12 * sh.N, st)) != hipSuccess)
+        return hip_fail(ctx, e, "fill");
+    if ((e = launch_blend_bwd(k, sh.vt, sp, images, grad_images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_bwd");
+    if ((e = launch_param_bwd(k, sh.vt, pp, views->cams, sp, gp, st)) != hipSuccess) return hip_fail(ctx, e, "param_bwd");
+    return BGT_OK;
+}
+
+bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters, void *stream) {
+    if (!ctx || !state || !counters || state_bytes < (size_t)(C_NUM * 8)) return BGT_E_INVALID;
+    bgt_status s;
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    int64_t c[C_NUM];
+    e = hipMemcpy(c, state, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy");
+    counters[0] = c[C_OVERFLOW];
+    counters[1] = c[C_GPAIRS];
+    counters[2] = c[C_BPAIRS];
+    counters[3] = c[C_FG];
+    counters[4] = c[C_BOUNDARY];
+    counters[5] = c[C_BIGTRI];
+    counters[6] = c[C_BIGSORT];
+    counters[7] = c[C_BIGBLIST];
+    if (c[C_OVERFLOW]) return fail(ctx, BGT_E_OVERFLOW, "pair capacity exceeded; raise pair_factor/bpair_factor");
+    return BGT_OK;
+}
+
+}  // extern "C"

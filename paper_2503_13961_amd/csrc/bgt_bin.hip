@@ -1,0 +1,251 @@
+// Tile binning for the rendering acceleration of Sec. 3.2: Gaussians go to
+// every tile their support reaches, sorted front to back within the tile;
+// boundary points go to every tile their radius reaches, sorted by primitive
+// id.  The sort is a two-level radix split: a counting pass on the tile id
+// (the high key digit) places each pair in its tile's segment, then each
+// segment is sorted on the low digits (depth, raster index) or (primitive,
+// raster index) with a bitonic network in LDS.  The low digits make every
+// key unique, so the result does not depend on the order of the atomics that
+// filled the segment.
+#include "bgt_internal.h"
+
+namespace bgt {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanBlock = kScanThreads * kScanItems;  // 1024
+
+// inclusive scan over a wave (64 lanes)
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// exclusive block scan of one value per thread; returns the block total
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T &total, T *lds_waves) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    T inc = wave_inclusive_scan(x);
+    if (lane == 63) lds_waves[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        T w = lane < nw ? lds_waves[lane] : T(0);
+        T wi = wave_inclusive_scan(w);
+        if (lane < nw) lds_waves[lane] = wi - w;
+        if (lane == nw - 1) lds_waves[32] = wi;
+    }
+    __syncthreads();
+    T res = inc - x + lds_waves[wave];
+    total = lds_waves[32];
+    __syncthreads();
+    return res;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t *gc, const int32_t *bc, int n,
+                                                              int64_t *sums, int nb) {
+    __shared__ int64_t ws[33];
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int64_t sg = 0, sb = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) { sg += gc[base + i]; sb += bc[base + i]; }
+    int64_t tg, tb;
+    block_exclusive_scan<int64_t>(sg, tg, ws);
+    block_exclusive_scan<int64_t>(sb, tb, ws);
+    if (threadIdx.x == 0) { sums[blockIdx.x] = tg; sums[nb + blockIdx.x] = tb; }
+}
+
+// exclusive scan of the block sums (one block), totals into the counters
+__global__ void __launch_bounds__(1024) k_scan_top(int64_t *sums, int nb, int64_t *counters) {
+    __shared__ int64_t ws[33];
+    for (int which = 0; which < 2; ++which) {
+        int64_t carry = 0;
+        int64_t *s = sums + (int64_t)which * nb;
+        for (int base = 0; base < nb; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            int64_t x = i < nb ? s[i] : 0, tot;
+            int64_t ex = block_exclusive_scan<int64_t>(x, tot, ws);
+            if (i < nb) s[i] = ex + carry;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) counters[which == 0 ? C_GPAIRS : C_BPAIRS] = carry;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(int32_t *gc, int32_t *gs, int32_t *gcur, int32_t *bc,
+                                                            int32_t *bs, int32_t *bcur, const int64_t *sums,
+                                                            int n, int nb, int64_t cap_g, int64_t cap_b,
+                                                            int64_t *counters) {
+    __shared__ int64_t ws[33];
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    for (int which = 0; which < 2; ++which) {
+        int32_t *cnt = which == 0 ? gc : bc;
+        int32_t *st = which == 0 ? gs : bs;
+        int32_t *cur = which == 0 ? gcur : bcur;
+        const int64_t cap = which == 0 ? cap_g : cap_b;
+        int64_t v[kScanItems], s = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = base + i < n ? cnt[base + i] : 0;
+            s += v[i];
+        }
+        int64_t tot;
+        int64_t off = block_exclusive_scan<int64_t>(s, tot, ws) + sums[(int64_t)which * nb + blockIdx.x];
+        bool ovf = false;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < n) {
+                int64_t c = v[i];
+                if (off + c > cap) { c = off < cap ? cap - off : 0; ovf = true; }
+                const int64_t sclamp = off < cap ? off : cap;
+                st[base + i] = (int32_t)sclamp;
+                cur[base + i] = (int32_t)sclamp;
+                cnt[base + i] = (int32_t)c;
+            }
+            off += v[i];
+        }
+        if (ovf) atomicOr((unsigned long long *)&counters[C_OVERFLOW], which == 0 ? 1ull : 2ull);
+    }
+}
+
+// ------------------------------------------------------------ scatter
+
+__global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePtrs st) {
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= vt.total_px) return;
+    const uint8_t fl = st.pflags[pix];
+    if (!(fl & PF_VALID)) return;
+    const int v = view_of_pixel(vt, pix);
+    const ViewInfo vi = vt.v[v];
+    const unsigned long long local = (unsigned long long)(pix - vi.px_off);
+    const float4 r3 = st.rec[(int64_t)pix * 4 + 3];
+    const int TS = k.tile;
+    {
+        const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
+        const int i0 = lo16(gx), i1 = hi16(gx), j0 = lo16(gy), j1 = hi16(gy);
+        const unsigned long long key = (st.gkey[pix] << 24) | local;
+        if (i0 <= i1 && j0 <= j1)
+            for (int ty = j0 / TS; ty <= j1 / TS; ++ty)
+                for (int tx = i0 / TS; tx <= i1 / TS; ++tx) {
+                    const int t = vi.tile_off + ty * vi.tiles_x + tx;
+                    const int slot = atomicAdd(&st.g_cursor[t], 1);
+                    if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = key;
+                }
+    }
+    if (fl & PF_BOUNDARY) {
+        const int bx = __float_as_int(r3.z), by = __float_as_int(r3.w);
+        const int i0 = lo16(bx), i1 = hi16(bx), j0 = lo16(by), j1 = hi16(by);
+        const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
+        const unsigned long long key = ((unsigned long long)prim << 24) | local;
+        if (i0 <= i1 && j0 <= j1)
+            for (int ty = j0 / TS; ty <= j1 / TS; ++ty)
+                for (int tx = i0 / TS; tx <= i1 / TS; ++tx) {
+                    const int t = vi.tile_off + ty * vi.tiles_x + tx;
+                    const int slot = atomicAdd(&st.b_cursor[t], 1);
+                    if (slot < st.b_start[t] + st.b_count[t]) st.b_keys[slot] = key;
+                }
+    }
+}
+
+// ------------------------------------------------------------ segment sort
+
+// Ascending bitonic network whose first step of every merge compares mirrored
+// positions; positions >= n behave as +inf and never move, so a segment is
+// padded virtually to the next power of two.
+template <typename Get, typename CmpX>
+__device__ __forceinline__ void bitonic_steps(int n2, CmpX cmpx) {
+    for (int kk = 2; kk <= n2; kk <<= 1) {
+        const int half = kk >> 1;
+        for (int q = threadIdx.x; q < (n2 >> 1); q += blockDim.x) {
+            const int blk = q / half, pos = q % half;
+            cmpx(blk * kk + pos, blk * kk + kk - 1 - pos);
+        }
+        __syncthreads();
+        for (int j = kk >> 2; j >= 1; j >>= 1) {
+            for (int q = threadIdx.x; q < (n2 >> 1); q += blockDim.x) {
+                const int blk = q / j, pos = q % j;
+                const int a = blk * 2 * j + pos;
+                cmpx(a, a + j);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct NoGet {};
+
+__global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st) {
+    __shared__ unsigned long long keys[kSortLds];
+    const int t = blockIdx.x, which = blockIdx.y;
+    const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
+    if (cnt == 0) return;
+    const int start = which == 0 ? st.g_start[t] : st.b_start[t];
+    if (cnt > kSortLds) {
+        if (threadIdx.x == 0) {
+            const long long q = atomicAdd((unsigned long long *)&st.counters[C_BIGSORT_Q + which], 1ull);
+            st.bigsort_q[(int64_t)which * vt.total_tiles + q] = t;
+            atomicAdd((unsigned long long *)&st.counters[C_BIGSORT], 1ull);
+        }
+        return;
+    }
+    const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
+    int n2 = 1;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) keys[i] = i < cnt ? src[start + i] : ~0ull;
+    __syncthreads();
+    bitonic_steps<NoGet>(n2, [&](int a, int b) {
+        const unsigned long long x = keys[a], y = keys[b];
+        if (y < x) { keys[a] = y; keys[b] = x; }
+    });
+    const int off = vt.v[view_of_tile(vt, t)].px_off;
+    uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) dst[start + i] = (uint32_t)(off + (int)(keys[i] & 0xFFFFFFull));
+}
+
+// Segments longer than the LDS buffer: same network on global memory, one
+// block per segment (rare; correctness path).
+__global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st) {
+    const int which = blockIdx.y;
+    const int64_t nq = st.counters[C_BIGSORT_Q + which];
+    for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+        const int t = st.bigsort_q[(int64_t)which * vt.total_tiles + qi];
+        const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
+        const int start = which == 0 ? st.g_start[t] : st.b_start[t];
+        unsigned long long *keys = (which == 0 ? st.g_keys : st.b_keys) + start;
+        int n2 = 1;
+        while (n2 < cnt) n2 <<= 1;
+        bitonic_steps<NoGet>(n2, [&](int a, int b) {
+            if (b >= cnt) return;
+            const unsigned long long x = keys[a], y = keys[b];
+            if (y < x) { keys[a] = y; keys[b] = x; }
+        });
+        const int off = vt.v[view_of_tile(vt, t)].px_off;
+        uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) dst[start + i] = (uint32_t)(off + (int)(keys[i] & 0xFFFFFFull));
+        __syncthreads();
+    }
+}
+
+hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s) {
+    const int n = vt.total_tiles;
+    const int nb = (n + kScanBlock - 1) / kScanBlock;
+    int64_t *sums = (int64_t *)st.scan_tmp;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, (const int32_t *)st.g_count,
+                       (const int32_t *)st.b_count, n, sums, nb);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, st.counters);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, st.g_count, st.g_start, st.g_cursor,
+                       st.b_count, st.b_start, st.b_cursor, (const int64_t *)sums, n, nb, k.cap_g, k.cap_b,
+                       st.counters);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((vt.total_px + 255) / 256)), dim3(256), 0, s, k, vt, st);
+    hipLaunchKernelGGL(k_sort_tiles, dim3(n, 2), dim3(256), 0, s, vt, st);
+    hipLaunchKernelGGL(k_sort_big, dim3(64, 2), dim3(256), 0, s, vt, st);
+    return hipGetLastError();
+}
+
+}  // namespace bgt

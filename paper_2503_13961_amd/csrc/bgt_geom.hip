@@ -1,0 +1,521 @@
+// Geometry stages of the BG-Triangle rasterizer on gfx950:
+//   tessellation lattice (Sec. 3.1 Eq. 1-2 at the nodes of Sec. 3.2),
+//   projection + fixed-point snapping, depth-tested raster into a 64-bit
+//   z-buffer, and per-pixel resolve + sub-primitive generation (Sec. 3.2,
+//   Eq. 3-5, EWA splatting) with the boundary set B and boundary radii.
+//
+// Every quantity that decides an integer (snapped coordinates, coverage,
+// depth order, tile ranges) is computed in FP64.  The blending stages read
+// FP32 copies.
+#include "bgt_internal.h"
+
+namespace bgt {
+
+// ------------------------------------------------------------ fill kernels
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int fill_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Bernstein basis
+
+// n!/(i! j! k!) u^i v^j w^k in the order of Eq. 1's double sum.
+template <int DEG, typename T>
+__device__ __forceinline__ void bernstein(T u, T v, T w, T *B) {
+    constexpr double fact[6] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0};
+    T pu[DEG + 1], pv[DEG + 1], pw[DEG + 1];
+    pu[0] = pv[0] = pw[0] = T(1);
+#pragma unroll
+    for (int e = 1; e <= DEG; ++e) {
+        pu[e] = pu[e - 1] * u;
+        pv[e] = pv[e - 1] * v;
+        pw[e] = pw[e - 1] * w;
+    }
+    int idx = 0;
+#pragma unroll
+    for (int i = 0; i <= DEG; ++i)
+#pragma unroll
+        for (int j = 0; j <= DEG - i; ++j) {
+            const int kk = DEG - i - j;
+            B[idx++] = T(fact[DEG] / (fact[i] * fact[j] * fact[kk])) * pu[i] * pv[j] * pw[kk];
+        }
+}
+
+// ------------------------------------------------------------ tessellation
+
+// (a, b) of lattice node m: a = 0..L outer, b = 0..L-a inner
+__device__ __forceinline__ void lattice_node(int L, int m, int &a, int &b) {
+    a = 0;
+    while (m > L - a) { m -= L - a + 1; ++a; }
+    b = m;
+}
+
+__device__ __forceinline__ int lattice_index(int L, int a, int b) { return a * (L + 1) - a * (a - 1) / 2 + b; }
+
+// lattice indices of the three corners of flat sub-triangle s (up triangles
+// (a,b),(a+1,b),(a,b+1) first, then down triangles (a+1,b),(a+1,b+1),(a,b+1))
+__device__ __forceinline__ void subtri_corners(int L, int s, int *m) {
+    const int up = L * (L + 1) / 2;
+    int a = 0;
+    if (s < up) {
+        while (s >= L - a) { s -= L - a; ++a; }
+        m[0] = lattice_index(L, a, s);
+        m[1] = lattice_index(L, a + 1, s);
+        m[2] = lattice_index(L, a, s + 1);
+    } else {
+        s -= up;
+        while (s >= L - 1 - a) { s -= L - 1 - a; ++a; }
+        m[0] = lattice_index(L, a + 1, s);
+        m[1] = lattice_index(L, a + 1, s + 1);
+        m[2] = lattice_index(L, a, s + 1);
+    }
+}
+
+template <int DEG>
+__global__ void k_tessellate(Consts k, PrimPtrs pr, double *wverts, float *verts_out) {
+    constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)k.VL * k.P) return;
+    const int p = (int)(idx % k.P), m = (int)(idx / k.P);
+    int a, b;
+    lattice_node(k.L, m, a, b);
+    const double u = (double)a / k.L, v = (double)b / k.L, w = (double)(k.L - a - b) / k.L;
+    double B[NCP];
+    bernstein<DEG>(u, v, w, B);
+    double S[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NCP; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) S[d] += B[c] * (double)pr.ctrl[((int64_t)d * NCP + c) * k.P + p];
+    if (wverts)
+        for (int d = 0; d < 3; ++d) wverts[((int64_t)m * k.P + p) * 3 + d] = S[d];
+    if (verts_out)
+        for (int d = 0; d < 3; ++d) verts_out[((int64_t)d * k.VL + m) * k.P + p] = (float)S[d];
+}
+
+hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts, float *verts_out,
+                             hipStream_t s) {
+    int64_t n = (int64_t)k.VL * k.P;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (k.degree) {
+        case 1: hipLaunchKernelGGL(k_tessellate<1>, grid, block, 0, s, k, pr, wverts, verts_out); break;
+        case 2: hipLaunchKernelGGL(k_tessellate<2>, grid, block, 0, s, k, pr, wverts, verts_out); break;
+        case 3: hipLaunchKernelGGL(k_tessellate<3>, grid, block, 0, s, k, pr, wverts, verts_out); break;
+        case 4: hipLaunchKernelGGL(k_tessellate<4>, grid, block, 0, s, k, pr, wverts, verts_out); break;
+        case 5: hipLaunchKernelGGL(k_tessellate<5>, grid, block, 0, s, k, pr, wverts, verts_out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ projection
+
+struct Cam {
+    double R[9], t[3], fx, fy, cx, cy;
+};
+
+__device__ __forceinline__ Cam load_cam(const float *cams, int v) {
+    Cam c;
+    const float *q = cams + 16 * v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c.R[i] = (double)q[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c.t[i] = (double)q[9 + i];
+    c.fx = q[12]; c.fy = q[13]; c.cx = q[14]; c.cy = q[15];
+    return c;
+}
+
+__device__ __forceinline__ void cam_apply(const Cam &c, const double *X, double *t) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) t[r] = c.R[3 * r] * X[0] + c.R[3 * r + 1] * X[1] + c.R[3 * r + 2] * X[2] + c.t[r];
+}
+
+__global__ void k_project(Consts k, ViewTable vt, const float *cams, const double *wverts, VertRec *verts) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per_view = (int64_t)k.VL * k.P;
+    if (idx >= per_view * vt.n) return;
+    const int v = (int)(idx / per_view);
+    const int64_t mp = idx % per_view;
+    const Cam c = load_cam(cams, v);
+    double X[3] = {wverts[mp * 3], wverts[mp * 3 + 1], wverts[mp * 3 + 2]}, t[3];
+    cam_apply(c, X, t);
+    VertRec r;
+    r.x = r.y = r.iz = 0.0;
+    r.X = INT32_MIN;
+    r.Y = 0;
+    if (t[2] > (double)k.z_near) {
+        const double x = c.fx * t[0] / t[2] + c.cx;
+        const double y = c.fy * t[1] / t[2] + c.cy;
+        const double lim = 1048576.0;  // 2^20 px keeps edge functions inside int64
+        if (fabs(x) < lim && fabs(y) < lim) {
+            r.x = x;
+            r.y = y;
+            r.iz = 1.0 / t[2];
+            r.X = (int32_t)rint(x * 256.0);
+            r.Y = (int32_t)rint(y * 256.0);
+        }
+    }
+    verts[idx] = r;
+}
+
+// ------------------------------------------------------------ raster
+
+struct TriSetup {
+    int64_t X[3], Y[3];
+    double iz[3];
+    int64_t A;
+    bool own[3];
+    int i0, i1, j0, j1;
+};
+
+__device__ __forceinline__ int64_t floor_div256(int64_t a) { return a >> 8; }
+__device__ __forceinline__ int64_t ceil_div256(int64_t a) { return -((-a) >> 8); }
+
+// Top-left ownership of a directed edge (exactly one of a->b, b->a owns it).
+__device__ __forceinline__ bool owned(int64_t dx, int64_t dy) { return dy > 0 || (dy == 0 && dx < 0); }
+
+__device__ __forceinline__ int64_t edge_fn(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px, int64_t py) {
+    return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+// Returns false when the triangle is culled or misses the image.
+__device__ __forceinline__ bool tri_setup(const Consts &k, const ViewInfo &vi, const VertRec *vv, int s, int p,
+                                          TriSetup &ts) {
+    int m[3];
+    subtri_corners(k.L, s, m);
+    VertRec r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        r[c] = vv[(int64_t)m[c] * k.P + p];
+        if (r[c].X == INT32_MIN) return false;  // near-plane cull
+    }
+    int64_t A = edge_fn(r[0].X, r[0].Y, r[1].X, r[1].Y, r[2].X, r[2].Y);
+    if (A == 0) return false;
+    int o1 = 1, o2 = 2;
+    if (A < 0) { o1 = 2; o2 = 1; A = -A; }
+    const int ord[3] = {0, o1, o2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ts.X[c] = r[ord[c]].X;
+        ts.Y[c] = r[ord[c]].Y;
+        ts.iz[c] = r[ord[c]].iz;
+    }
+    ts.A = A;
+    ts.own[0] = owned(ts.X[2] - ts.X[1], ts.Y[2] - ts.Y[1]);
+    ts.own[1] = owned(ts.X[0] - ts.X[2], ts.Y[0] - ts.Y[2]);
+    ts.own[2] = owned(ts.X[1] - ts.X[0], ts.Y[1] - ts.Y[0]);
+    int64_t minX = min(ts.X[0], min(ts.X[1], ts.X[2])), maxX = max(ts.X[0], max(ts.X[1], ts.X[2]));
+    int64_t minY = min(ts.Y[0], min(ts.Y[1], ts.Y[2])), maxY = max(ts.Y[0], max(ts.Y[1], ts.Y[2]));
+    int64_t i0 = ceil_div256(minX - 128), i1 = floor_div256(maxX - 128);
+    int64_t j0 = ceil_div256(minY - 128), j1 = floor_div256(maxY - 128);
+    if (i0 < 0) i0 = 0;
+    if (j0 < 0) j0 = 0;
+    if (i1 > vi.W - 1) i1 = vi.W - 1;
+    if (j1 > vi.H - 1) j1 = vi.H - 1;
+    if (i0 > i1 || j0 > j1) return false;
+    ts.i0 = (int)i0; ts.i1 = (int)i1; ts.j0 = (int)j0; ts.j1 = (int)j1;
+    return true;
+}
+
+// Coverage of pixel centre (i, j) and, when covered, the z-buffer candidate:
+// the 1/z plane (affine in screen space) at the centre, high 40 bits of its
+// FP64 pattern, then the inverted triangle id (lower id wins ties).
+__device__ __forceinline__ unsigned long long raster_pixel(const TriSetup &ts, int i, int j, uint32_t tri) {
+    const int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
+    const int64_t E0 = edge_fn(ts.X[1], ts.Y[1], ts.X[2], ts.Y[2], px, py);
+    const int64_t E1 = edge_fn(ts.X[2], ts.Y[2], ts.X[0], ts.Y[0], px, py);
+    const int64_t E2 = edge_fn(ts.X[0], ts.Y[0], ts.X[1], ts.Y[1], px, py);
+    const bool in = (E0 > 0 || (E0 == 0 && ts.own[0])) && (E1 > 0 || (E1 == 0 && ts.own[1])) &&
+                    (E2 > 0 || (E2 == 0 && ts.own[2]));
+    if (!in) return 0ull;
+    const double key = fma((double)E2, ts.iz[2], fma((double)E1, ts.iz[1], (double)E0 * ts.iz[0])) / (double)ts.A;
+    const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
+    return ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - tri);
+}
+
+__global__ void k_raster(Consts k, ViewTable vt, const VertRec *verts, unsigned long long *zbuf, int32_t *big,
+                         int64_t *counters) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per_view = (int64_t)k.L2 * k.P;
+    if (idx >= per_view * vt.n) return;
+    const int v = (int)(idx / per_view);
+    const int64_t sp = idx % per_view;
+    const int s = (int)(sp / k.P), p = (int)(sp % k.P);
+    const ViewInfo vi = vt.v[v];
+    TriSetup ts;
+    if (!tri_setup(k, vi, verts + (int64_t)v * k.VL * k.P, s, p, ts)) return;
+    const int64_t area = (int64_t)(ts.i1 - ts.i0 + 1) * (ts.j1 - ts.j0 + 1);
+    if (area > kBigTriPixels) {
+        const long long slot = atomicAdd((unsigned long long *)&counters[C_BIGTRI], 1ull);
+        if (slot < k.cap_big) big[slot] = (int32_t)idx;
+        else atomicOr((unsigned long long *)&counters[C_OVERFLOW], 4ull);
+        return;
+    }
+    const uint32_t tri = (uint32_t)(p * k.L2 + s);
+    unsigned long long *zb = zbuf + vi.px_off;
+    for (int j = ts.j0; j <= ts.j1; ++j)
+        for (int i = ts.i0; i <= ts.i1; ++i) {
+            const unsigned long long c = raster_pixel(ts, i, j, tri);
+            if (c) atomicMax(&zb[(int64_t)j * vi.W + i], c);
+        }
+}
+
+// Triangles with a large bounding box: one block each, pixels over threads.
+__global__ void k_raster_big(Consts k, ViewTable vt, const VertRec *verts, unsigned long long *zbuf,
+                             const int32_t *big, const int64_t *counters) {
+    int64_t n = counters[C_BIGTRI];
+    if (n > k.cap_big) n = k.cap_big;
+    const int64_t per_view = (int64_t)k.L2 * k.P;
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int64_t idx = big[q];
+        const int v = (int)(idx / per_view);
+        const int64_t sp = idx % per_view;
+        const int s = (int)(sp / k.P), p = (int)(sp % k.P);
+        const ViewInfo vi = vt.v[v];
+        TriSetup ts;
+        if (!tri_setup(k, vi, verts + (int64_t)v * k.VL * k.P, s, p, ts)) continue;
+        const uint32_t tri = (uint32_t)(p * k.L2 + s);
+        const int bw = ts.i1 - ts.i0 + 1;
+        const int64_t area = (int64_t)bw * (ts.j1 - ts.j0 + 1);
+        unsigned long long *zb = zbuf + vi.px_off;
+        for (int64_t e = threadIdx.x; e < area; e += blockDim.x) {
+            const int i = ts.i0 + (int)(e % bw), j = ts.j0 + (int)(e / bw);
+            const unsigned long long c = raster_pixel(ts, i, j, tri);
+            if (c) atomicMax(&zb[(int64_t)j * vi.W + i], c);
+        }
+    }
+}
+
+// ------------------------------------------------------------ resolve + generation
+
+__device__ __forceinline__ int zb_prim(unsigned long long z, int L2) {
+    return z == 0ull ? -1 : (int)((0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull)) / (uint32_t)L2);
+}
+
+// pixel-centre index range [lo, hi] covered by the closed interval [c - r, c + r]
+__device__ __forceinline__ void centre_range(double c, double r, int n, int &lo, int &hi) {
+    double a = ceil(c - r - 0.5), b = floor(c + r - 0.5);
+    if (a < 0.0) a = 0.0;
+    if (b > (double)(n - 1)) b = (double)(n - 1);
+    if (!(a <= b)) { lo = 1; hi = 0; return; }
+    lo = (int)a;
+    hi = (int)b;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st) {
+    constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = pix < vt.total_px;
+    bool fg = false, isb = false;
+    if (act) {
+        const int v = view_of_pixel(vt, pix);
+        const ViewInfo vi = vt.v[v];
+        const int lp = pix - vi.px_off, x = lp % vi.W, y = lp / vi.W;
+        const unsigned long long z = st.zbuf[pix];
+        const int tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
+        st.I_tri[pix] = tri;
+        uint8_t flags = 0;
+        float2 uvo = make_float2(0.f, 0.f);
+        if (tri >= 0) {
+            const int p = tri / k.L2, s = tri % k.L2;
+            const unsigned long long *zr = st.zbuf + vi.px_off;
+            bool bnd = false;
+            if (x > 0 && zb_prim(zr[lp - 1], k.L2) != p) bnd = true;
+            if (x + 1 < vi.W && zb_prim(zr[lp + 1], k.L2) != p) bnd = true;
+            if (y > 0 && zb_prim(zr[lp - vi.W], k.L2) != p) bnd = true;
+            if (y + 1 < vi.H && zb_prim(zr[lp + vi.W], k.L2) != p) bnd = true;
+            // perspective-correct barycentrics in the winning flat triangle
+            int m[3];
+            subtri_corners(k.L, s, m);
+            const VertRec *vv = st.verts + (int64_t)v * k.VL * k.P;
+            double vx[3], vy[3], viz[3], lu[3], lv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const VertRec r = vv[(int64_t)m[c] * k.P + p];
+                vx[c] = r.x; vy[c] = r.y; viz[c] = r.iz;
+                int a, b;
+                lattice_node(k.L, m[c], a, b);
+                lu[c] = (double)a / k.L;
+                lv[c] = (double)b / k.L;
+            }
+            const double qx = x + 0.5, qy = y + 0.5;
+            const double d = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
+            double lam[3];
+            if (d != 0.0) {
+                lam[0] = ((vx[2] - vx[1]) * (qy - vy[1]) - (vy[2] - vy[1]) * (qx - vx[1])) / d;
+                lam[1] = ((vx[0] - vx[2]) * (qy - vy[2]) - (vy[0] - vy[2]) * (qx - vx[2])) / d;
+                lam[2] = ((vx[1] - vx[0]) * (qy - vy[0]) - (vy[1] - vy[0]) * (qx - vx[0])) / d;
+            } else {
+                lam[0] = lam[1] = lam[2] = 1.0 / 3.0;
+            }
+            double ws = 0.0, beta[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { beta[c] = lam[c] * viz[c]; ws += beta[c]; }
+            double u = 0.0, vb = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { u += beta[c] / ws * lu[c]; vb += beta[c] / ws * lv[c]; }
+            uvo = make_float2((float)u, (float)vb);
+            // Eq. 3 (position) and Eq. 4 (diffuse colour)
+            double B[NCP];
+            bernstein<DEG>(u, vb, 1.0 - u - vb, B);
+            double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NCP; ++c)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    S[dd] += B[c] * (double)pr.ctrl[((int64_t)dd * NCP + c) * k.P + p];
+                    col[dd] += B[c] * (double)pr.color[((int64_t)dd * NCP + c) * k.P + p];
+                }
+            const Cam c = load_cam(cams, v);
+            double t[3];
+            cam_apply(c, S, t);
+            if (t[2] > (double)k.z_near) {
+                const double tz = t[2];
+                const double J00 = c.fx / tz, J02 = -c.fx * t[0] / (tz * tz);
+                const double J11 = c.fy / tz, J12 = -c.fy * t[1] / (tz * tz);
+                double Tm[6];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Tm[cc] = J00 * c.R[cc] + J02 * c.R[6 + cc];
+                    Tm[3 + cc] = J11 * c.R[3 + cc] + J12 * c.R[6 + cc];
+                }
+                // Eq. 5 with a resolution-1 attribute map: one rotation and scale per patch
+                double q[4], qn = 0.0;
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) { q[dd] = pr.quat[(int64_t)dd * k.T * k.P + p]; qn += q[dd] * q[dd]; }
+                qn = sqrt(qn);
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) q[dd] /= qn;
+                const double qw = q[0], qx_ = q[1], qy_ = q[2], qz = q[3];
+                const double Rq[9] = {1 - 2 * (qy_ * qy_ + qz * qz), 2 * (qx_ * qy_ - qw * qz), 2 * (qx_ * qz + qw * qy_),
+                                      2 * (qx_ * qy_ + qw * qz), 1 - 2 * (qx_ * qx_ + qz * qz), 2 * (qy_ * qz - qw * qx_),
+                                      2 * (qx_ * qz - qw * qy_), 2 * (qy_ * qz + qw * qx_), 1 - 2 * (qx_ * qx_ + qy_ * qy_)};
+                double sc[3];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) sc[dd] = exp((double)pr.log_scale[(int64_t)dd * k.T * k.P + p]);
+                // V = Tm Rq diag(s): Sigma2D = V V^T + low-pass
+                double V0[3], V1[3];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    V0[cc] = (Tm[0] * Rq[cc] + Tm[1] * Rq[3 + cc] + Tm[2] * Rq[6 + cc]) * sc[cc];
+                    V1[cc] = (Tm[3] * Rq[cc] + Tm[4] * Rq[3 + cc] + Tm[5] * Rq[6 + cc]) * sc[cc];
+                }
+                const double SA = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + k.dilation;
+                const double SB = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
+                const double SC = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + k.dilation;
+                const double det = SA * SC - SB * SB;
+                const double mux = c.fx * t[0] / tz + c.cx, muy = c.fy * t[1] / tz + c.cy;
+                int gi0, gi1, gj0, gj1;
+                centre_range(mux, k.kappa * sqrt(SA), vi.W, gi0, gi1);
+                centre_range(muy, k.kappa * sqrt(SC), vi.H, gj0, gj1);
+                float sigma = 0.f;
+                int bi0 = 1, bi1 = 0, bj0 = 1, bj1 = 0;
+                if (bnd) {
+                    // isotropic boundary Gaussian of scale r_b: r_b^2 J J^T + low-pass
+                    const double rb = (double)k.r_ref / (double)pr.sharp[p], r2 = rb * rb;
+                    const double ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
+                    const double mb = r2 * (J02 * J12);
+                    const double mc = r2 * (J11 * J11 + J12 * J12) + k.dilation;
+                    const double lam_max = 0.5 * (ma + mc) + sqrt(0.25 * (ma - mc) * (ma - mc) + mb * mb);
+                    const double sg = 3.0 * sqrt(lam_max);
+                    sigma = (float)sg;
+                    centre_range(mux, sg, vi.W, bi0, bi1);
+                    centre_range(muy, sg, vi.H, bj0, bj1);
+                    flags |= PF_BOUNDARY;
+                }
+                flags |= PF_VALID;
+                float4 *rec = st.rec + (int64_t)pix * 4;
+                rec[0] = make_float4((float)(mux - (x + 0.5)), (float)(muy - (y + 0.5)), (float)(SC / det),
+                                     (float)(-SB / det));
+                rec[1] = make_float4((float)(SA / det), (float)col[0], (float)col[1], (float)col[2]);
+                rec[2] = make_float4(pr.opacity[p], __int_as_float(p), sigma, (float)tz);
+                rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
+                                     __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
+                st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;
+                // pair counts per tile
+                const int TS = k.tile;
+                if (gi0 <= gi1 && gj0 <= gj1)
+                    for (int ty = gj0 / TS; ty <= gj1 / TS; ++ty)
+                        for (int tx = gi0 / TS; tx <= gi1 / TS; ++tx)
+                            atomicAdd(&st.g_count[vi.tile_off + ty * vi.tiles_x + tx], 1);
+                if (bi0 <= bi1 && bj0 <= bj1)
+                    for (int ty = bj0 / TS; ty <= bj1 / TS; ++ty)
+                        for (int tx = bi0 / TS; tx <= bi1 / TS; ++tx)
+                            atomicAdd(&st.b_count[vi.tile_off + ty * vi.tiles_x + tx], 1);
+            }
+            fg = true;
+            isb = (flags & PF_BOUNDARY) != 0;
+        }
+        st.I_uv[pix] = uvo;
+        st.pflags[pix] = flags;
+    }
+    const unsigned long long mf = __ballot(fg), mb = __ballot(isb);
+    if (__lane_id() == 0) {
+        if (mf) atomicAdd((unsigned long long *)&st.counters[C_FG], (unsigned long long)__popcll(mf));
+        if (mb) atomicAdd((unsigned long long *)&st.counters[C_BOUNDARY], (unsigned long long)__popcll(mb));
+    }
+}
+
+hipError_t launch_geometry(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                           const StatePtrs &st, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_tessellate(k, pr, st.wverts, nullptr, s)) != hipSuccess) return e;
+    {
+        const int64_t n = (int64_t)vt.n * k.VL * k.P;
+        hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, vt, cams,
+                           (const double *)st.wverts, st.verts);
+    }
+    {
+        const int64_t n = (int64_t)vt.n * k.L2 * k.P;
+        hipLaunchKernelGGL(k_raster, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k, vt,
+                           (const VertRec *)st.verts, st.zbuf, st.big_tris, st.counters);
+        hipLaunchKernelGGL(k_raster_big, dim3(1024), dim3(256), 0, s, k, vt, (const VertRec *)st.verts, st.zbuf,
+                           (const int32_t *)st.big_tris, (const int64_t *)st.counters);
+    }
+    {
+        dim3 grid((unsigned)((vt.total_px + 255) / 256)), block(256);
+        switch (k.degree) {
+            case 1: hipLaunchKernelGGL(k_gen<1>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            case 2: hipLaunchKernelGGL(k_gen<2>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            case 3: hipLaunchKernelGGL(k_gen<3>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            case 4: hipLaunchKernelGGL(k_gen<4>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            case 5: hipLaunchKernelGGL(k_gen<5>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bgt

@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP translation units of libbgt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bgt.h"
+
+namespace bgt {
+
+// ---------------------------------------------------------------- sizes
+
+constexpr int kMaxL = 8;
+constexpr int kMaxNcp = (BGT_MAX_DEGREE + 1) * (BGT_MAX_DEGREE + 2) / 2;  // 21
+constexpr int kSortLds = 2048;        // per-tile list length sorted in LDS
+constexpr int kBigTriPixels = 256;    // bbox size above which a triangle is rasterized by a block
+
+// state counter slots (int64)
+enum Counter {
+    C_OVERFLOW = 0,   // bit0 gauss pairs, bit1 boundary pairs, bit2 big-triangle queue
+    C_GPAIRS = 1,
+    C_BPAIRS = 2,
+    C_FG = 3,
+    C_BOUNDARY = 4,
+    C_BIGTRI = 5,
+    C_BIGSORT = 6,
+    C_BIGBLIST = 7,
+    C_BIGSORT_Q = 8,  // queue length for the global-memory sort (g in low, b via C_BIGSORT_QB)
+    C_BIGSORT_QB = 9,
+    C_NUM = 16
+};
+
+// per-pixel flags
+constexpr uint8_t PF_VALID = 1;     // the pixel has a Gaussian
+constexpr uint8_t PF_BOUNDARY = 2;  // the pixel is a boundary point
+
+// ---------------------------------------------------------------- views
+
+struct ViewInfo {
+    int32_t W, H, tiles_x, tiles_y, px_off, tile_off;
+};
+
+struct ViewTable {
+    int32_t n, total_px, total_tiles, total_b8;  // total_b8: 8x8 pixel blocks over all views
+    ViewInfo v[BGT_MAX_VIEWS];
+};
+
+__device__ __forceinline__ int view_of_pixel(const ViewTable &vt, int pix) {
+    int lo = 0, hi = vt.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].px_off <= pix) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewTable &vt, int tile) {
+    int lo = 0, hi = vt.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- constants
+
+struct Consts {
+    int32_t L, L2, VL, tile;
+    int32_t degree, ncp, P, T;
+    int32_t batch, pad0;
+    float z_near, g_min, t_min, alpha_max, dilation, r_ref;
+    float bg[3];
+    float kappa2;          // 2 ln(1/g_min), float
+    double kappa;          // sqrt(2 ln(1/g_min)), double
+    int64_t cap_g, cap_b, cap_big;
+};
+
+struct PrimPtrs {
+    const float *ctrl, *color, *log_scale, *quat, *opacity, *sharp;
+};
+
+struct GradPtrs {
+    float *ctrl, *color, *log_scale, *quat, *opacity, *sharp;
+};
+
+// per-view projected lattice vertex
+struct VertRec {
+    double x, y, iz;       // unsnapped projection and 1/z
+    int32_t X, Y;          // 1/256-px fixed point; X == INT32_MIN marks a culled vertex
+};
+
+// Gaussian record, 4 x float4 per pixel:
+//  r0 = (mu_x - x - 1/2, mu_y - y - 1/2, Q_a, Q_b): the mean relative to the
+//       centre of the Gaussian's own pixel (x, y) keeps FP32 offsets small;
+//       conic Q = [[a, b], [b, c]]
+//  r1 = (Q_c, c_r, c_g, c_b)
+//  r2 = (opacity, prim (int bits), sigma_b, depth)
+//  r3 = (g x-range, g y-range, b x-range, b y-range) as int16 pairs (lo | hi << 16)
+struct StatePtrs {
+    int64_t *counters;
+    unsigned long long *zbuf;
+    int32_t *I_tri;
+    float2 *I_uv;
+    uint8_t *pflags;
+    float4 *rec;
+    unsigned long long *gkey;
+    float *T_final;
+    int32_t *last;
+    VertRec *verts;        // [V][VL][P]
+    double *wverts;        // [VL][P][3] world lattice
+    int32_t *g_count, *g_start, *g_cursor;
+    int32_t *b_count, *b_start, *b_cursor;
+    unsigned long long *g_keys, *b_keys;
+    uint32_t *g_list, *b_list;
+    float *dgauss;         // [N_px][12]
+    int32_t *big_tris;     // [cap_big] queue of raster items
+    int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
+    int32_t *scan_tmp;     // block sums
+};
+
+__device__ __forceinline__ int pack16(int lo, int hi) { return (lo & 0xFFFF) | (hi << 16); }
+__device__ __forceinline__ int lo16(int v) { return (int)(int16_t)(v & 0xFFFF); }
+__device__ __forceinline__ int hi16(int v) { return v >> 16; }
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts, float *verts_out,
+                             hipStream_t s);
+hipError_t launch_geometry(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                           const StatePtrs &st, hipStream_t s);
+hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s);
+hipError_t launch_blend_fwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, float *image,
+                            hipStream_t s);
+hipError_t launch_blend_bwd(const Consts &k, const ViewTable &vt, const StatePtrs &st,
+                            const float *image, const float *grad_image, hipStream_t s);
+hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                            const StatePtrs &st, const GradPtrs &gr, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+
+}  // namespace bgt

@@ -1,0 +1,249 @@
+// Parameter backward pass: per-Gaussian gradients (mean, conic, colour,
+// opacity) and per-boundary-point gradients (position, radius) flow through
+// the EWA projection and the boundary radius to the BG-Triangle parameters:
+//   dl/dp_ijk   = sum_q B^n_ijk(I_uv(q)) dl/dS_q     (Supplementary Sec. C)
+//   dl/dp^c_ijk = sum_q B^n_ijk(I_uv(q)) dl/dc_q     (Eq. 4)
+// plus log-scale, rotation, opacity and sharpness.  One wave covers an 8x8
+// pixel block; pixels of the same primitive are summed across the wave
+// (segmented by primitive id) before one atomic per parameter.
+#include "bgt_internal.h"
+
+namespace bgt {
+
+__device__ __forceinline__ float wsum(float x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <int DEG>
+__device__ __forceinline__ void bern_f(float u, float v, float w, float *B) {
+    constexpr float fact[6] = {1.f, 1.f, 2.f, 6.f, 24.f, 120.f};
+    float pu[DEG + 1], pv[DEG + 1], pw[DEG + 1];
+    pu[0] = pv[0] = pw[0] = 1.f;
+#pragma unroll
+    for (int e = 1; e <= DEG; ++e) { pu[e] = pu[e - 1] * u; pv[e] = pv[e - 1] * v; pw[e] = pw[e - 1] * w; }
+    int idx = 0;
+#pragma unroll
+    for (int i = 0; i <= DEG; ++i)
+#pragma unroll
+        for (int j = 0; j <= DEG - i; ++j) {
+            const int kk = DEG - i - j;
+            B[idx++] = fact[DEG] / (fact[i] * fact[j] * fact[kk]) * pu[i] * pv[j] * pw[kk];
+        }
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimPtrs pr, const float *cams,
+                                                  StatePtrs st, GradPtrs gr) {
+    constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    const int lane = threadIdx.x & 63;
+    const int wblock = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // global 8x8 block
+    // locate the view and pixel of this lane
+    int pix = -1, prim = -1;
+    float dS[3] = {0.f, 0.f, 0.f}, dcol[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
+    float dop = 0.f, dsh = 0.f;
+    float B[NCP];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) B[c] = 0.f;
+    bool act = false;
+    if (wblock < vt.total_b8) {
+        int v = 0;
+        {   // views are few; linear search over the 8x8-block prefix
+            int acc = 0;
+            for (v = 0; v < vt.n; ++v) {
+                const int nb = ((vt.v[v].W + 7) >> 3) * ((vt.v[v].H + 7) >> 3);
+                if (wblock < acc + nb) break;
+                acc += nb;
+            }
+            const ViewInfo vi = vt.v[v];
+            const int lb = wblock - acc, bxn = (vi.W + 7) >> 3;
+            const int x = (lb % bxn) * 8 + (lane & 7), y = (lb / bxn) * 8 + (lane >> 3);
+            if (x < vi.W && y < vi.H) pix = vi.px_off + y * vi.W + x;
+        }
+        if (pix >= 0 && (st.pflags[pix] & PF_VALID)) {
+            const float *g = st.dgauss + (int64_t)pix * 12;
+            const float dmux = g[0], dmuy = g[1], dqa = g[2], dqb = g[3], dqc = g[4];
+            dcol[0] = g[5]; dcol[1] = g[6]; dcol[2] = g[7];
+            dop = g[8];
+            const float dsig = g[9];
+            if (dmux != 0.f || dmuy != 0.f || dqa != 0.f || dqb != 0.f || dqc != 0.f || dcol[0] != 0.f ||
+                dcol[1] != 0.f || dcol[2] != 0.f || dop != 0.f || dsig != 0.f) {
+                act = true;
+                prim = st.I_tri[pix] / k.L2;
+                const int p = prim;
+                const float2 uv = st.I_uv[pix];
+                bern_f<DEG>(uv.x, uv.y, 1.f - uv.x - uv.y, B);
+                float S[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < NCP; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) S[d] += B[c] * pr.ctrl[((int64_t)d * NCP + c) * k.P + p];
+                const int v = view_of_pixel(vt, pix);
+                const float *cm = cams + 16 * v;
+                float W[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) W[i] = cm[i];
+                const float fx = cm[12], fy = cm[13];
+                float t[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) t[r] = W[3 * r] * S[0] + W[3 * r + 1] * S[1] + W[3 * r + 2] * S[2] + cm[9 + r];
+                const float iz = 1.f / t[2];
+                const float J00 = fx * iz, J02 = -fx * t[0] * iz * iz, J11 = fy * iz, J12 = -fy * t[1] * iz * iz;
+                float Tm[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { Tm[c] = J00 * W[c] + J02 * W[6 + c]; Tm[3 + c] = J11 * W[3 + c] + J12 * W[6 + c]; }
+                // rotation and scale of the patch (resolution-1 attribute map)
+                float q[4], qn = 0.f;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
+                qn = sqrtf(qn);
+                const float qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
+                const float R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                                    2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                                    2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+                float s[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s[d] = __expf(pr.log_scale[(int64_t)d * k.T * k.P + p]);
+                float M[9];  // R diag(s)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) M[3 * r + c] = R[3 * r + c] * s[c];
+                float V[6];  // Tm M, Sigma2D = V V^T + low-pass
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) V[3 * a + c] = Tm[3 * a] * M[c] + Tm[3 * a + 1] * M[3 + c] + Tm[3 * a + 2] * M[6 + c];
+                const float SA = V[0] * V[0] + V[1] * V[1] + V[2] * V[2] + k.dilation;
+                const float SB = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
+                const float SC = V[3] * V[3] + V[4] * V[4] + V[5] * V[5] + k.dilation;
+                // conic = inverse: a = C/det, b = -B/det, c = A/det
+                const float det = SA * SC - SB * SB, id2 = 1.f / (det * det);
+                const float dA = (-SC * SC * dqa + SB * SC * dqb - SB * SB * dqc) * id2;
+                const float dB = (2.f * SB * SC * dqa - (SA * SC + SB * SB) * dqb + 2.f * SA * SB * dqc) * id2;
+                const float dC = (-SB * SB * dqa + SA * SB * dqb - SA * SA * dqc) * id2;
+                // d/dV = 2 Gs V with Gs = [[dA, dB/2], [dB/2, dC]]
+                float dV[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dV[c] = 2.f * dA * V[c] + dB * V[3 + c];
+                    dV[3 + c] = dB * V[c] + 2.f * dC * V[3 + c];
+                }
+                float dTm[6], dM[9];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+                        dTm[3 * a + r] = dV[3 * a] * M[3 * r] + dV[3 * a + 1] * M[3 * r + 1] + dV[3 * a + 2] * M[3 * r + 2];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) dM[3 * r + c] = Tm[r] * dV[c] + Tm[3 + r] * dV[3 + c];
+                float dR[9];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float ds = 0.f;
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) { ds += dM[3 * r + c] * R[3 * r + c]; dR[3 * r + c] = dM[3 * r + c] * s[c]; }
+                    dls[c] = ds * s[c];
+                }
+                {   // rotation matrix -> unit quaternion -> raw quaternion
+                    float gw = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+                    float gx = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] - 2.f * qx * dR[8]);
+                    float gy = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.f * qy * dR[8]);
+                    float gz = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
+                    const float dot = qw * gw + qx * gx + qy * gy + qz * gz;
+                    dq[0] = (gw - qw * dot) / qn; dq[1] = (gx - qx * dot) / qn;
+                    dq[2] = (gy - qy * dot) / qn; dq[3] = (gz - qz * dot) / qn;
+                }
+                // dJ = dTm W^T (J has four non-zero entries)
+                float dJ00 = dTm[0] * W[0] + dTm[1] * W[1] + dTm[2] * W[2];
+                float dJ02 = dTm[0] * W[6] + dTm[1] * W[7] + dTm[2] * W[8];
+                float dJ11 = dTm[3] * W[3] + dTm[4] * W[4] + dTm[5] * W[5];
+                float dJ12 = dTm[3] * W[6] + dTm[4] * W[7] + dTm[5] * W[8];
+                if (dsig != 0.f) {
+                    // sigma = 3 sqrt(lambda_max(r_b^2 J J^T + low-pass)), r_b = r_ref / sharpness
+                    const float sh = pr.sharp[p];
+                    const float rb = k.r_ref / sh, r2 = rb * rb;
+                    const float ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
+                    const float mb = r2 * J02 * J12;
+                    const float mc = r2 * (J11 * J11 + J12 * J12) + k.dilation;
+                    const float hd = 0.5f * (ma - mc);
+                    const float sq = sqrtf(hd * hd + mb * mb);
+                    const float lam = 0.5f * (ma + mc) + sq;
+                    const float dlam = dsig * 1.5f / sqrtf(lam);
+                    float dma, dmb, dmc;
+                    if (sq > 0.f) {
+                        dma = dlam * (0.5f + 0.5f * hd / sq);
+                        dmc = dlam * (0.5f - 0.5f * hd / sq);
+                        dmb = dlam * mb / sq;
+                    } else {
+                        dma = dmc = 0.5f * dlam;
+                        dmb = 0.f;
+                    }
+                    dJ00 += 2.f * r2 * J00 * dma;
+                    dJ02 += 2.f * r2 * J02 * dma + r2 * J12 * dmb;
+                    dJ12 += r2 * J02 * dmb + 2.f * r2 * J12 * dmc;
+                    dJ11 += 2.f * r2 * J11 * dmc;
+                    const float dr2 = dma * (J00 * J00 + J02 * J02) + dmb * J02 * J12 + dmc * (J11 * J11 + J12 * J12);
+                    dsh = dr2 * 2.f * rb * (-k.r_ref / (sh * sh));
+                }
+                // mu = (fx t_x/t_z + cx, fy t_y/t_z + cy) and J(t)
+                const float iz2 = iz * iz, iz3 = iz2 * iz;
+                float dt[3];
+                dt[0] = dmux * fx * iz - dJ02 * fx * iz2;
+                dt[1] = dmuy * fy * iz - dJ12 * fy * iz2;
+                dt[2] = -dmux * fx * t[0] * iz2 - dmuy * fy * t[1] * iz2 - dJ00 * fx * iz2 + dJ02 * 2.f * fx * t[0] * iz3 -
+                        dJ11 * fy * iz2 + dJ12 * 2.f * fy * t[1] * iz3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dS[c] = W[c] * dt[0] + W[3 + c] * dt[1] + W[6 + c] * dt[2];
+            }
+        }
+    }
+    // segmented reduction over the wave by primitive id, one atomic per value
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int gl = __shfl(prim, leader, 64);
+        const bool mine = act && prim == gl;
+        const unsigned long long mm = __ballot(mine);
+        const bool one = __popcll(mm) == 1;
+        auto red = [&](float x, float *dst) {
+            const float vsum = one ? __shfl(x, leader, 64) : wsum(mine ? x : 0.f);
+            if (lane == leader && vsum != 0.f) unsafeAtomicAdd(dst, vsum);
+        };
+#pragma unroll
+        for (int c = 0; c < NCP; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                red(B[c] * dS[d], &gr.ctrl[((int64_t)d * NCP + c) * k.P + gl]);
+                red(B[c] * dcol[d], &gr.color[((int64_t)d * NCP + c) * k.P + gl]);
+            }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) red(dls[d], &gr.log_scale[(int64_t)d * k.T * k.P + gl]);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) red(dq[d], &gr.quat[(int64_t)d * k.T * k.P + gl]);
+        red(dop, &gr.opacity[gl]);
+        red(dsh, &gr.sharp[gl]);
+        pending &= ~mm;
+        if (mine) act = false;
+    }
+}
+
+hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                            const StatePtrs &st, const GradPtrs &gr, hipStream_t s) {
+    const int nblk = vt.total_b8;
+    dim3 grid((unsigned)((nblk + 3) / 4)), block(256);
+    switch (k.degree) {
+        case 1: hipLaunchKernelGGL(k_param_bwd<1>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        case 2: hipLaunchKernelGGL(k_param_bwd<2>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        case 3: hipLaunchKernelGGL(k_param_bwd<3>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        case 4: hipLaunchKernelGGL(k_param_bwd<4>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        case 5: hipLaunchKernelGGL(k_param_bwd<5>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bgt

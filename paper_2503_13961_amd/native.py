@@ -1,0 +1,192 @@
+"""ctypes binding of libbgt.so: the C ABI declared in include/bgt.h.
+
+Argument marshalling only; every step of the rendering runs in the HIP
+kernels of the library.  Importing this module fails loudly when the
+library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbgt.so")
+
+BGT_OK, BGT_E_INVALID, BGT_E_NOMEM, BGT_E_OVERFLOW, BGT_E_HIP, BGT_E_UNSUPPORTED = range(6)
+BGT_MAX_VIEWS = 64
+BGT_STATE_FIELDS = 24
+STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey", "T_final", "last",
+                     "verts", "g_count", "g_start", "g_cursor", "b_count", "b_start", "b_cursor",
+                     "g_keys", "g_list", "b_keys", "b_list", "dgauss", "big_tris", "scan", "end"]
+EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
+           "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
+           "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query"]
+
+
+class BgtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"bgt status {status}: {msg}")
+        self.status = status
+
+
+class bgt_prims(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("num_prims", C.c_int32), ("attr_res", C.c_int32),
+                ("reserved", C.c_int32), ("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p),
+                ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
+                ("sharpness", C.c_void_p)]
+
+
+class bgt_grads(C.Structure):
+    _fields_ = [("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p), ("log_scale", C.c_void_p),
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sharpness", C.c_void_p)]
+
+
+class bgt_views(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("reserved", C.c_int32), ("wh", C.POINTER(C.c_int32)),
+                ("cams", C.c_void_p)]
+
+
+class bgt_config(C.Structure):
+    _fields_ = [("tess_level", C.c_int32), ("tile", C.c_int32), ("batch", C.c_int32),
+                ("flags", C.c_int32), ("z_near", C.c_float), ("g_min", C.c_float),
+                ("t_min", C.c_float), ("alpha_max", C.c_float), ("dilation", C.c_float),
+                ("r_ref", C.c_float), ("bg", C.c_float * 3), ("pair_factor", C.c_float),
+                ("bpair_factor", C.c_float)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["bg"] = tuple(self.bg)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libbgt.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+        L.bgt_default_config.argtypes = [C.POINTER(bgt_config)]
+        L.bgt_default_config.restype = None
+        L.bgt_validate_config.argtypes = [C.POINTER(bgt_config)]
+        L.bgt_validate_prims.argtypes = [C.POINTER(bgt_prims), C.POINTER(bgt_config)]
+        L.bgt_validate_views.argtypes = [C.POINTER(bgt_views)]
+        L.bgt_create.argtypes = [C.POINTER(bgt_config), C.c_int, C.POINTER(vp)]
+        L.bgt_destroy.argtypes = [vp]
+        L.bgt_destroy.restype = None
+        L.bgt_last_error.argtypes = [vp]
+        L.bgt_last_error.restype = C.c_char_p
+        L.bgt_tessellate.argtypes = [vp, C.POINTER(bgt_prims), vp, vp]
+        L.bgt_state_size.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), C.POINTER(C.c_size_t)]
+        L.bgt_state_layout.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), i64p]
+        L.bgt_render_fwd.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), vp, vp, C.c_size_t, vp]
+        L.bgt_render_bwd.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), vp, vp, vp, C.c_size_t,
+                                     C.POINTER(bgt_grads), vp]
+        L.bgt_query.argtypes = [vp, vp, C.c_size_t, i64p, vp]
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ thin wrappers (same names)
+
+def bgt_default_config(**overrides) -> bgt_config:
+    c = bgt_config()
+    lib().bgt_default_config(C.byref(c))
+    for k, v in overrides.items():
+        if k == "bg":
+            c.bg = (C.c_float * 3)(*v)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def bgt_validate_config(cfg: bgt_config) -> int:
+    return lib().bgt_validate_config(C.byref(cfg))
+
+
+def bgt_validate_prims(prims: bgt_prims, cfg: bgt_config) -> int:
+    return lib().bgt_validate_prims(C.byref(prims), C.byref(cfg))
+
+
+def bgt_validate_views(views: bgt_views) -> int:
+    return lib().bgt_validate_views(C.byref(views))
+
+
+def bgt_create(cfg: bgt_config | None, device: int) -> C.c_void_p:
+    h = C.c_void_p()
+    st = lib().bgt_create(C.byref(cfg) if cfg is not None else None, device, C.byref(h))
+    if st != BGT_OK:
+        raise BgtError(st, "bgt_create failed")
+    return h
+
+
+def bgt_destroy(ctx) -> None:
+    lib().bgt_destroy(ctx)
+
+
+def bgt_last_error(ctx) -> str:
+    return lib().bgt_last_error(ctx).decode()
+
+
+def _check(ctx, st):
+    if st != BGT_OK:
+        raise BgtError(st, bgt_last_error(ctx))
+    return st
+
+
+def bgt_tessellate(ctx, prims: bgt_prims, verts_ptr: int, stream: int = 0) -> int:
+    return _check(ctx, lib().bgt_tessellate(ctx, C.byref(prims), verts_ptr, stream))
+
+
+def bgt_state_size(ctx, prims: bgt_prims, views: bgt_views) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().bgt_state_size(ctx, C.byref(prims), C.byref(views), C.byref(n)))
+    return int(n.value)
+
+
+def bgt_state_layout(ctx, prims: bgt_prims, views: bgt_views) -> dict:
+    off = (C.c_int64 * BGT_STATE_FIELDS)()
+    _check(ctx, lib().bgt_state_layout(ctx, C.byref(prims), C.byref(views), off))
+    return dict(zip(STATE_FIELD_NAMES, [int(x) for x in off]))
+
+
+def bgt_render_fwd(ctx, prims, views, images_ptr, state_ptr, state_bytes, stream=0) -> int:
+    return _check(ctx, lib().bgt_render_fwd(ctx, C.byref(prims), C.byref(views), images_ptr, state_ptr,
+                                            state_bytes, stream))
+
+
+def bgt_render_bwd(ctx, prims, views, images_ptr, grad_images_ptr, state_ptr, state_bytes, grads: bgt_grads,
+                   stream=0) -> int:
+    return _check(ctx, lib().bgt_render_bwd(ctx, C.byref(prims), C.byref(views), images_ptr, grad_images_ptr,
+                                            state_ptr, state_bytes, C.byref(grads), stream))
+
+
+def bgt_query(ctx, state_ptr, state_bytes, stream=0):
+    """Returns (status, counters[8]); status may be BGT_E_OVERFLOW."""
+    out = (C.c_int64 * 8)()
+    st = lib().bgt_query(ctx, state_ptr, state_bytes, out, stream)
+    if st not in (BGT_OK, BGT_E_OVERFLOW):
+        raise BgtError(st, bgt_last_error(ctx))
+    return st, [int(x) for x in out]
+
+
+# ------------------------------------------------------------ struct builders
+
+def make_prims(degree, num_prims, ctrl, color_ctrl, log_scale, quat, opacity, sharpness, attr_res=1):
+    """Pointers are integers (device addresses)."""
+    return bgt_prims(degree, num_prims, attr_res, 0, ctrl, color_ctrl, log_scale, quat, opacity, sharpness)
+
+
+def make_views(wh_int32_array, cams_ptr):
+    """wh: host numpy int32 [V][2] (kept alive by the caller); cams: device pointer."""
+    n = int(wh_int32_array.shape[0])
+    p = wh_int32_array.ctypes.data_as(C.POINTER(C.c_int32))
+    return bgt_views(n, 0, p, cams_ptr)
+
+
+def make_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness):
+    return bgt_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness)

@@ -1,0 +1,89 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and read its state back; build the matching oracle configuration."""
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2503_13961_amd import scenes as S
+
+F32 = lambda x: float(np.float32(x))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_config(tile=16, L=4, bg=(0.0, 0.0, 0.0), **kw):
+    """The oracle's constants set to the float32 values the library uses."""
+    d = dict(L=L, tile=tile, z_near=F32(0.2), g_min=2.0 ** -15, t_min=2.0 ** -15, alpha_max=F32(0.99),
+             dilation=F32(0.3), r_ref=F32(1e-2), bg=tuple(F32(b) for b in bg))
+    d.update(kw)
+    return oracle.Config(**d)
+
+
+def run_gpu(scene, cams, tile=16, L=4, bg=(0.0, 0.0, 0.0), grad_images=None, renderer=None, **cfg):
+    """Forward (and optionally backward) through the C ABI; returns host arrays."""
+    import torch
+    from paper_2503_13961_amd.render import Renderer, scene_tensors
+    dev = torch.device("cuda", 0)
+    r = renderer or Renderer(0, tile=tile, tess_level=L, bg=bg, **cfg)
+    params = scene_tensors(scene, dev)
+    camt = torch.from_numpy(cams.cams).to(dev)
+    wh = np.ascontiguousarray(cams.wh, dtype=np.int32)
+    images, state = r.forward(scene.degree, params, camt, wh)
+    torch.cuda.synchronize()
+    lay = r.layout(scene.degree, params, camt, wh)
+    st = state.cpu().numpy()
+    N = cams.num_pixels
+
+    def sec(name, dtype, count):
+        o = lay[name]
+        return st[o:o + np.dtype(dtype).itemsize * count].view(dtype)
+
+    ntiles = sum(((int(w) + tile - 1) // tile) * ((int(h) + tile - 1) // tile) for w, h in cams.wh)
+    out = dict(images=images.cpu().numpy().astype(np.float64), I_tri=sec("I_tri", np.int32, N).copy(),
+               I_uv=sec("I_uv", np.float32, 2 * N).reshape(N, 2).copy(),
+               pflags=sec("pflags", np.uint8, N).copy(), rec=sec("rec", np.float32, 16 * N).reshape(N, 16).copy(),
+               T_final=sec("T_final", np.float32, N).copy(), last=sec("last", np.int32, N).copy(),
+               g_count=sec("g_count", np.int32, ntiles).copy(), g_start=sec("g_start", np.int32, ntiles).copy(),
+               b_count=sec("b_count", np.int32, ntiles).copy(), b_start=sec("b_start", np.int32, ntiles).copy())
+    gtot = int(out["g_start"][-1] + out["g_count"][-1]) if ntiles else 0
+    btot = int(out["b_start"][-1] + out["b_count"][-1]) if ntiles else 0
+    out["g_list"] = sec("g_list", np.uint32, gtot).astype(np.int64)
+    out["b_list"] = sec("b_list", np.uint32, btot).astype(np.int64)
+    status, counters = r.query(state)
+    out["counters"] = counters
+    out["status"] = status
+    if grad_images is not None:
+        gi = torch.from_numpy(np.ascontiguousarray(grad_images, dtype=np.float32)).to(dev)
+        grads = r.backward(scene.degree, params, camt, wh, images, gi, state)
+        torch.cuda.synchronize()
+        out["grads"] = {k: v.cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    return out
+
+
+def oracle_frames(scene, cams, cfg):
+    return [oracle.Frame(scene, cams.cams[v], int(cams.wh[v, 0]), int(cams.wh[v, 1]), cfg)
+            for v in range(cams.n_views)]
+
+
+def view_offsets(cams):
+    n = cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1]
+    return np.concatenate([[0], np.cumsum(n)])
+
+
+def tile_offsets(cams, tile):
+    n = [((int(w) + tile - 1) // tile) * ((int(h) + tile - 1) // tile) for w, h in cams.wh]
+    return np.concatenate([[0], np.cumsum(n)])
+
+
+def l1_cotangent(image, target):
+    return np.sign(image - target) / image.size
+
+
+def grad_error(g, ref):
+    """Worst absolute error relative to the tensor's largest reference entry."""
+    scale = np.abs(ref).max()
+    return float(np.abs(g - ref).max() / scale) if scale > 0 else float(np.abs(g).max())

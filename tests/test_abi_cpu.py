@@ -1,0 +1,86 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and its host-only validation and sizing behave as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_13961_amd import native as N
+from paper_2503_13961_amd import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "bgt.h")).read()
+    return sorted(set(re.findall(r"\b(bgt_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(N.EXPORTS) == names
+
+
+def test_default_config_is_valid_and_checks_reject_bad_values():
+    c = N.bgt_default_config()
+    assert N.bgt_validate_config(c) == N.BGT_OK
+    assert (c.tess_level, c.tile, c.z_near) == (4, 16, np.float32(0.2))
+    for field, bad in (("tile", 12), ("tess_level", 0), ("tess_level", 9), ("batch", 48),
+                       ("alpha_max", 1.0), ("g_min", 0.0), ("z_near", 0.0), ("pair_factor", 0.0)):
+        assert N.bgt_validate_config(N.bgt_default_config(**{field: bad})) == N.BGT_E_INVALID, field
+    assert N.bgt_validate_config(N.bgt_default_config(bg=(0, float("nan"), 0))) == N.BGT_E_INVALID
+
+
+def test_prims_and_views_validation():
+    c = N.bgt_default_config()
+    good = N.make_prims(2, 10, 1, 1, 1, 1, 1, 1)
+    assert N.bgt_validate_prims(good, c) == N.BGT_OK
+    assert N.bgt_validate_prims(N.make_prims(0, 10, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
+    assert N.bgt_validate_prims(N.make_prims(6, 10, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
+    assert N.bgt_validate_prims(N.make_prims(2, 0, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 0, 1, 1), c) == N.BGT_E_INVALID
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, attr_res=3), c) == N.BGT_E_UNSUPPORTED
+    # sub-triangle ids must fit 24 bits
+    assert N.bgt_validate_prims(N.make_prims(2, 1 << 20, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
+    wh = np.array([[800, 800], [37, 1]], np.int32)
+    assert N.bgt_validate_views(N.make_views(wh, 1)) == N.BGT_OK
+    assert N.bgt_validate_views(N.make_views(wh, 0)) == N.BGT_E_INVALID
+    for bad in ([[0, 5]], [[20000, 2]], [[4096, 4096]]):
+        assert N.bgt_validate_views(N.make_views(np.array(bad, np.int32), 1)) == N.BGT_E_INVALID
+    many = np.ones((N.BGT_MAX_VIEWS + 1, 2), np.int32)
+    assert N.bgt_validate_views(N.make_views(many, 1)) == N.BGT_E_INVALID
+
+
+def test_host_only_context_sizes_state_and_refuses_work():
+    ctx = N.bgt_create(N.bgt_default_config(), -1)
+    try:
+        sc, cams, _ = S.workload("sphere2k_16v_800")
+        pr = N.make_prims(2, sc.num_prims, 1, 1, 1, 1, 1, 1)
+        vw = N.make_views(cams.wh, 1)
+        n = N.bgt_state_size(ctx, pr, vw)
+        lay = N.bgt_state_layout(ctx, pr, vw)
+        assert lay["end"] == n
+        offs = [lay[k] for k in N.STATE_FIELD_NAMES]
+        assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+        npx = cams.num_pixels
+        assert lay["I_tri"] - lay["zbuf"] >= 8 * npx and lay["rec"] + 64 * npx <= lay["gkey"]
+        with pytest.raises(N.BgtError) as e:
+            N.bgt_render_fwd(ctx, pr, vw, 1, 1, n, 0)
+        assert e.value.status == N.BGT_E_INVALID
+        assert "host-only" in N.bgt_last_error(ctx)
+    finally:
+        N.bgt_destroy(ctx)
+
+
+def test_create_rejects_bad_device_and_config():
+    with pytest.raises(N.BgtError):
+        N.bgt_create(N.bgt_default_config(tile=7), -1)
+    h = C.c_void_p()
+    assert N.lib().bgt_create(None, -1, C.byref(h)) == N.BGT_OK
+    N.bgt_destroy(h)
