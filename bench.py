@@ -1,0 +1,290 @@
+#!/usr/bin/env python
+"""Throughput of the BG-Triangle rasterizer (forward + backward) on one MI355X.
+
+A step is one pass of the whole path over one batch: tessellation, raster,
+sub-primitive generation, tile binning, discontinuity-aware blending, the
+L1-loss cotangent and the backward pass to every BG-Triangle parameter.
+Workload: the 2000-patch deformed sphere seen by 16 cameras on a sphere of
+radius 3 at 800x800 (10.24 Mpx per step), all views in one batched launch
+sequence captured in a hipGraph.  The same kernels launched view after view
+are timed beside it.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixels/s at 800×800, 16 views batched vs per-view, at 1e-4 error"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--workload", default="sphere2k_16v_800")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=2, help="views in the oracle's timed sample")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the batched graph replays (for rocprofv3); prints the JSON line")
+    return ap.parse_args()
+
+
+class Step:
+    """Pre-allocated buffers and the launch sequence of one fwd+bwd step."""
+
+    def __init__(self, renderer, degree, params, camt, wh, target):
+        import torch
+        self.torch = torch
+        self.r, self.degree, self.params, self.camt, self.wh = renderer, degree, params, camt, wh
+        self.npx = int((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
+        dev = camt.device
+        self.images = torch.empty((self.npx, 3), dtype=torch.float32, device=dev)
+        self.gimg = torch.empty_like(self.images)
+        self.target = target
+        self.grads = {k: torch.empty_like(v) for k, v in params.items()}
+        # size the state (and its pair capacities) with a checked eager pass
+        _, self.state = renderer.forward(degree, params, camt, wh, images=self.images, check=True)
+
+    def __call__(self):
+        torch = self.torch
+        self.r.forward(self.degree, self.params, self.camt, self.wh, state=self.state, images=self.images,
+                       check=False)
+        torch.sub(self.images, self.target, out=self.gimg)
+        torch.sign(self.gimg, out=self.gimg)
+        self.gimg.mul_(1.0 / self.gimg.numel())
+        self.r.backward(self.degree, self.params, self.camt, self.wh, self.images, self.gimg, self.state,
+                        grads=self.grads)
+
+
+class PerViewStep:
+    """The same kernels launched once per view (16 separate pipelines)."""
+
+    def __init__(self, renderer, degree, params, camt, wh, target):
+        import torch
+        self.torch = torch
+        off = np.concatenate([[0], np.cumsum(wh[:, 0].astype(np.int64) * wh[:, 1])])
+        self.steps = [Step(renderer, degree, params, camt[v:v + 1].contiguous(), wh[v:v + 1].copy(),
+                           target[off[v]:off[v + 1]]) for v in range(len(wh))]
+        self.grads = {k: torch.empty_like(v) for k, v in params.items()}
+        self.npx = int(off[-1])
+
+    def __call__(self):
+        torch = self.torch
+        for s in self.steps:
+            s.r.forward(s.degree, s.params, s.camt, s.wh, state=s.state, images=s.images, check=False)
+        for s in self.steps:
+            torch.sub(s.images, s.target, out=s.gimg)
+            torch.sign(s.gimg, out=s.gimg)
+            s.gimg.mul_(1.0 / (3 * self.npx))
+        for g in self.grads.values():
+            g.zero_()
+        for s in self.steps:
+            s.r.backward(s.degree, s.params, s.camt, s.wh, s.images, s.gimg, s.state, grads=s.grads)
+            for k, g in self.grads.items():
+                g.add_(s.grads[k])
+
+
+def capture(step):
+    import torch
+    step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    return g
+
+
+def time_replays(g, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def stage_profile(step, n=5):
+    """Per-stage kernel durations (ms) from the library's HIP events, eager."""
+    import torch
+    from paper_2503_13961_amd import native as N
+    r = step.r
+    N.bgt_profile(r.ctx, True)
+    acc = None
+    for _ in range(n):
+        step()
+        t = N.bgt_stage_times(r.ctx)
+        acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
+    N.bgt_profile(r.ctx, False)
+    torch.cuda.synchronize()
+    return {k: v / n for k, v in acc.items()}
+
+
+def algorithmic(counters, npx, ntiles, P, ncp):
+    """Algorithmic HBM bytes of each blend kernel per launch (each essential
+    read or write counted once):
+      forward : per Gaussian pair 4 B list entry + 48 B record (mean offset,
+                conic, colour, opacity, id, pixel range); per boundary pair
+                4 B + 16 B (position, radius, id); per pixel 4 B id read,
+                12 B image, 4 B transmittance, 4 B stop index written;
+                per tile 16 B of list ranges.
+      backward: the forward's reads again, plus per pixel 12 B image and
+                12 B cotangent read, and per Gaussian pair a 36 B gradient
+                read-modify-write (9 floats), per boundary pair 12 B."""
+    gp, bp = counters[1], counters[2]
+    fwd = gp * (4 + 48) + bp * (4 + 16) + npx * (4 + 12 + 4 + 4) + ntiles * 16
+    bwd = gp * (4 + 48 + 2 * 36) + bp * (4 + 16 + 2 * 12) + npx * (4 + 4 + 12 + 12) + ntiles * 16
+    return {"blend_fwd": fwd, "blend_bwd": bwd}
+
+
+def cpu_baseline(scene, cams, nviews):
+    """The FP64 oracle, fwd+bwd, on the first `nviews` views (a bounded sample)."""
+    import oracle
+    from paper_2503_13961_amd import scenes as S
+    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
+                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
+    t0 = time.perf_counter()
+    px = 0
+    for v in range(nviews):
+        W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
+        img = fr.render()[0]
+        gi = np.sign(img - S.l1_target(W * H, seed=v)) / (3 * W * H)
+        fr.grad(gi)
+        px += W * H
+    dt = time.perf_counter() - t0
+    return {"value": px / dt / 1e6, "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nviews} of the 16 views ({px} px), forward + backward, FP64, OpenMP",
+            "seconds": round(dt, 3), "cpu": platform.processor() or platform.machine()}
+
+
+def parity_check(scene, cams, images, samples=6000, seed=0):
+    """Image parity of the timed replay's output on sampled pixels of every view."""
+    import oracle
+    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
+                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
+    rng = np.random.default_rng(seed)
+    off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
+    worst = 0.0
+    for v in range(cams.n_views):
+        W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
+        pix = rng.choice(W * H, size=min(samples // cams.n_views, W * H), replace=False).astype(np.int32)
+        ref = fr.render(pix)[0]
+        worst = max(worst, float(np.abs(images[off[v] + pix] - ref).max()))
+    return worst
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(views would shard across GPUs with one all-reduce of the parameter gradients).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2503_13961_amd import scenes as S
+    from paper_2503_13961_amd.render import Renderer, scene_tensors
+
+    dev = torch.device("cuda", 0)
+    scene, cams, desc = S.workload(args.workload)
+    log(f"[bench] {desc}; tile {args.tile}")
+    params = scene_tensors(scene, dev)
+    camt = torch.from_numpy(cams.cams).to(dev)
+    wh = np.ascontiguousarray(cams.wh, dtype=np.int32)
+    target = torch.from_numpy(S.l1_target(cams.num_pixels)).to(dev)
+    r = Renderer(0, tile=args.tile)
+    step = Step(r, scene.degree, params, camt, wh, target)
+    st, counters = r.query(step.state)
+    log(f"[bench] counters {counters}")
+    g = capture(step)
+    log("[bench] graph captured")
+    ms = time_replays(g, args.steps, args.warmup)
+    npx = step.npx
+    value = npx / (ms * 1e-3) / 1e6
+    log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpix/s")
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {desc}", "views": int(cams.n_views),
+                      "width": int(wh[0, 0]), "height": int(wh[0, 1]), "pixels": npx,
+                      "prims": scene.num_prims, "degree": scene.degree, "tile": args.tile,
+                      "batched": True, "hipgraph": True}}
+    images_batched = step.images.detach().cpu().numpy()
+    if args.profile_run:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_per_view:
+        pv = PerViewStep(Renderer(0, tile=args.tile), scene.degree, params, camt, wh, target)
+        gpv = capture(pv)
+        ms_pv = time_replays(gpv, args.steps, args.warmup)
+        imgs_pv = torch.cat([s.images for s in pv.steps]).cpu().numpy()
+        same = bool(np.array_equal(imgs_pv, images_batched))
+        gdiff = max(float((pv.grads[k] - step.grads[k]).abs().max() / step.grads[k].abs().max().clamp_min(1e-30))
+                    for k in step.grads)
+        out["per_view"] = {"ms_per_step": round(ms_pv, 4), "value": round(npx / (ms_pv * 1e-3) / 1e6, 2),
+                           "batched_speedup": round(ms_pv / ms, 3), "images_bitwise_equal": same,
+                           "grad_max_rel_diff": gdiff}
+        log(f"[bench] per-view: {ms_pv:.3f} ms/step; images equal {same}; grad diff {gdiff:.2e}")
+        del pv, gpv
+    stages = stage_profile(step)
+    out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
+    log(f"[bench] stages {out['stage_ms']}")
+    ntiles = sum(((int(w) + args.tile - 1) // args.tile) * ((int(h) + args.tile - 1) // args.tile) for w, h in wh)
+    alg = algorithmic(counters, npx, ntiles, scene.num_prims, (scene.degree + 1) * (scene.degree + 2) // 2)
+    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
+    achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
+    out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "algorithmic_bytes": int(alg[dom]), "kernel_ms": round(stages[dom], 4)}
+    out["counters"] = {"gauss_pairs": counters[1], "boundary_pairs": counters[2], "foreground_px": counters[3],
+                       "boundary_px": counters[4]}
+    if not args.no_parity:
+        err = parity_check(scene, cams, images_batched)
+        out["parity"] = {"image_max_abs_err_sampled": err, "tolerance": 1e-4, "ok": err <= 1e-4}
+        log(f"[bench] parity: sampled image max abs err {err:.2e}")
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(scene, cams, args.cpu_views)
+        out["cpu_baseline"] = cb
+        log(f"[bench] cpu baseline {cb}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

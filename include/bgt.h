@@ -157,6 +157,18 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
 bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters,
                      void *stream);
 
+/* Optional stage timing.  While enabled, the context records a pair of HIP
+ * events around each stage it enqueues; bgt_stage_times synchronizes on the
+ * last recorded event and returns (host ms[BGT_NUM_STAGES]) the duration of
+ * the most recent launch of each stage, -1 for stages not launched since
+ * profiling was enabled.  Keep profiling off while a stream is captured.
+ * Stages: 0 tessellation + projection + raster, 1 sub-primitive generation,
+ * 2 tile binning (scan, scatter, sort), 3 blend forward, 4 blend backward,
+ * 5 parameter backward.  The clears of the gradient buffers are not timed. */
+#define BGT_NUM_STAGES 6
+bgt_status bgt_profile(bgt_ctx *ctx, int enable);
+bgt_status bgt_stage_times(bgt_ctx *ctx, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,10 @@ struct bgt_ctx {
     bgt_config cfg;
     int device;
     std::string err;
+    bool profiling = false;
+    bool recorded[BGT_NUM_STAGES] = {};
+    hipEvent_t ev0[BGT_NUM_STAGES] = {}, ev1[BGT_NUM_STAGES] = {};
+    int last_stage = -1;
 };
 
 namespace {
@@ -194,6 +198,23 @@ bgt_status use_device(bgt_ctx *ctx) {
     return BGT_OK;
 }
 
+// brackets one stage with the context's timing events when profiling is on
+struct StageTimer {
+    bgt_ctx *ctx;
+    int stage;
+    hipStream_t s;
+    StageTimer(bgt_ctx *c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+        if (ctx->profiling) hipEventRecord(ctx->ev0[stage], s);
+    }
+    ~StageTimer() {
+        if (ctx->profiling) {
+            hipEventRecord(ctx->ev1[stage], s);
+            ctx->recorded[stage] = true;
+            ctx->last_stage = stage;
+        }
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -216,7 +237,50 @@ bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out) {
     return BGT_OK;
 }
 
-void bgt_destroy(bgt_ctx *ctx) { delete ctx; }
+void bgt_destroy(bgt_ctx *ctx) {
+    if (!ctx) return;
+    for (int i = 0; i < BGT_NUM_STAGES; ++i) {
+        if (ctx->ev0[i]) hipEventDestroy(ctx->ev0[i]);
+        if (ctx->ev1[i]) hipEventDestroy(ctx->ev1[i]);
+    }
+    delete ctx;
+}
+
+bgt_status bgt_profile(bgt_ctx *ctx, int enable) {
+    if (!ctx) return BGT_E_INVALID;
+    bgt_status s;
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    if (enable && !ctx->ev0[0]) {
+        for (int i = 0; i < BGT_NUM_STAGES; ++i) {
+            hipError_t e = hipEventCreate(&ctx->ev0[i]);
+            if (e == hipSuccess) e = hipEventCreate(&ctx->ev1[i]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+        }
+    }
+    ctx->profiling = enable != 0;
+    for (int i = 0; i < BGT_NUM_STAGES; ++i) ctx->recorded[i] = false;
+    ctx->last_stage = -1;
+    return BGT_OK;
+}
+
+bgt_status bgt_stage_times(bgt_ctx *ctx, float *ms) {
+    if (!ctx || !ms) return BGT_E_INVALID;
+    bgt_status s;
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    if (ctx->last_stage >= 0) {
+        hipError_t e = hipEventSynchronize(ctx->ev1[ctx->last_stage]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+    }
+    for (int i = 0; i < BGT_NUM_STAGES; ++i) {
+        ms[i] = -1.0f;
+        if (ctx->recorded[i]) {
+            hipError_t e = hipEventSynchronize(ctx->ev1[i]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], ctx->ev0[i], ctx->ev1[i]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+        }
+    }
+    return BGT_OK;
+}
 
 const char *bgt_last_error(const bgt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -274,9 +338,22 @@ bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     if ((e = launch_fill_u64(sp.zbuf, 0ull, sh.N, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_i32(sp.g_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_i32(sp.b_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
-    if ((e = launch_geometry(sh.k, sh.vt, pp, views->cams, sp, st)) != hipSuccess) return hip_fail(ctx, e, "geometry");
-    if ((e = launch_binning(sh.k, sh.vt, sp, st)) != hipSuccess) return hip_fail(ctx, e, "binning");
-    if ((e = launch_blend_fwd(sh.k, sh.vt, sp, images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_fwd");
+    {
+        StageTimer tm(ctx, 0, st);
+        if ((e = launch_raster(sh.k, sh.vt, pp, views->cams, sp, st)) != hipSuccess) return hip_fail(ctx, e, "raster");
+    }
+    {
+        StageTimer tm(ctx, 1, st);
+        if ((e = launch_gen(sh.k, sh.vt, pp, views->cams, sp, st)) != hipSuccess) return hip_fail(ctx, e, "generation");
+    }
+    {
+        StageTimer tm(ctx, 2, st);
+        if ((e = launch_binning(sh.k, sh.vt, sp, st)) != hipSuccess) return hip_fail(ctx, e, "binning");
+    }
+    {
+        StageTimer tm(ctx, 3, st);
+        if ((e = launch_blend_fwd(sh.k, sh.vt, sp, images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_fwd");
+    }
     return BGT_OK;
 }
 
@@ -314,8 +391,14 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(sp.dgauss, 0.f, 12 * sh.N, st)) != hipSuccess)
         return hip_fail(ctx, e, "fill");
-    if ((e = launch_blend_bwd(k, sh.vt, sp, images, grad_images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_bwd");
-    if ((e = launch_param_bwd(k, sh.vt, pp, views->cams, sp, gp, st)) != hipSuccess) return hip_fail(ctx, e, "param_bwd");
+    {
+        StageTimer tm(ctx, 4, st);
+        if ((e = launch_blend_bwd(k, sh.vt, sp, images, grad_images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_bwd");
+    }
+    {
+        StageTimer tm(ctx, 5, st);
+        if ((e = launch_param_bwd(k, sh.vt, pp, views->cams, sp, gp, st)) != hipSuccess) return hip_fail(ctx, e, "param_bwd");
+    }
     return BGT_OK;
 }
 

@@ -488,8 +488,8 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
     }
 }
 
-hipError_t launch_geometry(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
-                           const StatePtrs &st, hipStream_t s) {
+hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                         const StatePtrs &st, hipStream_t s) {
     hipError_t e;
     if ((e = launch_tessellate(k, pr, st.wverts, nullptr, s)) != hipSuccess) return e;
     {
@@ -504,6 +504,11 @@ hipError_t launch_geometry(const Consts &k, const ViewTable &vt, const PrimPtrs 
         hipLaunchKernelGGL(k_raster_big, dim3(1024), dim3(256), 0, s, k, vt, (const VertRec *)st.verts, st.zbuf,
                            (const int32_t *)st.big_tris, (const int64_t *)st.counters);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                      const StatePtrs &st, hipStream_t s) {
     {
         dim3 grid((unsigned)((vt.total_px + 255) / 256)), block(256);
         switch (k.degree) {

@@ -127,8 +127,10 @@ __device__ __forceinline__ int hi16(int v) { return v >> 16; }
 
 hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts, float *verts_out,
                              hipStream_t s);
-hipError_t launch_geometry(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
-                           const StatePtrs &st, hipStream_t s);
+hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                         const StatePtrs &st, hipStream_t s);
+hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
+                      const StatePtrs &st, hipStream_t s);
 hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s);
 hipError_t launch_blend_fwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, float *image,
                             hipStream_t s);

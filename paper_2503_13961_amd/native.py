@@ -20,7 +20,10 @@ STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey
                      "g_keys", "g_list", "b_keys", "b_list", "dgauss", "big_tris", "scan", "end"]
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
-           "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query"]
+           "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query", "bgt_profile",
+           "bgt_stage_times"]
+BGT_NUM_STAGES = 6
+STAGE_NAMES = ["raster", "generation", "binning", "blend_fwd", "blend_bwd", "param_bwd"]
 
 
 class BgtError(RuntimeError):
@@ -87,6 +90,8 @@ def lib():
         L.bgt_render_bwd.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), vp, vp, vp, C.c_size_t,
                                      C.POINTER(bgt_grads), vp]
         L.bgt_query.argtypes = [vp, vp, C.c_size_t, i64p, vp]
+        L.bgt_profile.argtypes = [vp, C.c_int]
+        L.bgt_stage_times.argtypes = [vp, C.POINTER(C.c_float)]
         _lib = L
     return _lib
 
@@ -172,6 +177,16 @@ def bgt_query(ctx, state_ptr, state_bytes, stream=0):
     if st not in (BGT_OK, BGT_E_OVERFLOW):
         raise BgtError(st, bgt_last_error(ctx))
     return st, [int(x) for x in out]
+
+
+def bgt_profile(ctx, enable: bool) -> int:
+    return _check(ctx, lib().bgt_profile(ctx, 1 if enable else 0))
+
+
+def bgt_stage_times(ctx) -> dict:
+    ms = (C.c_float * BGT_NUM_STAGES)()
+    _check(ctx, lib().bgt_stage_times(ctx, ms))
+    return dict(zip(STAGE_NAMES, [float(x) for x in ms]))
 
 
 # ------------------------------------------------------------ struct builders
