@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=2, help="views in the oracle's timed sample")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the batched graph replays (for rocprofv3); prints the JSON line")
+    ap.add_argument("--eager", action="store_true",
+                    help="with --profile-run: launch the steps eagerly instead of replaying the graph")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -229,8 +233,23 @@ def main():
     camt = torch.from_numpy(cams.cams).to(dev)
     wh = np.ascontiguousarray(cams.wh, dtype=np.int32)
     target = torch.from_numpy(S.l1_target(cams.num_pixels)).to(dev)
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mb} MiB read + written")
+        del src, dst
     r = Renderer(0, tile=args.tile)
     step = Step(r, scene.degree, params, camt, wh, target)
+    if args.profile_run and args.eager:
+        for _ in range(args.warmup + args.steps):
+            step()
+        torch.cuda.synchronize()
+        log("[bench] eager profile steps done")
+        print(json.dumps({"profile_run": "eager", "steps": args.steps + args.warmup}), flush=True)
+        return
     st, counters = r.query(step.state)
     log(f"[bench] counters {counters}")
     g = capture(step)

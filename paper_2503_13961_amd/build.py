@@ -18,9 +18,16 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-u
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+# per-file extras: the blend kernels issue their LDS/global atomics from one
+# lane after an explicit wave reduction, so the compiler's own atomic
+# combining would only add a readlane loop around each of them
+EXTRA = {"bgt_blend.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else []) + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else []) + EXTRA.get(os.path.basename(src), []) + \
+        ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

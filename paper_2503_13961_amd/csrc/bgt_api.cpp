@@ -89,6 +89,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
         vi.tiles_y = (vi.H + c.tile - 1) / c.tile;
         vi.px_off = (int32_t)px;
         vi.tile_off = (int32_t)tiles;
+        vi.b8_off = (int32_t)b8;
+        vi.b8_x = (vi.W + 7) / 8;
         px += (int64_t)vi.W * vi.H;
         tiles += (int64_t)vi.tiles_x * vi.tiles_y;
         b8 += (int64_t)((vi.W + 7) / 8) * ((vi.H + 7) / 8);

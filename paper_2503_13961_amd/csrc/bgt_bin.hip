@@ -117,40 +117,56 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int32_t *gc, int32_t
 // ------------------------------------------------------------ scatter
 
 __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePtrs st) {
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= vt.total_px) return;
-    const uint8_t fl = st.pflags[pix];
-    if (!(fl & PF_VALID)) return;
-    const int v = view_of_pixel(vt, pix);
+    const int lane = threadIdx.x & 63;
+    int v, x, y;
+    const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
     const ViewInfo vi = vt.v[v];
-    const unsigned long long local = (unsigned long long)(pix - vi.px_off);
-    const float4 r3 = st.rec[(int64_t)pix * 4 + 3];
     const int TS = k.tile;
-    {
-        const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
-        const int i0 = lo16(gx), i1 = hi16(gx), j0 = lo16(gy), j1 = hi16(gy);
-        const unsigned long long key = (st.gkey[pix] << 24) | local;
-        if (i0 <= i1 && j0 <= j1)
-            for (int ty = j0 / TS; ty <= j1 / TS; ++ty)
-                for (int tx = i0 / TS; tx <= i1 / TS; ++tx) {
-                    const int t = vi.tile_off + ty * vi.tiles_x + tx;
-                    const int slot = atomicAdd(&st.g_cursor[t], 1);
-                    if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = key;
+    int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;
+    unsigned long long gkey = 0ull, bkey = 0ull;
+    if (act) {
+        const int lp = y * vi.W + x, pix = vi.px_off + lp;
+        const uint8_t fl = st.pflags[pix];
+        if (fl & PF_VALID) {
+            const float4 r3 = st.rec[(int64_t)pix * 4 + 3];
+            const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
+            if (lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
+                gt0 = lo16(gx) / TS; gt1 = hi16(gx) / TS; gu0 = lo16(gy) / TS; gu1 = hi16(gy) / TS;
+            }
+            gkey = (st.gkey[pix] << 24) | (unsigned long long)lp;
+            if (fl & PF_BOUNDARY) {
+                const int bx = __float_as_int(r3.z), by = __float_as_int(r3.w);
+                if (lo16(bx) <= hi16(bx) && lo16(by) <= hi16(by)) {
+                    bt0 = lo16(bx) / TS; bt1 = hi16(bx) / TS; bu0 = lo16(by) / TS; bu1 = hi16(by) / TS;
                 }
+                const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
+                bkey = ((unsigned long long)prim << 24) | (unsigned long long)lp;
+            }
+        }
     }
-    if (fl & PF_BOUNDARY) {
-        const int bx = __float_as_int(r3.z), by = __float_as_int(r3.w);
-        const int i0 = lo16(bx), i1 = hi16(bx), j0 = lo16(by), j1 = hi16(by);
-        const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
-        const unsigned long long key = ((unsigned long long)prim << 24) | local;
-        if (i0 <= i1 && j0 <= j1)
-            for (int ty = j0 / TS; ty <= j1 / TS; ++ty)
-                for (int tx = i0 / TS; tx <= i1 / TS; ++tx) {
-                    const int t = vi.tile_off + ty * vi.tiles_x + tx;
-                    const int slot = atomicAdd(&st.b_cursor[t], 1);
-                    if (slot < st.b_start[t] + st.b_count[t]) st.b_keys[slot] = key;
-                }
-    }
+    // one cursor atomic per group of lanes at the same tile; each lane takes
+    // the slot of its rank within the group
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off,
+                      [&](int t, unsigned long long gm, bool in, int leader) {
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&st.g_cursor[t], __popcll(gm));
+        base = __shfl(base, leader, 64);
+        if (in) {
+            const int slot = base + __popcll(gm & below);
+            if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = gkey;
+        }
+    });
+    for_tiles_grouped(bt0, bt1, bu0, bu1, vi.tiles_x, vi.tile_off,
+                      [&](int t, unsigned long long gm, bool in, int leader) {
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&st.b_cursor[t], __popcll(gm));
+        base = __shfl(base, leader, 64);
+        if (in) {
+            const int slot = base + __popcll(gm & below);
+            if (slot < st.b_start[t] + st.b_count[t]) st.b_keys[slot] = bkey;
+        }
+    });
 }
 
 // ------------------------------------------------------------ segment sort
@@ -242,7 +258,7 @@ hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs 
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, st.g_count, st.g_start, st.g_cursor,
                        st.b_count, st.b_start, st.b_cursor, (const int64_t *)sums, n, nb, k.cap_g, k.cap_b,
                        st.counters);
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((vt.total_px + 255) / 256)), dim3(256), 0, s, k, vt, st);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((vt.total_b8 + 3) / 4)), dim3(256), 0, s, k, vt, st);
     hipLaunchKernelGGL(k_sort_tiles, dim3(n, 2), dim3(256), 0, s, vt, st);
     hipLaunchKernelGGL(k_sort_big, dim3(64, 2), dim3(256), 0, s, vt, st);
     return hipGetLastError();

@@ -44,7 +44,7 @@ struct TileGeom {
 template <int TS, typename MapT>
 struct BoundaryLds {
     float bdx[kBoundaryLds], bdy[kBoundaryLds], bs[kBoundaryLds];
-    int bix[kBoundaryLds], biy[kBoundaryLds];
+    int bxy[kBoundaryLds];  // tile-relative pixel x | y << 16 (int16 each)
     int bp[kBoundaryLds], brun[kBoundaryLds];
     int run_prim[kBoundaryLds], run_start[kBoundaryLds + 1];
     int wsum[33];
@@ -56,10 +56,15 @@ struct BoundaryLds {
 // the Gaussian's own pixel, w0 the origin of the wave's 8x8 block and delta
 // the mean's offset from g's centre: one rounding that does not depend on
 // the tile size.
+// A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
+// the Gaussian's own pixel, w0 the origin of the wave's 8x8 block and delta
+// the mean's offset from g's centre: one rounding that does not depend on
+// the tile size.
 template <int TS, int K>
 struct BatchLds {
-    float mx[TS * TS / 64][K], my[TS * TS / 64][K];
-    float qa[K], qb[K], qc[K], cr[K], cg[K], cb[K], op[K];
+    float2 m[TS * TS / 64][K];  // per-wave mean offsets
+    float4 q[K];                // conic (a, b, c), opacity
+    float4 c[K];                // colour, unused
     int prim[K], run[K], xr[K], yr[K], gp[K];
 };
 
@@ -101,8 +106,7 @@ __device__ __forceinline__ void stage_boundary(BoundaryLds<TS, MapT> &B, const S
         const float4 r0 = st.rec[(int64_t)bpix * 4];
         const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
         const int lp = bpix - vi.px_off;
-        B.bix[e] = lp % vi.W - ox;  // relative to the tile origin
-        B.biy[e] = lp / vi.W - oy;
+        B.bxy[e] = pack16(lp % vi.W - ox, lp / vi.W - oy);  // relative to the tile origin
         B.bdx[e] = r0.x;
         B.bdy[e] = r0.y;
         B.bs[e] = r2.z;
@@ -140,8 +144,13 @@ __device__ __forceinline__ int find_run(const int *run_prim, int n_runs, int g) 
     return -1;
 }
 
+// |(dx, dy)| with an explicit rounding sequence, so every code path that
+// evaluates a boundary distance produces the same bits
+__device__ __forceinline__ float bdist(float dx, float dy) { return sqrtf(__fmaf_rn(dx, dx, __fmul_rn(dy, dy))); }
+
+// gamma(d; sigma) = min(2^(d/sigma - 1), 1)  (Eq. 7)
 __device__ __forceinline__ float gamma_fn(float d, float sigma) {
-    const float g = exp2f(d / sigma - 1.0f);
+    const float g = exp2f(__fsub_rn(__fdiv_rn(d, sigma), 1.0f));
     return g < 1.0f ? g : 1.0f;
 }
 
@@ -151,8 +160,8 @@ __device__ __forceinline__ float gamma_lds(const BoundaryLds<TS, MapT> &B, int r
     float best = 1.0f;
     *arg = -1;
     for (int e = B.run_start[r]; e < B.run_start[r + 1]; ++e) {
-        const float dx = (float)(lx - B.bix[e]) - B.bdx[e], dy = (float)(ly - B.biy[e]) - B.bdy[e];
-        const float g = gamma_fn(sqrtf(dx * dx + dy * dy), B.bs[e]);
+        const float dx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], dy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
+        const float g = gamma_fn(bdist(dx, dy), B.bs[e]);
         if (g < best) { best = g; *arg = e; }
     }
     return best;
@@ -177,7 +186,7 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
         const float4 r0 = st.rec[(int64_t)bpix * 4];
         const int lp = bpix - vi.px_off;
         const float dx = (float)(px - lp % vi.W) - r0.x, dy = (float)(py - lp / vi.W) - r0.y;
-        const float gm = gamma_fn(sqrtf(dx * dx + dy * dy), r2.z);
+        const float gm = gamma_fn(bdist(dx, dy), r2.z);
         if (gm < best) { best = gm; *arg = e; }
     }
     return best;
@@ -197,7 +206,7 @@ __device__ __forceinline__ void build_gamma_maps(BoundaryLds<TS, MapT> &B) {
     for (int e = threadIdx.x; e < B.nbl; e += blockDim.x) {
         const int r = B.brun[e];
         if (r >= RunMaps<TS>::value) continue;
-        const int bix = B.bix[e], biy = B.biy[e];
+        const int bix = lo16(B.bxy[e]), biy = hi16(B.bxy[e]);
         const float bdx = B.bdx[e], bdy = B.bdy[e], sg = B.bs[e];
         const float rf = sg + fabsf(bdx) + fabsf(bdy);
         const int rad = rf < (float)(2 * TS) ? (int)ceilf(rf) + 1 : 2 * TS;  // NaN/inf -> whole tile
@@ -206,9 +215,9 @@ __device__ __forceinline__ void build_gamma_maps(BoundaryLds<TS, MapT> &B) {
         for (int y = y0; y <= y1; ++y)
             for (int x = x0; x <= x1; ++x) {
                 const float dx = (float)(x - bix) - bdx, dy = (float)(y - biy) - bdy;
-                const float d = sqrtf(dx * dx + dy * dy);
+                const float d = bdist(dx, dy);
                 if (d < sg) {
-                    const float g = exp2f(d / sg - 1.0f);
+                    const float g = gamma_fn(d, sg);
                     if (g < 1.0f) {
                         if (sizeof(MapT) == 4)
                             atomicMin((unsigned *)&B.map[r][G::tid_of(x, y)], __float_as_uint(g));
@@ -233,19 +242,59 @@ __device__ __forceinline__ void load_batch(BatchLds<TS, K> &S, const StatePtrs &
     const int lp = gp - vi.px_off;
     const int x = lp % vi.W - ox, y = lp / vi.W - oy;  // tile-relative pixel of the Gaussian
 #pragma unroll
-    for (int w = 0; w < G::NT / 64; ++w) {
-        S.mx[w][kk] = (float)(x - (w % G::SPR) * 8) + r0.x;
-        S.my[w][kk] = (float)(y - (w / G::SPR) * 8) + r0.y;
-    }
-    S.qa[kk] = r0.z; S.qb[kk] = r0.w; S.qc[kk] = r1.x;
-    S.cr[kk] = r1.y; S.cg[kk] = r1.z; S.cb[kk] = r1.w;
-    S.op[kk] = r2.x;
+    for (int w = 0; w < G::NT / 64; ++w)
+        S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + r0.x, (float)(y - (w / G::SPR) * 8) + r0.y);
+    S.q[kk] = make_float4(r0.z, r0.w, r1.x, r2.x);
+    S.c[kk] = make_float4(r1.y, r1.z, r1.w, 0.f);
     const int g = __float_as_int(r2.y);
     S.prim[kk] = g;
     S.run[kk] = slow_b ? -2 : find_run(run_prim, n_runs, g);
     S.xr[kk] = __float_as_int(r3.x);
     S.yr[kk] = __float_as_int(r3.y);
     S.gp[kk] = gp;
+}
+
+// does the pixel range (packed int16 pairs) touch the 8x8 block at (x0, y0)?
+__device__ __forceinline__ bool touches_block(int xr, int yr, int x0, int y0) {
+    return !(hi16(xr) < x0 || lo16(xr) > x0 + 7 || hi16(yr) < y0 || lo16(yr) > y0 + 7);
+}
+
+// Nine sums over the wave at once, step-major, so that consecutive DPP adds
+// are independent (no hazard stalls between the steps of one sum).
+__device__ __forceinline__ void wave_sum9_to_63(float *v);
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+    // bound_ctrl: lanes whose source is outside the row/wave read 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+
+// Sum over the 64 lanes with DPP: row shifts leave each 16-lane row's sum in
+// its lane 15, then two row broadcasts add rows 0-2 into lane 63.  Only lane
+// 63's result is meaningful (the other lanes hold partial sums).
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+    v += dpp_f<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_f<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_f<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_f<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_f<0x142, 0xF>(v);  // row_bcast:15: lane 63 += lane 47 (row 2)
+    v += dpp_f<0x143, 0xF>(v);  // row_bcast:31: lane 63 += lane 31 (rows 0 + 1)
+    return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_step9(float *v) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] += dpp_f<CTRL, 0xF>(v[i]);
+}
+
+__device__ __forceinline__ void wave_sum9_to_63(float *v) {
+    dpp_step9<0x111>(v);  // row_shr:1
+    dpp_step9<0x112>(v);  // row_shr:2
+    dpp_step9<0x114>(v);  // row_shr:4
+    dpp_step9<0x118>(v);  // row_shr:8
+    dpp_step9<0x142>(v);  // row_bcast:15
+    dpp_step9<0x143>(v);  // row_bcast:31
 }
 
 // ------------------------------------------------------------ forward
@@ -255,7 +304,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     using G = TileGeom<TS>;
     __shared__ BoundaryLds<TS, unsigned> B;
     __shared__ BatchLds<TS, K> S;
-    const int t = blockIdx.x, tid = threadIdx.x;
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
     const int tl = t - vi.tile_off, tx = tl % vi.tiles_x, ty = tl / vi.tiles_x;
@@ -271,7 +320,6 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     }
     const int ox = tx * TS, oy = ty * TS;
     const float qx = (float)(lx & 7), qy = (float)(ly & 7);  // position in the wave's 8x8 block
-    const int wave = tid >> 6;
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
@@ -284,21 +332,30 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     bool done = !inside;
     int last = gc;
-    const float kappa2 = k.kappa2, amax = k.alpha_max, tmin = k.t_min;
+    const float amax = k.alpha_max, tmin = k.t_min;
+    // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
+    const float e_min = -0.5f * k.kappa2 * 1.44269504088896341f;
+    constexpr float kE = -0.5f * 1.44269504088896341f;
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;
         if (tid < K && base + tid < gc) load_batch<TS, K>(S, st, vi, gs0, base + tid, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
         __syncthreads();
         const int nk = min(K, gc - base);
-        if (!done) {
-            for (int kk = 0; kk < nk; ++kk) {
-                const int xr = S.xr[kk], yr = S.yr[kk];
-                if (hi16(xr) < wx0 || lo16(xr) > wx0 + 7 || hi16(yr) < wy0 || lo16(yr) > wy0 + 7) continue;
+        if (__all(done)) continue;
+        for (int c0 = 0; c0 < K; c0 += 64) {
+            const int j = c0 + lane;
+            unsigned long long mask = __ballot(j < nk && touches_block(S.xr[j], S.yr[j], wx0, wy0));
+            while (mask) {
+                const int kk = c0 + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                if (done) continue;
                 const int g = S.prim[kk], r = S.run[kk];
-                if (g != h && r == -1) continue;  // w = 0: no boundary of g near this tile
-                const float dx = qx - S.mx[wave][kk], dy = qy - S.my[wave][kk];
-                const float power = S.qa[kk] * dx * dx + 2.0f * S.qb[kk] * dx * dy + S.qc[kk] * dy * dy;
-                if (power > kappa2) continue;
+                if (g != h && r == -1) continue;  // w = 0: no boundary point of g near this tile
+                const float2 m = S.m[wave][kk];
+                const float4 q = S.q[kk];
+                const float dx = qx - m.x, dy = qy - m.y;
+                const float e = kE * (q.x * dx * dx + 2.0f * q.y * dx * dy + q.z * dy * dy);
+                if (e < e_min) continue;
                 float gam = 1.0f;
                 if (r >= 0) {
                     int arg;
@@ -309,15 +366,15 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                 }
                 const float w = g == h ? gam : 1.0f - gam;
                 if (w <= 0.0f) continue;
-                const float Gv = __expf(-0.5f * power);
-                float a = S.op[kk] * w * Gv;
+                float a = q.w * w * exp2f(e);
                 a = a > amax ? amax : a;
                 const float ta = T * a;
-                C0 += ta * S.cr[kk];
-                C1 += ta * S.cg[kk];
-                C2 += ta * S.cb[kk];
+                const float4 c = S.c[kk];
+                C0 += ta * c.x;
+                C1 += ta * c.y;
+                C2 += ta * c.z;
                 T = T * (1.0f - a);
-                if (T < tmin) { done = true; last = base + kk + 1; break; }
+                if (T < tmin) { done = true; last = base + kk + 1; }
             }
         }
     }
@@ -332,23 +389,39 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 
 // ------------------------------------------------------------ backward
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
+// Front-to-back replay of the forward per pixel: T_i is recomputed exactly as
+// the forward did, the suffix S_i = sum_{j>i} T_j a_j c_j + T_n bg is the
+// forward colour minus the running prefix, and
+//   dl/dc_i = T_i a_i dl/dC,  dl/da_i = dl/dC . (T_i c_i - S_i / (1 - a_i)),
+//   dl/dw = dl/da a / w (Supplementary Sec. C), G = exp(-d^T Q d / 2).
+// Per Gaussian the 9 gradient values are summed over the wave with DPP and
+// over the waves in LDS, then added to global memory once per tile.  The
+// boundary terms accumulate per (run, pixel) and go to the minimising
+// boundary point at the end of the tile.
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
     using G = TileGeom<TS>;
-    __shared__ BoundaryLds<TS, unsigned long long> B;
-    __shared__ BatchLds<TS, K> S;
-    __shared__ float acc[K][9];
-    __shared__ float dgam[RunMaps<TS>::value][TS * TS];
-    __shared__ float bacc[kBoundaryLds][3];
+    constexpr int RM = RunMaps<TS>::value;
+    __shared__ BoundaryLds<TS, unsigned> B;
+    // the batch stage and its gradient sums are dead once the list is done;
+    // the per-point boundary sums reuse their space
+    struct LoopLds {
+        BatchLds<TS, K> S;
+        float acc[K][9];
+    };
+    union TailLds {
+        LoopLds loop;
+        float bacc[kBoundaryLds][3];
+    };
+    __shared__ TailLds U;
     __shared__ int max_last;
-    const int t = blockIdx.x, tid = threadIdx.x;
+    BatchLds<TS, K> &S = U.loop.S;
+    float(&acc)[K][9] = U.loop.acc;
+    float dgam[RM];  // per-run sums of dl/dgamma* at this pixel (registers, uniform index)
+#pragma unroll
+    for (int i = 0; i < RM; ++i) dgam[i] = 0.f;
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
     const int tl = t - vi.tile_off, tx = tl % vi.tiles_x, ty = tl / vi.tiles_x;
@@ -357,27 +430,28 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int px = tx * TS + lx, py = ty * TS + ly;
     const bool inside = px < vi.W && py < vi.H;
     const int pix = vi.px_off + py * vi.W + px;
+    const int gc = st.g_count[t];
     int h = -1, mylast = 0;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f, im0 = 0.f, im1 = 0.f, im2 = 0.f;
     if (inside) {
         const int tri = st.I_tri[pix];
         h = tri < 0 ? -1 : tri / k.L2;
-        mylast = min(max(st.last[pix], 0), st.g_count[t]);
+        mylast = min(max(st.last[pix], 0), gc);
         g0 = grad_image[3 * (int64_t)pix]; g1 = grad_image[3 * (int64_t)pix + 1]; g2 = grad_image[3 * (int64_t)pix + 2];
         im0 = image[3 * (int64_t)pix]; im1 = image[3 * (int64_t)pix + 1]; im2 = image[3 * (int64_t)pix + 2];
         if (g0 == 0.f && g1 == 0.f && g2 == 0.f) mylast = 0;
     }
     const int ox = tx * TS, oy = ty * TS;
-    const float qx = (float)(lx & 7), qy = (float)(ly & 7);  // position in the wave's 8x8 block
-    const int wave = tid >> 6, lane = tid & 63;
+    const float qx = (float)(lx & 7), qy = (float)(ly & 7);
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     if (tid == 0) max_last = 0;
     for (int i = tid; i < K * 9; i += blockDim.x) (&acc[0][0])[i] = 0.f;
-    for (int i = tid; i < RunMaps<TS>::value * TS * TS; i += blockDim.x) (&dgam[0][0])[i] = 0.f;
-    for (int i = tid; i < kBoundaryLds * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
     atomicMax(&max_last, mylast);
+    int wave_last = mylast;  // last list entry any lane of this wave replays
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
     stage_boundary<TS>(B, st, bs0, bc, ox, oy, vi);  // (syncs)
@@ -387,75 +461,74 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int gs0 = st.g_start[t];
     const int nlast = max_last;
     float T = 1.0f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
-    const float kappa2 = k.kappa2, amax = k.alpha_max;
-    const float bg0 = k.bg[0], bg1 = k.bg[1], bg2 = k.bg[2];
-    (void)bg0; (void)bg1; (void)bg2;
+    const float amax = k.alpha_max;
+    const float e_min = -0.5f * k.kappa2 * 1.44269504088896341f;
+    constexpr float kE = -0.5f * 1.44269504088896341f;
     const float LN2 = 0.69314718055994531f;
     for (int base = 0; base < nlast; base += K) {
         if (tid < K && base + tid < nlast) load_batch<TS, K>(S, st, vi, gs0, base + tid, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
         __syncthreads();
         const int nk = min(K, nlast - base);
-        for (int kk = 0; kk < nk; ++kk) {
-            const int xr = S.xr[kk], yr = S.yr[kk];
-            if (hi16(xr) < wx0 || lo16(xr) > wx0 + 7 || hi16(yr) < wy0 || lo16(yr) > wy0 + 7) continue;  // wave-uniform
-            float d_mx = 0.f, d_my = 0.f, d_qa = 0.f, d_qb = 0.f, d_qc = 0.f, d_c0 = 0.f, d_c1 = 0.f, d_c2 = 0.f, d_o = 0.f;
-            bool contrib = false;
-            if (base + kk < mylast) {
-                const int g = S.prim[kk], r = S.run[kk];
-                if (!(g != h && r == -1)) {
-                    const float dx = qx - S.mx[wave][kk], dy = qy - S.my[wave][kk];
-                    const float qa = S.qa[kk], qb = S.qb[kk], qc = S.qc[kk];
-                    const float power = qa * dx * dx + 2.0f * qb * dx * dy + qc * dy * dy;
-                    if (power <= kappa2) {
+        for (int c0 = 0; c0 < K && base + c0 < wave_last; c0 += 64) {
+            const int j = c0 + lane;
+            unsigned long long mask =
+                __ballot(j < nk && base + j < wave_last && touches_block(S.xr[j], S.yr[j], wx0, wy0));
+            while (mask) {
+                const int kk = c0 + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                float d_mx = 0.f, d_my = 0.f, d_qa = 0.f, d_qb = 0.f, d_qc = 0.f, d_c0 = 0.f, d_c1 = 0.f, d_c2 = 0.f,
+                      d_o = 0.f;
+                bool contrib = false;
+                const int g = S.prim[kk];
+                const int r = __builtin_amdgcn_readfirstlane(S.run[kk]);  // wave-uniform
+                if (base + kk < mylast && (g == h || r != -1)) {
+                    const float2 m = S.m[wave][kk];
+                    const float4 q = S.q[kk];
+                    const float dx = qx - m.x, dy = qy - m.y;
+                    const float e = kE * (q.x * dx * dx + 2.0f * q.y * dx * dy + q.z * dy * dy);
+                    if (e >= e_min) {
                         float gam = 1.0f;
                         int arg = -1;
                         if (r >= 0) {
-                            if (r < RunMaps<TS>::value) {
-                                const unsigned long long mv = B.map[r][tid];
-                                gam = __uint_as_float((unsigned)(mv >> 32));
-                                arg = (int)(mv & 0xFFFFFFFFull);
-                            } else {
-                                gam = gamma_lds<TS>(B, r, lx, ly, &arg);
-                            }
+                            gam = r < RM ? __uint_as_float(B.map[r][tid]) : gamma_lds<TS>(B, r, lx, ly, &arg);
                         } else if (r == -2) {
                             gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
                         }
                         const float w = g == h ? gam : 1.0f - gam;
                         if (w > 0.0f) {
                             contrib = true;
-                            const float Gv = __expf(-0.5f * power);
-                            const float o = S.op[kk];
+                            const float Gv = exp2f(e);
+                            const float o = q.w;
                             const float raw = o * w * Gv;
                             const bool clamped = raw > amax;
                             const float a = clamped ? amax : raw;
                             const float ta = T * a;
-                            const float c0 = S.cr[kk], c1 = S.cg[kk], c2 = S.cb[kk];
+                            const float4 c = S.c[kk];
                             d_c0 = ta * g0; d_c1 = ta * g1; d_c2 = ta * g2;
-                            P0 += ta * c0; P1 += ta * c1; P2 += ta * c2;
-                            // S_i = sum_{j>i} T_j a_j c_j + T_n bg = C - prefix_{<=i}
-                            const float inv = 1.0f / (1.0f - a);
-                            const float dalpha = g0 * (T * c0 - (im0 - P0) * inv) + g1 * (T * c1 - (im1 - P1) * inv) +
-                                                 g2 * (T * c2 - (im2 - P2) * inv);
+                            P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
+                            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+                            const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
+                                                 g2 * (T * c.z - (im2 - P2) * inv);
                             T = T * (1.0f - a);
                             if (!clamped) {
                                 d_o = dalpha * w * Gv;
-                                const float dG = dalpha * o * w * Gv;  // dl/dG * G
-                                d_mx = dG * (qa * dx + qb * dy);
-                                d_my = dG * (qb * dx + qc * dy);
+                                const float dG = d_o * o;  // dl/dG * G
+                                d_mx = dG * (q.x * dx + q.y * dy);
+                                d_my = dG * (q.y * dx + q.z * dy);
                                 d_qa = -0.5f * dG * dx * dx;
                                 d_qb = -dG * dx * dy;
                                 d_qc = -0.5f * dG * dy * dy;
-                                if (arg >= 0 && gam < 1.0f) {
+                                if (r != -1 && gam < 1.0f) {
                                     const float dgm = (g == h ? 1.0f : -1.0f) * dalpha * o * Gv;
-                                    if (r >= 0 && r < RunMaps<TS>::value) {
-                                        dgam[r][tid] += dgm;
-                                    } else {
-                                        // no map: push the boundary-point gradient now
+                                    if (r >= 0 && r < RM) {
+                                        dgam[r] += dgm;  // r is wave-uniform: indexed register access
+                                    } else if (arg >= 0) {
+                                        // no map for this run: push the boundary-point gradient now
                                         float ddx, ddy, sg;
                                         const int bpix = (int)st.b_list[bs0 + arg];
                                         if (r >= 0) {
-                                            ddx = (float)(lx - B.bix[arg]) - B.bdx[arg];
-                                            ddy = (float)(ly - B.biy[arg]) - B.bdy[arg];
+                                            ddx = (float)(lx - lo16(B.bxy[arg])) - B.bdx[arg];
+                                            ddy = (float)(ly - hi16(B.bxy[arg])) - B.bdy[arg];
                                             sg = B.bs[arg];
                                         } else {
                                             const float4 r0 = st.rec[(int64_t)bpix * 4];
@@ -478,17 +551,13 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         }
                     }
                 }
-            }
-            if (__any(contrib)) {
-                d_mx = wave_sum(d_mx); d_my = wave_sum(d_my);
-                d_qa = wave_sum(d_qa); d_qb = wave_sum(d_qb); d_qc = wave_sum(d_qc);
-                d_c0 = wave_sum(d_c0); d_c1 = wave_sum(d_c1); d_c2 = wave_sum(d_c2);
-                d_o = wave_sum(d_o);
-                if (lane == 0) {
-                    atomicAdd(&acc[kk][0], d_mx); atomicAdd(&acc[kk][1], d_my);
-                    atomicAdd(&acc[kk][2], d_qa); atomicAdd(&acc[kk][3], d_qb); atomicAdd(&acc[kk][4], d_qc);
-                    atomicAdd(&acc[kk][5], d_c0); atomicAdd(&acc[kk][6], d_c1); atomicAdd(&acc[kk][7], d_c2);
-                    atomicAdd(&acc[kk][8], d_o);
+                if (__any(contrib)) {
+                    float vals[9] = {d_mx, d_my, d_qa, d_qb, d_qc, d_c0, d_c1, d_c2, d_o};
+                    wave_sum9_to_63(vals);
+                    if (lane == 63) {
+#pragma unroll
+                        for (int f = 0; f < 9; ++f) atomicAdd(&acc[kk][f], vals[f]);
+                    }
                 }
             }
         }
@@ -498,21 +567,26 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             if (val != 0.f) {
                 const int kk = i / 9, f = i % 9;
                 unsafeAtomicAdd(&st.dgauss[(int64_t)S.gp[kk] * 12 + f], val);
+                (&acc[0][0])[i] = 0.f;
             }
-            (&acc[0][0])[i] = 0.f;
         }
         __syncthreads();
     }
-    // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma
-    const int nmap = B.n_runs < RunMaps<TS>::value ? B.n_runs : RunMaps<TS>::value;
-    for (int r = 0; r < nmap; ++r) {
-        const float dg = dgam[r][tid];
-        if (dg == 0.f) continue;
-        const unsigned long long mv = B.map[r][tid];
-        const float gam = __uint_as_float((unsigned)(mv >> 32));
-        const int e = (int)(mv & 0xFFFFFFFFull);
-        if (!(gam < 1.0f) || e < 0 || e >= B.nbl) continue;
-        const float ddx = (float)(lx - B.bix[e]) - B.bdx[e], ddy = (float)(ly - B.biy[e]) - B.bdy[e];
+    // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
+    // The arg-min is searched again over the run (first, i.e. lowest raster
+    // index, among equal minima).
+    float(&bacc)[kBoundaryLds][3] = U.bacc;
+    for (int i = tid; i < kBoundaryLds * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
+    __syncthreads();
+    const int nmap = B.n_runs < RM ? B.n_runs : RM;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const float dg = dgam[r];
+        if (r >= nmap || dg == 0.f) continue;
+        int e = -1;
+        const float gam = gamma_lds<TS>(B, r, lx, ly, &e);
+        if (e < 0 || !(gam < 1.0f)) continue;
+        const float ddx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], ddy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
         const float sg = B.bs[e];
         const float d = sqrtf(ddx * ddx + ddy * ddy);
         const float dd = dg * LN2 / sg * gam;

@@ -336,13 +336,14 @@ __device__ __forceinline__ void centre_range(double c, double r, int n, int &lo,
 template <int DEG>
 __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = pix < vt.total_px;
+    const int lane = threadIdx.x & 63;
+    int v, x, y;
+    const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
     bool fg = false, isb = false;
+    int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;  // tile rectangles
+    const ViewInfo vi = vt.v[v];
     if (act) {
-        const int v = view_of_pixel(vt, pix);
-        const ViewInfo vi = vt.v[v];
-        const int lp = pix - vi.px_off, x = lp % vi.W, y = lp / vi.W;
+        const int lp = y * vi.W + x, pix = vi.px_off + lp;
         const unsigned long long z = st.zbuf[pix];
         const int tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
         st.I_tri[pix] = tri;
@@ -464,16 +465,10 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
                                      __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
                 st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;
-                // pair counts per tile
+                // tiles reached by the Gaussian's support and by the boundary disc
                 const int TS = k.tile;
-                if (gi0 <= gi1 && gj0 <= gj1)
-                    for (int ty = gj0 / TS; ty <= gj1 / TS; ++ty)
-                        for (int tx = gi0 / TS; tx <= gi1 / TS; ++tx)
-                            atomicAdd(&st.g_count[vi.tile_off + ty * vi.tiles_x + tx], 1);
-                if (bi0 <= bi1 && bj0 <= bj1)
-                    for (int ty = bj0 / TS; ty <= bj1 / TS; ++ty)
-                        for (int tx = bi0 / TS; tx <= bi1 / TS; ++tx)
-                            atomicAdd(&st.b_count[vi.tile_off + ty * vi.tiles_x + tx], 1);
+                if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS; }
+                if (bi0 <= bi1 && bj0 <= bj1) { bt0 = bi0 / TS; bt1 = bi1 / TS; bu0 = bj0 / TS; bu1 = bj1 / TS; }
             }
             fg = true;
             isb = (flags & PF_BOUNDARY) != 0;
@@ -481,8 +476,15 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
         st.I_uv[pix] = uvo;
         st.pflags[pix] = flags;
     }
+    // pair counts per tile, one atomic per group of lanes at the same tile
+    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off, [&](int t, unsigned long long gm, bool, int leader) {
+        if (lane == leader) atomicAdd(&st.g_count[t], __popcll(gm));
+    });
+    for_tiles_grouped(bt0, bt1, bu0, bu1, vi.tiles_x, vi.tile_off, [&](int t, unsigned long long gm, bool, int leader) {
+        if (lane == leader) atomicAdd(&st.b_count[t], __popcll(gm));
+    });
     const unsigned long long mf = __ballot(fg), mb = __ballot(isb);
-    if (__lane_id() == 0) {
+    if (lane == 0) {
         if (mf) atomicAdd((unsigned long long *)&st.counters[C_FG], (unsigned long long)__popcll(mf));
         if (mb) atomicAdd((unsigned long long *)&st.counters[C_BOUNDARY], (unsigned long long)__popcll(mb));
     }
@@ -510,7 +512,7 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s) {
     {
-        dim3 grid((unsigned)((vt.total_px + 255) / 256)), block(256);
+        dim3 grid((unsigned)((vt.total_b8 + 3) / 4)), block(256);  // one wave per 8x8 block
         switch (k.degree) {
             case 1: hipLaunchKernelGGL(k_gen<1>, grid, block, 0, s, k, vt, pr, cams, st); break;
             case 2: hipLaunchKernelGGL(k_gen<2>, grid, block, 0, s, k, vt, pr, cams, st); break;

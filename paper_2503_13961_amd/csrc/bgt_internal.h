@@ -38,6 +38,7 @@ constexpr uint8_t PF_BOUNDARY = 2;  // the pixel is a boundary point
 
 struct ViewInfo {
     int32_t W, H, tiles_x, tiles_y, px_off, tile_off;
+    int32_t b8_off, b8_x;  // first 8x8 pixel block of the view, blocks per row
 };
 
 struct ViewTable {
@@ -61,6 +62,46 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, int tile) {
         if (vt.v[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Pixel of lane `lane` in global 8x8 block `blk` (waves walk 8x8 blocks so
+// that neighbouring pixels share a wave).  Returns false outside the image.
+__device__ __forceinline__ bool block8_pixel(const ViewTable &vt, int blk, int lane, int &v, int &x, int &y) {
+    int lo = 0, hi = vt.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].b8_off <= blk) lo = mid; else hi = mid - 1;
+    }
+    v = lo;
+    const ViewInfo &vi = vt.v[lo];
+    const int lb = blk - vi.b8_off;
+    x = (lb % vi.b8_x) * 8 + (lane & 7);
+    y = (lb / vi.b8_x) * 8 + (lane >> 3);
+    return blk < vt.total_b8 && x < vi.W && y < vi.H;
+}
+
+// Visit the tiles [tx0, tx1] x [ty0, ty1] of every lane's rectangle (row-major,
+// empty when tx0 > tx1); lanes at the same tile are handled together:
+// f(tile, group_mask, in_group, leader) is called by the whole wave once per
+// group.  Saves one atomic per lane on per-tile counters.
+template <typename F>
+__device__ __forceinline__ void for_tiles_grouped(int tx0, int tx1, int ty0, int ty1, int tiles_x, int tile_off,
+                                                  F &&f) {
+    int cx = tx0, cy = ty0;
+    bool alive = tx0 <= tx1 && ty0 <= ty1;
+    while (true) {
+        const unsigned long long am = __ballot(alive);
+        if (!am) break;
+        const int mine = alive ? tile_off + cy * tiles_x + cx : -1;
+        const int leader = __ffsll((long long)am) - 1;
+        const int t0 = __shfl(mine, leader, 64);
+        const bool in = alive && mine == t0;
+        const unsigned long long gm = __ballot(in);
+        f(t0, gm, in, leader);
+        if (in) {
+            if (++cx > tx1) { cx = tx0; if (++cy > ty1) alive = false; }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- constants

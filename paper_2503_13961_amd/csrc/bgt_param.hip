@@ -47,20 +47,9 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
 #pragma unroll
     for (int c = 0; c < NCP; ++c) B[c] = 0.f;
     bool act = false;
-    if (wblock < vt.total_b8) {
-        int v = 0;
-        {   // views are few; linear search over the 8x8-block prefix
-            int acc = 0;
-            for (v = 0; v < vt.n; ++v) {
-                const int nb = ((vt.v[v].W + 7) >> 3) * ((vt.v[v].H + 7) >> 3);
-                if (wblock < acc + nb) break;
-                acc += nb;
-            }
-            const ViewInfo vi = vt.v[v];
-            const int lb = wblock - acc, bxn = (vi.W + 7) >> 3;
-            const int x = (lb % bxn) * 8 + (lane & 7), y = (lb / bxn) * 8 + (lane >> 3);
-            if (x < vi.W && y < vi.H) pix = vi.px_off + y * vi.W + x;
-        }
+    {
+        int v0, x0, y0;
+        if (block8_pixel(vt, wblock, lane, v0, x0, y0)) pix = vt.v[v0].px_off + y0 * vt.v[v0].W + x0;
         if (pix >= 0 && (st.pflags[pix] & PF_VALID)) {
             const float *g = st.dgauss + (int64_t)pix * 12;
             const float dmux = g[0], dmuy = g[1], dqa = g[2], dqb = g[3], dqc = g[4];
