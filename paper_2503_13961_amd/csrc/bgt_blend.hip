@@ -63,10 +63,14 @@ struct BoundaryLds {
 template <int TS, int K>
 struct BatchLds {
     float2 m[TS * TS / 64][K];  // per-wave mean offsets
-    float4 q[K];                // conic (a, b, c), opacity
+    float4 e[K];                // conic in exponent form kE (a, 2b, c), opacity
     float4 c[K];                // colour, unused
-    int prim[K], run[K], xr[K], yr[K], gp[K];
+    int2 pr[K];                 // primitive id, run index
+    int xr[K], yr[K];
 };
+
+// -log2(e)/2: G = exp(-d^T Q d / 2) = 2^(kE d^T Q d)
+constexpr float kE = -0.5f * 1.44269504088896341f;
 
 // block-wide exclusive scan of int flags (blockDim multiple of 64)
 __device__ __forceinline__ int block_scan_excl(int x, int &total, int *ws) {
@@ -231,27 +235,40 @@ __device__ __forceinline__ void build_gamma_maps(BoundaryLds<TS, MapT> &B) {
     __syncthreads();
 }
 
+// Records of one batch slot, fetched from global memory one batch ahead of
+// their use by the loader threads (tid < K); the list entry is fetched one
+// batch earlier still, so neither load stalls the wave that issues it.
+struct SlotPrefetch {
+    float4 r0, r1, r2, r3;
+    int gp = -1;       // pixel (record index) of the records in flight
+    int gp_next = -1;  // list entry for the batch after them
+    __device__ __forceinline__ void issue(const StatePtrs &st, int gs0, int n, int base_next, int tid, int K) {
+        gp = gp_next;
+        if (gp >= 0) {
+            const float4 *rp = st.rec + (int64_t)gp * 4;
+            r0 = rp[0]; r1 = rp[1]; r2 = rp[2]; r3 = rp[3];
+        }
+        const int i2 = base_next + K + tid;
+        gp_next = (tid < K && i2 < n) ? (int)st.g_list[gs0 + i2] : -1;
+    }
+};
+
 template <int TS, int K>
-__device__ __forceinline__ void load_batch(BatchLds<TS, K> &S, const StatePtrs &st, const ViewInfo &vi, int gs0,
-                                           int i, int kk, int ox, int oy, const int *run_prim, int n_runs,
-                                           bool slow_b) {
+__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, const ViewInfo &vi, int kk,
+                                           int ox, int oy, const int *run_prim, int n_runs, bool slow_b) {
     using G = TileGeom<TS>;
-    const int gp = (int)st.g_list[gs0 + i];
-    const float4 *rp = st.rec + (int64_t)gp * 4;
-    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+    const int gp = P.gp;
     const int lp = gp - vi.px_off;
     const int x = lp % vi.W - ox, y = lp / vi.W - oy;  // tile-relative pixel of the Gaussian
 #pragma unroll
     for (int w = 0; w < G::NT / 64; ++w)
-        S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + r0.x, (float)(y - (w / G::SPR) * 8) + r0.y);
-    S.q[kk] = make_float4(r0.z, r0.w, r1.x, r2.x);
-    S.c[kk] = make_float4(r1.y, r1.z, r1.w, 0.f);
-    const int g = __float_as_int(r2.y);
-    S.prim[kk] = g;
-    S.run[kk] = slow_b ? -2 : find_run(run_prim, n_runs, g);
-    S.xr[kk] = __float_as_int(r3.x);
-    S.yr[kk] = __float_as_int(r3.y);
-    S.gp[kk] = gp;
+        S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
+    S.e[kk] = make_float4(kE * P.r0.z, 2.0f * kE * P.r0.w, kE * P.r1.x, P.r2.x);
+    S.c[kk] = make_float4(P.r1.y, P.r1.z, P.r1.w, 0.f);
+    const int g = __float_as_int(P.r2.y);
+    S.pr[kk] = make_int2(g, slow_b ? -2 : find_run(run_prim, n_runs, g));
+    S.xr[kk] = __float_as_int(P.r3.x);
+    S.yr[kk] = __float_as_int(P.r3.y);
 }
 
 // does the pixel range (packed int16 pairs) touch the 8x8 block at (x0, y0)?
@@ -334,49 +351,74 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     int last = gc;
     const float amax = k.alpha_max, tmin = k.t_min;
     // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
-    const float e_min = -0.5f * k.kappa2 * 1.44269504088896341f;
-    constexpr float kE = -0.5f * 1.44269504088896341f;
+    const float e_min = kE * k.kappa2;
+    SlotPrefetch pf;
+    pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
+    pf.issue(st, gs0, gc, 0, tid, K);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
     for (int base = 0; base < gc; base += K) {
-        if (__syncthreads_and(done ? 1 : 0)) break;
-        if (tid < K && base + tid < gc) load_batch<TS, K>(S, st, vi, gs0, base + tid, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
-        __syncthreads();
+        if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
+        pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
         const int nk = min(K, gc - base);
-        if (__all(done)) continue;
+        if (!__all(done)) {
         for (int c0 = 0; c0 < K; c0 += 64) {
             const int j = c0 + lane;
             unsigned long long mask = __ballot(j < nk && touches_block(S.xr[j], S.yr[j], wx0, wy0));
-            while (mask) {
-                const int kk = c0 + __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
-                if (done) continue;
-                const int g = S.prim[kk], r = S.run[kk];
-                if (g != h && r == -1) continue;  // w = 0: no boundary point of g near this tile
-                const float2 m = S.m[wave][kk];
-                const float4 q = S.q[kk];
-                const float dx = qx - m.x, dy = qy - m.y;
-                const float e = kE * (q.x * dx * dx + 2.0f * q.y * dx * dy + q.z * dy * dy);
-                if (e < e_min) continue;
-                float gam = 1.0f;
-                if (r >= 0) {
-                    int arg;
-                    gam = r < RunMaps<TS>::value ? __uint_as_float(B.map[r][tid]) : gamma_lds<TS>(B, r, lx, ly, &arg);
-                } else if (r == -2) {
-                    int arg;
-                    gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+            if (!mask) continue;
+            // software pipeline: the next Gaussian's LDS record is read while
+            // the current one is composited
+            int kk = c0 + __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            int2 pr = S.pr[kk];
+            float2 m = S.m[wave][kk];
+            float4 ex = S.e[kk];
+            float4 c = S.c[kk];
+            while (true) {
+                const int kn = mask ? c0 + __ffsll((long long)mask) - 1 : -1;
+                int2 pr_n = pr;
+                float2 m_n = m;
+                float4 ex_n = ex, c_n = c;
+                if (kn >= 0) {
+                    mask &= mask - 1;
+                    pr_n = S.pr[kn];
+                    m_n = S.m[wave][kn];
+                    ex_n = S.e[kn];
+                    c_n = S.c[kn];
                 }
-                const float w = g == h ? gam : 1.0f - gam;
-                if (w <= 0.0f) continue;
-                float a = q.w * w * exp2f(e);
-                a = a > amax ? amax : a;
-                const float ta = T * a;
-                const float4 c = S.c[kk];
-                C0 += ta * c.x;
-                C1 += ta * c.y;
-                C2 += ta * c.z;
-                T = T * (1.0f - a);
-                if (T < tmin) { done = true; last = base + kk + 1; }
+                const int g = pr.x, r = pr.y;
+                if (!done && (g == h || r != -1)) {  // else w = 0: no boundary point of g near this tile
+                    const float dx = qx - m.x, dy = qy - m.y;
+                    const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);
+                    if (e >= e_min) {
+                        float gam = 1.0f;
+                        if (r >= 0) {
+                            int arg;
+                            gam = r < RunMaps<TS>::value ? __uint_as_float(B.map[r][tid])
+                                                         : gamma_lds<TS>(B, r, lx, ly, &arg);
+                        } else if (r == -2) {
+                            int arg;
+                            gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                        }
+                        const float w = g == h ? gam : 1.0f - gam;
+                        if (w > 0.0f) {
+                            float a = ex.w * w * exp2f(e);
+                            a = a > amax ? amax : a;
+                            const float ta = T * a;
+                            C0 += ta * c.x;
+                            C1 += ta * c.y;
+                            C2 += ta * c.z;
+                            T = T * (1.0f - a);
+                            if (T < tmin) { done = true; last = base + kk + 1; }
+                        }
+                    }
+                }
+                if (kn < 0) break;
+                kk = kn; pr = pr_n; m = m_n; ex = ex_n; c = c_n;
             }
         }
+        }
+        __syncthreads();  // everyone is done with this batch
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
     }
     if (inside) {
         image[3 * (int64_t)pix + 0] = C0 + T * k.bg[0];
@@ -462,12 +504,16 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int nlast = max_last;
     float T = 1.0f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
     const float amax = k.alpha_max;
-    const float e_min = -0.5f * k.kappa2 * 1.44269504088896341f;
-    constexpr float kE = -0.5f * 1.44269504088896341f;
+    const float e_min = kE * k.kappa2;
     const float LN2 = 0.69314718055994531f;
+    SlotPrefetch pf;
+    pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
+    pf.issue(st, gs0, nlast, 0, tid, K);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
     for (int base = 0; base < nlast; base += K) {
-        if (tid < K && base + tid < nlast) load_batch<TS, K>(S, st, vi, gs0, base + tid, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
-        __syncthreads();
+        __syncthreads();  // publishes the staged batch
+        const int cur_gp = pf.gp;
+        pf.issue(st, gs0, nlast, base + K, tid, K);  // next batch's records, in flight during the replay
         const int nk = min(K, nlast - base);
         for (int c0 = 0; c0 < K && base + c0 < wave_last; c0 += 64) {
             const int j = c0 + lane;
@@ -479,13 +525,14 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 float d_mx = 0.f, d_my = 0.f, d_qa = 0.f, d_qb = 0.f, d_qc = 0.f, d_c0 = 0.f, d_c1 = 0.f, d_c2 = 0.f,
                       d_o = 0.f;
                 bool contrib = false;
-                const int g = S.prim[kk];
-                const int r = __builtin_amdgcn_readfirstlane(S.run[kk]);  // wave-uniform
+                const int2 prk = S.pr[kk];
+                const int g = prk.x;
+                const int r = __builtin_amdgcn_readfirstlane(prk.y);  // wave-uniform
                 if (base + kk < mylast && (g == h || r != -1)) {
                     const float2 m = S.m[wave][kk];
-                    const float4 q = S.q[kk];
+                    const float4 ex = S.e[kk];
                     const float dx = qx - m.x, dy = qy - m.y;
-                    const float e = kE * (q.x * dx * dx + 2.0f * q.y * dx * dy + q.z * dy * dy);
+                    const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
                     if (e >= e_min) {
                         float gam = 1.0f;
                         int arg = -1;
@@ -497,6 +544,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         const float w = g == h ? gam : 1.0f - gam;
                         if (w > 0.0f) {
                             contrib = true;
+                            // conic back from its exponent form
+                            const float4 q = make_float4(ex.x * (1.0f / kE), ex.y * (0.5f / kE), ex.z * (1.0f / kE), ex.w);
                             const float Gv = exp2f(e);
                             const float o = q.w;
                             const float raw = o * w * Gv;
@@ -562,19 +611,22 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();
-        for (int i = tid; i < nk * 9; i += blockDim.x) {
-            const float val = (&acc[0][0])[i];
-            if (val != 0.f) {
-                const int kk = i / 9, f = i % 9;
-                unsafeAtomicAdd(&st.dgauss[(int64_t)S.gp[kk] * 12 + f], val);
-                (&acc[0][0])[i] = 0.f;
+        if (tid < K && cur_gp >= 0) {  // each loader flushes its own slot, then stages the next batch
+#pragma unroll
+            for (int f = 0; f < 9; ++f) {
+                const float val = acc[tid][f];
+                if (val != 0.f) {
+                    unsafeAtomicAdd(&st.dgauss[(int64_t)cur_gp * 12 + f], val);
+                    acc[tid][f] = 0.f;
+                }
             }
         }
-        __syncthreads();
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (first, i.e. lowest raster
     // index, among equal minima).
+    __syncthreads();  // the loaders' last flush reads acc, which bacc overlays
     float(&bacc)[kBoundaryLds][3] = U.bacc;
     for (int i = tid; i < kBoundaryLds * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
