@@ -35,7 +35,7 @@ struct Shape {
     Consts k;
     int64_t N, NT;
     int64_t off[BGT_STATE_FIELDS];
-    int64_t wverts_off, bigsort_off;
+    int64_t wverts_off, psetup_off, bigsort_off;
 };
 
 bgt_status fail(bgt_ctx *ctx, bgt_status st, const char *msg) {
@@ -123,7 +123,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
         const int64_t wbytes = 24 * (int64_t)k.VL * k.P;
         sh.off[F_VERTS] = o;
         sh.wverts_off = align256(o + vbytes);
-        o = align256(sh.wverts_off + wbytes);
+        sh.psetup_off = align256(sh.wverts_off + wbytes);
+        o = align256(sh.psetup_off + 80 * (int64_t)k.P);
     }
     put(F_GCOUNT, 4 * NT);
     put(F_GSTART, 4 * NT);
@@ -160,6 +161,7 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.last = (int32_t *)(b + sh.off[F_LAST]);
     p.verts = (VertRec *)(b + sh.off[F_VERTS]);
     p.wverts = (double *)(b + sh.wverts_off);
+    p.psetup = (double *)(b + sh.psetup_off);
     p.g_count = (int32_t *)(b + sh.off[F_GCOUNT]);
     p.g_start = (int32_t *)(b + sh.off[F_GSTART]);
     p.g_cursor = (int32_t *)(b + sh.off[F_GCURSOR]);

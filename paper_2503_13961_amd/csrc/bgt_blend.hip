@@ -15,12 +15,18 @@
 
 namespace bgt {
 
-// runs with an LDS gamma* map (fewer for 32x32 tiles to fit the LDS budget)
+// Per tile size: runs with an LDS gamma* map and boundary points staged in
+// LDS.  The budget keeps 5-6 workgroups per CU; on the 2000-patch sphere at
+// 16 px a tile has at most 13 runs and 157 points (the 20,000-patch box: 24
+// and 251).  Tiles beyond it take the slower paths, never a wrong one.
 template <int TS>
 struct RunMaps {
-    static constexpr int value = TS >= 32 ? 4 : 16;
+    static constexpr int value = TS >= 32 ? 4 : 12;
 };
-constexpr int kBoundaryLds = 512; // boundary points staged in LDS per tile
+template <int TS>
+struct BoundaryCap {
+    static constexpr int value = TS >= 32 ? 512 : (TS >= 16 ? 256 : 128);
+};
 
 template <int TS>
 struct TileGeom {
@@ -43,10 +49,11 @@ struct TileGeom {
 // so every value depends only on the point and the pixel, never on the tile.
 template <int TS, typename MapT>
 struct BoundaryLds {
-    float bdx[kBoundaryLds], bdy[kBoundaryLds], bs[kBoundaryLds];
-    int bxy[kBoundaryLds];  // tile-relative pixel x | y << 16 (int16 each)
-    int bp[kBoundaryLds], brun[kBoundaryLds];
-    int run_prim[kBoundaryLds], run_start[kBoundaryLds + 1];
+    static constexpr int CAP = BoundaryCap<TS>::value;
+    float bdx[CAP], bdy[CAP], bs[CAP];
+    int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
+    int bp[CAP], brun[CAP];
+    int run_prim[CAP], run_start[CAP + 1];
     int wsum[33];
     int n_runs, nbl;
     MapT map[RunMaps<TS>::value][TS * TS];
@@ -104,7 +111,7 @@ __device__ __forceinline__ int block_scan_excl(int x, int &total, int *ws) {
 template <int TS, typename MapT>
 __device__ __forceinline__ void stage_boundary(BoundaryLds<TS, MapT> &B, const StatePtrs &st, int bs0, int bc,
                                                int ox, int oy, const ViewInfo &vi) {
-    const int nbl = bc < kBoundaryLds ? bc : kBoundaryLds;
+    const int nbl = bc < B.CAP ? bc : B.CAP;
     for (int e = threadIdx.x; e < nbl; e += blockDim.x) {
         const int bpix = (int)st.b_list[bs0 + e];
         const float4 r0 = st.rec[(int64_t)bpix * 4];
@@ -341,7 +348,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
     stage_boundary<TS>(B, st, bs0, bc, ox, oy, vi);
-    const bool slow_b = bc > kBoundaryLds;
+    const bool slow_b = bc > BoundaryCap<TS>::value;
     if (slow_b && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_BIGBLIST], 1ull);
     build_gamma_maps<TS>(B);
 
@@ -454,7 +461,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     };
     union TailLds {
         LoopLds loop;
-        float bacc[kBoundaryLds][3];
+        float bacc[BoundaryCap<TS>::value][3];
     };
     __shared__ TailLds U;
     __shared__ int max_last;
@@ -497,7 +504,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
     stage_boundary<TS>(B, st, bs0, bc, ox, oy, vi);  // (syncs)
-    const bool slow_b = bc > kBoundaryLds;
+    const bool slow_b = bc > BoundaryCap<TS>::value;
     build_gamma_maps<TS>(B);
 
     const int gs0 = st.g_start[t];
@@ -627,8 +634,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     // The arg-min is searched again over the run (first, i.e. lowest raster
     // index, among equal minima).
     __syncthreads();  // the loaders' last flush reads acc, which bacc overlays
-    float(&bacc)[kBoundaryLds][3] = U.bacc;
-    for (int i = tid; i < kBoundaryLds * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
+    float(&bacc)[BoundaryCap<TS>::value][3] = U.bacc;
+    for (int i = tid; i < BoundaryCap<TS>::value * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
     const int nmap = B.n_runs < RM ? B.n_runs : RM;
 #pragma unroll

@@ -139,6 +139,35 @@ hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ per-patch setup
+
+// Eq. 5 with a resolution-1 attribute map: one rotation and scale per patch.
+// psetup[p] = (Rq diag(exp(log_scale)) row-major (9), r_b^2) in FP64.
+__global__ void k_prim_setup(Consts k, PrimPtrs pr, double *psetup) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= k.P) return;
+    double q[4], qn = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
+    qn = sqrt(qn);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) q[d] /= qn;
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                          2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    double sc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sc[d] = exp((double)pr.log_scale[(int64_t)d * k.T * k.P + p]);
+    double *o = psetup + (int64_t)p * 10;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[3 * r + c] = Rq[3 * r + c] * sc[c];
+    const double rb = (double)k.r_ref / (double)pr.sharp[p];
+    o[9] = rb * rb;
+}
+
 // ------------------------------------------------------------ projection
 
 struct Cam {
@@ -373,20 +402,20 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             }
             const double qx = x + 0.5, qy = y + 0.5;
             const double d = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
-            double lam[3];
+            // screen-space barycentrics (edge functions / area), then weights lambda_k / z_k
+            double beta[3];
             if (d != 0.0) {
-                lam[0] = ((vx[2] - vx[1]) * (qy - vy[1]) - (vy[2] - vy[1]) * (qx - vx[1])) / d;
-                lam[1] = ((vx[0] - vx[2]) * (qy - vy[2]) - (vy[0] - vy[2]) * (qx - vx[2])) / d;
-                lam[2] = ((vx[1] - vx[0]) * (qy - vy[0]) - (vy[1] - vy[0]) * (qx - vx[0])) / d;
+                beta[0] = ((vx[2] - vx[1]) * (qy - vy[1]) - (vy[2] - vy[1]) * (qx - vx[1])) * viz[0];
+                beta[1] = ((vx[0] - vx[2]) * (qy - vy[2]) - (vy[0] - vy[2]) * (qx - vx[2])) * viz[1];
+                beta[2] = ((vx[1] - vx[0]) * (qy - vy[0]) - (vy[1] - vy[0]) * (qx - vx[0])) * viz[2];
             } else {
-                lam[0] = lam[1] = lam[2] = 1.0 / 3.0;
+                beta[0] = viz[0]; beta[1] = viz[1]; beta[2] = viz[2];
             }
-            double ws = 0.0, beta[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { beta[c] = lam[c] * viz[c]; ws += beta[c]; }
+            // the common factor 1/area cancels in the normalisation
+            const double iws = 1.0 / (beta[0] + beta[1] + beta[2]);
             double u = 0.0, vb = 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { u += beta[c] / ws * lu[c]; vb += beta[c] / ws * lv[c]; }
+            for (int c = 0; c < 3; ++c) { u += beta[c] * iws * lu[c]; vb += beta[c] * iws * lv[c]; }
             uvo = make_float2((float)u, (float)vb);
             // Eq. 3 (position) and Eq. 4 (diffuse colour)
             double B[NCP];
@@ -403,41 +432,32 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             double t[3];
             cam_apply(c, S, t);
             if (t[2] > (double)k.z_near) {
-                const double tz = t[2];
-                const double J00 = c.fx / tz, J02 = -c.fx * t[0] / (tz * tz);
-                const double J11 = c.fy / tz, J12 = -c.fy * t[1] / (tz * tz);
+                const double tz = t[2], iz = 1.0 / tz;
+                const double J00 = c.fx * iz, J02 = -c.fx * t[0] * iz * iz;
+                const double J11 = c.fy * iz, J12 = -c.fy * t[1] * iz * iz;
                 double Tm[6];
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
                     Tm[cc] = J00 * c.R[cc] + J02 * c.R[6 + cc];
                     Tm[3 + cc] = J11 * c.R[3 + cc] + J12 * c.R[6 + cc];
                 }
-                // Eq. 5 with a resolution-1 attribute map: one rotation and scale per patch
-                double q[4], qn = 0.0;
+                // Eq. 5 with a resolution-1 attribute map: M = Rq diag(s) of the patch;
+                // V = Tm M, Sigma2D = V V^T + low-pass
+                const double *M = st.psetup + (int64_t)p * 10;
+                double Mv[9];
 #pragma unroll
-                for (int dd = 0; dd < 4; ++dd) { q[dd] = pr.quat[(int64_t)dd * k.T * k.P + p]; qn += q[dd] * q[dd]; }
-                qn = sqrt(qn);
-#pragma unroll
-                for (int dd = 0; dd < 4; ++dd) q[dd] /= qn;
-                const double qw = q[0], qx_ = q[1], qy_ = q[2], qz = q[3];
-                const double Rq[9] = {1 - 2 * (qy_ * qy_ + qz * qz), 2 * (qx_ * qy_ - qw * qz), 2 * (qx_ * qz + qw * qy_),
-                                      2 * (qx_ * qy_ + qw * qz), 1 - 2 * (qx_ * qx_ + qz * qz), 2 * (qy_ * qz - qw * qx_),
-                                      2 * (qx_ * qz - qw * qy_), 2 * (qy_ * qz + qw * qx_), 1 - 2 * (qx_ * qx_ + qy_ * qy_)};
-                double sc[3];
-#pragma unroll
-                for (int dd = 0; dd < 3; ++dd) sc[dd] = exp((double)pr.log_scale[(int64_t)dd * k.T * k.P + p]);
-                // V = Tm Rq diag(s): Sigma2D = V V^T + low-pass
+                for (int i = 0; i < 9; ++i) Mv[i] = M[i];
                 double V0[3], V1[3];
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
-                    V0[cc] = (Tm[0] * Rq[cc] + Tm[1] * Rq[3 + cc] + Tm[2] * Rq[6 + cc]) * sc[cc];
-                    V1[cc] = (Tm[3] * Rq[cc] + Tm[4] * Rq[3 + cc] + Tm[5] * Rq[6 + cc]) * sc[cc];
+                    V0[cc] = Tm[0] * Mv[cc] + Tm[1] * Mv[3 + cc] + Tm[2] * Mv[6 + cc];
+                    V1[cc] = Tm[3] * Mv[cc] + Tm[4] * Mv[3 + cc] + Tm[5] * Mv[6 + cc];
                 }
                 const double SA = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + k.dilation;
                 const double SB = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
                 const double SC = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + k.dilation;
-                const double det = SA * SC - SB * SB;
-                const double mux = c.fx * t[0] / tz + c.cx, muy = c.fy * t[1] / tz + c.cy;
+                const double idet = 1.0 / (SA * SC - SB * SB);
+                const double mux = c.fx * t[0] * iz + c.cx, muy = c.fy * t[1] * iz + c.cy;
                 int gi0, gi1, gj0, gj1;
                 centre_range(mux, k.kappa * sqrt(SA), vi.W, gi0, gi1);
                 centre_range(muy, k.kappa * sqrt(SC), vi.H, gj0, gj1);
@@ -445,7 +465,7 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 int bi0 = 1, bi1 = 0, bj0 = 1, bj1 = 0;
                 if (bnd) {
                     // isotropic boundary Gaussian of scale r_b: r_b^2 J J^T + low-pass
-                    const double rb = (double)k.r_ref / (double)pr.sharp[p], r2 = rb * rb;
+                    const double r2 = M[9];
                     const double ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
                     const double mb = r2 * (J02 * J12);
                     const double mc = r2 * (J11 * J11 + J12 * J12) + k.dilation;
@@ -458,9 +478,9 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 }
                 flags |= PF_VALID;
                 float4 *rec = st.rec + (int64_t)pix * 4;
-                rec[0] = make_float4((float)(mux - (x + 0.5)), (float)(muy - (y + 0.5)), (float)(SC / det),
-                                     (float)(-SB / det));
-                rec[1] = make_float4((float)(SA / det), (float)col[0], (float)col[1], (float)col[2]);
+                rec[0] = make_float4((float)(mux - (x + 0.5)), (float)(muy - (y + 0.5)), (float)(SC * idet),
+                                     (float)(-SB * idet));
+                rec[1] = make_float4((float)(SA * idet), (float)col[0], (float)col[1], (float)col[2]);
                 rec[2] = make_float4(pr.opacity[p], __int_as_float(p), sigma, (float)tz);
                 rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
                                      __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
@@ -511,6 +531,7 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s) {
+    hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)((k.P + 255) / 256)), dim3(256), 0, s, k, pr, st.psetup);
     {
         dim3 grid((unsigned)((vt.total_b8 + 3) / 4)), block(256);  // one wave per 8x8 block
         switch (k.degree) {

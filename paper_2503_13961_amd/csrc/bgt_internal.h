@@ -150,6 +150,7 @@ struct StatePtrs {
     int32_t *last;
     VertRec *verts;        // [V][VL][P]
     double *wverts;        // [VL][P][3] world lattice
+    double *psetup;        // [P][10] Rq diag(s) (row-major) and r_b^2 per patch
     int32_t *g_count, *g_start, *g_cursor;
     int32_t *b_count, *b_start, *b_cursor;
     unsigned long long *g_keys, *b_keys;
