@@ -41,12 +41,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", default="auto", help="8, 16, 32 or auto (the autotuner picks tile and batch)")
+    ap.add_argument("--batch", type=int, default=64, help="Gaussians per LDS batch when --tile is given")
     ap.add_argument("--workload", default="sphere2k_16v_800")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=2, help="views in the oracle's timed sample")
+    ap.add_argument("--cpu-views", type=int, default=16, help="views in the oracle's timed sample")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the batched graph replays (for rocprofv3); prints the JSON line")
     ap.add_argument("--eager", action="store_true",
@@ -193,7 +194,7 @@ def cpu_baseline(scene, cams, nviews):
         px += W * H
     dt = time.perf_counter() - t0
     return {"value": px / dt / 1e6, "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nviews} of the 16 views ({px} px), forward + backward, FP64, OpenMP",
+            "sample": f"{nviews} of the {cams.n_views} views ({px} px), forward + backward, FP64, OpenMP",
             "seconds": round(dt, 3), "cpu": platform.processor() or platform.machine()}
 
 
@@ -214,6 +215,41 @@ def parity_check(scene, cams, images, samples=6000, seed=0):
     return worst
 
 
+def grad_parity_check(scene, cams, renderer, params, camt, wh, per_view=48, seed=1):
+    """Gradient parity at the full workload in the timed launch configuration.
+    The cotangent is an L1-loss sign pattern on `per_view` sampled pixels of
+    every view and zero elsewhere, so the oracle's backward (which skips
+    pixels with a zero cotangent) stays bounded; every parameter array is
+    compared to 1e-3 of its largest oracle entry."""
+    import torch
+    import oracle
+    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
+                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
+    rng = np.random.default_rng(seed)
+    off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
+    gi = np.zeros((int(off[-1]), 3), np.float32)
+    for v in range(cams.n_views):
+        n = int(off[v + 1] - off[v])
+        pix = off[v] + rng.choice(n, size=min(per_view, n), replace=False)
+        gi[pix] = np.sign(rng.standard_normal((len(pix), 3))).astype(np.float32) / gi.size
+    images, state = renderer.forward(scene.degree, params, camt, wh, check=True)
+    grads = renderer.backward(scene.degree, params, camt, wh, images, torch.from_numpy(gi).to(camt.device), state)
+    torch.cuda.synchronize()
+    ref = None
+    for v in range(cams.n_views):
+        W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
+        g = fr.grad(gi[off[v]:off[v + 1]].astype(np.float64))
+        ref = g if ref is None else {k: ref[k] + g[k] for k in ref}
+        del fr
+    worst = {}
+    for k, r in ref.items():
+        got = grads[k].detach().cpu().numpy().astype(np.float64).reshape(r.shape)
+        scale = np.abs(r).max()
+        worst[k] = float(np.abs(got - r).max() / scale) if scale > 0 else float(np.abs(got).max())
+    return worst
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -228,7 +264,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     scene, cams, desc = S.workload(args.workload)
-    log(f"[bench] {desc}; tile {args.tile}")
+    log(f"[bench] {desc}")
     params = scene_tensors(scene, dev)
     camt = torch.from_numpy(cams.cams).to(dev)
     wh = np.ascontiguousarray(cams.wh, dtype=np.int32)
@@ -241,7 +277,15 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {args.copy_probe_mb} MiB read + written")
         del src, dst
-    r = Renderer(0, tile=args.tile)
+    tune = None
+    if args.tile == "auto":
+        from paper_2503_13961_amd.autotune import autotune
+        tune = autotune(scene.degree, params, camt, wh, cache=False)
+        tile, batch = tune["tile"], tune["batch"]
+        log(f"[bench] autotuned tile {tile}, batch {batch} in {tune['seconds']} s: {tune['timings']}")
+    else:
+        tile, batch = int(args.tile), args.batch
+    r = Renderer(0, tile=tile, batch=batch)
     step = Step(r, scene.degree, params, camt, wh, target)
     if args.profile_run and args.eager:
         for _ in range(args.warmup + args.steps):
@@ -263,14 +307,16 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {desc}", "views": int(cams.n_views),
                       "width": int(wh[0, 0]), "height": int(wh[0, 1]), "pixels": npx,
-                      "prims": scene.num_prims, "degree": scene.degree, "tile": args.tile,
-                      "batched": True, "hipgraph": True}}
+                      "prims": scene.num_prims, "degree": scene.degree, "tile": tile, "batch": batch,
+                      "autotuned": tune is not None, "batched": True, "hipgraph": True}}
+    if tune is not None:
+        out["autotune_ms"] = {k: round(v, 4) for k, v in tune["timings"].items()}
     images_batched = step.images.detach().cpu().numpy()
     if args.profile_run:
         print(json.dumps(out), flush=True)
         return
     if not args.no_per_view:
-        pv = PerViewStep(Renderer(0, tile=args.tile), scene.degree, params, camt, wh, target)
+        pv = PerViewStep(Renderer(0, tile=tile, batch=batch), scene.degree, params, camt, wh, target)
         gpv = capture(pv)
         ms_pv = time_replays(gpv, args.steps, args.warmup)
         imgs_pv = torch.cat([s.images for s in pv.steps]).cpu().numpy()
@@ -285,7 +331,7 @@ def main():
     stages = stage_profile(step)
     out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
     log(f"[bench] stages {out['stage_ms']}")
-    ntiles = sum(((int(w) + args.tile - 1) // args.tile) * ((int(h) + args.tile - 1) // args.tile) for w, h in wh)
+    ntiles = sum(((int(w) + tile - 1) // tile) * ((int(h) + tile - 1) // tile) for w, h in wh)
     alg = algorithmic(counters, npx, ntiles, scene.num_prims, (scene.degree + 1) * (scene.degree + 2) // 2)
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
     achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
@@ -296,8 +342,12 @@ def main():
                        "boundary_px": counters[4]}
     if not args.no_parity:
         err = parity_check(scene, cams, images_batched)
-        out["parity"] = {"image_max_abs_err_sampled": err, "tolerance": 1e-4, "ok": err <= 1e-4}
-        log(f"[bench] parity: sampled image max abs err {err:.2e}")
+        gerr = grad_parity_check(scene, cams, r, params, camt, wh)
+        gmax = max(gerr.values())
+        out["parity"] = {"image_max_abs_err_sampled": err, "image_tolerance": 1e-4,
+                         "grad_max_rel_err_sampled": gmax, "grad_tolerance": 1e-3,
+                         "ok": bool(err <= 1e-4 and gmax <= 1e-3)}
+        log(f"[bench] parity: sampled image max abs err {err:.2e}; gradients {gerr}")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(scene, cams, args.cpu_views)
         out["cpu_baseline"] = cb

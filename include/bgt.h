@@ -88,7 +88,7 @@ typedef struct {
 typedef struct {
     int32_t tess_level;    /* L, sub-triangles per patch L^2, 1..8 (default 4) */
     int32_t tile;          /* blending tile side: 8, 16 or 32 (default 16) */
-    int32_t batch;         /* Gaussians staged per LDS batch: 32, 64 or 128 */
+    int32_t batch;         /* Gaussians staged per LDS batch: 32, 64 or 128, at most tile*tile */
     int32_t flags;         /* reserved, 0 */
     float z_near;          /* cull distance along the optical axis (0.2) */
     float g_min;           /* Gaussian support: G >= g_min (2^-15) */

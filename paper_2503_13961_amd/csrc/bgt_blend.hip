@@ -369,8 +369,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
         const int nk = min(K, gc - base);
         if (!__all(done)) {
         for (int c0 = 0; c0 < K; c0 += 64) {
-            const int j = c0 + lane;
-            unsigned long long mask = __ballot(j < nk && touches_block(S.xr[j], S.yr[j], wx0, wy0));
+            const int j = c0 + lane, jj = j < K ? j : K - 1;
+            unsigned long long mask = __ballot(j < nk && touches_block(S.xr[jj], S.yr[jj], wx0, wy0));
             if (!mask) continue;
             // software pipeline: the next Gaussian's LDS record is read while
             // the current one is composited
@@ -523,9 +523,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         pf.issue(st, gs0, nlast, base + K, tid, K);  // next batch's records, in flight during the replay
         const int nk = min(K, nlast - base);
         for (int c0 = 0; c0 < K && base + c0 < wave_last; c0 += 64) {
-            const int j = c0 + lane;
+            const int j = c0 + lane, jj = j < K ? j : K - 1;
             unsigned long long mask =
-                __ballot(j < nk && base + j < wave_last && touches_block(S.xr[j], S.yr[j], wx0, wy0));
+                __ballot(j < nk && base + j < wave_last && touches_block(S.xr[jj], S.yr[jj], wx0, wy0));
             while (mask) {
                 const int kk = c0 + __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
@@ -679,23 +679,25 @@ static hipError_t launch_bwd_t(const Consts &k, const ViewTable &vt, const State
     return hipGetLastError();
 }
 
+// (tile, batch) pairs with a kernel; a batch is loaded by one thread per
+// slot, so it cannot exceed the tile's pixel count
+#define BGT_BLEND_CONFIGS(X) X(8, 32) X(8, 64) X(16, 32) X(16, 64) X(16, 128) X(32, 32) X(32, 64) X(32, 128)
+
 hipError_t launch_blend_fwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, float *image, hipStream_t s) {
-    switch (k.tile) {
-        case 8: return launch_fwd_t<8, 64>(k, vt, st, image, s);
-        case 16: return launch_fwd_t<16, 64>(k, vt, st, image, s);
-        case 32: return launch_fwd_t<32, 64>(k, vt, st, image, s);
-        default: return hipErrorInvalidValue;
-    }
+#define BGT_CASE(TS, K) \
+    if (k.tile == TS && k.batch == K) return launch_fwd_t<TS, K>(k, vt, st, image, s);
+    BGT_BLEND_CONFIGS(BGT_CASE)
+#undef BGT_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_blend_bwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, const float *image,
                             const float *grad_image, hipStream_t s) {
-    switch (k.tile) {
-        case 8: return launch_bwd_t<8, 64>(k, vt, st, image, grad_image, s);
-        case 16: return launch_bwd_t<16, 64>(k, vt, st, image, grad_image, s);
-        case 32: return launch_bwd_t<32, 64>(k, vt, st, image, grad_image, s);
-        default: return hipErrorInvalidValue;
-    }
+#define BGT_CASE(TS, K) \
+    if (k.tile == TS && k.batch == K) return launch_bwd_t<TS, K>(k, vt, st, image, grad_image, s);
+    BGT_BLEND_CONFIGS(BGT_CASE)
+#undef BGT_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace bgt

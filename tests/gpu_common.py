@@ -23,8 +23,9 @@ def oracle_config(tile=16, L=4, bg=(0.0, 0.0, 0.0), **kw):
     return oracle.Config(**d)
 
 
-def run_gpu(scene, cams, tile=16, L=4, bg=(0.0, 0.0, 0.0), grad_images=None, renderer=None, **cfg):
-    """Forward (and optionally backward) through the C ABI; returns host arrays."""
+def run_gpu(scene, cams, tile=16, L=4, bg=(0.0, 0.0, 0.0), grad_images=None, renderer=None, lean=False, **cfg):
+    """Forward (and optionally backward) through the C ABI; returns host arrays
+    (with lean=True only the images, index map and pixel flags of the state)."""
     import torch
     from paper_2503_13961_amd.render import Renderer, scene_tensors
     dev = torch.device("cuda", 0)
@@ -35,24 +36,24 @@ def run_gpu(scene, cams, tile=16, L=4, bg=(0.0, 0.0, 0.0), grad_images=None, ren
     images, state = r.forward(scene.degree, params, camt, wh)
     torch.cuda.synchronize()
     lay = r.layout(scene.degree, params, camt, wh)
-    st = state.cpu().numpy()
     N = cams.num_pixels
 
-    def sec(name, dtype, count):
+    def sec(name, dtype, count):  # one state section, copied to the host
         o = lay[name]
-        return st[o:o + np.dtype(dtype).itemsize * count].view(dtype)
+        return state[o:o + np.dtype(dtype).itemsize * count].cpu().numpy().view(dtype)
 
     ntiles = sum(((int(w) + tile - 1) // tile) * ((int(h) + tile - 1) // tile) for w, h in cams.wh)
-    out = dict(images=images.cpu().numpy().astype(np.float64), I_tri=sec("I_tri", np.int32, N).copy(),
-               I_uv=sec("I_uv", np.float32, 2 * N).reshape(N, 2).copy(),
-               pflags=sec("pflags", np.uint8, N).copy(), rec=sec("rec", np.float32, 16 * N).reshape(N, 16).copy(),
-               T_final=sec("T_final", np.float32, N).copy(), last=sec("last", np.int32, N).copy(),
-               g_count=sec("g_count", np.int32, ntiles).copy(), g_start=sec("g_start", np.int32, ntiles).copy(),
-               b_count=sec("b_count", np.int32, ntiles).copy(), b_start=sec("b_start", np.int32, ntiles).copy())
-    gtot = int(out["g_start"][-1] + out["g_count"][-1]) if ntiles else 0
-    btot = int(out["b_start"][-1] + out["b_count"][-1]) if ntiles else 0
-    out["g_list"] = sec("g_list", np.uint32, gtot).astype(np.int64)
-    out["b_list"] = sec("b_list", np.uint32, btot).astype(np.int64)
+    out = dict(images=images.cpu().numpy().astype(np.float64), I_tri=sec("I_tri", np.int32, N),
+               pflags=sec("pflags", np.uint8, N))
+    if not lean:
+        out.update(I_uv=sec("I_uv", np.float32, 2 * N).reshape(N, 2), rec=sec("rec", np.float32, 16 * N).reshape(N, 16),
+                   T_final=sec("T_final", np.float32, N), last=sec("last", np.int32, N),
+                   g_count=sec("g_count", np.int32, ntiles), g_start=sec("g_start", np.int32, ntiles),
+                   b_count=sec("b_count", np.int32, ntiles), b_start=sec("b_start", np.int32, ntiles))
+        gtot = int(out["g_start"][-1] + out["g_count"][-1]) if ntiles else 0
+        btot = int(out["b_start"][-1] + out["b_count"][-1]) if ntiles else 0
+        out["g_list"] = sec("g_list", np.uint32, gtot).astype(np.int64)
+        out["b_list"] = sec("b_list", np.uint32, btot).astype(np.int64)
     status, counters = r.query(state)
     out["counters"] = counters
     out["status"] = status

@@ -35,6 +35,10 @@ def test_default_config_is_valid_and_checks_reject_bad_values():
                        ("alpha_max", 1.0), ("g_min", 0.0), ("z_near", 0.0), ("pair_factor", 0.0)):
         assert N.bgt_validate_config(N.bgt_default_config(**{field: bad})) == N.BGT_E_INVALID, field
     assert N.bgt_validate_config(N.bgt_default_config(bg=(0, float("nan"), 0))) == N.BGT_E_INVALID
+    for tile, batch in ((8, 32), (8, 64), (16, 128), (32, 128)):
+        assert N.bgt_validate_config(N.bgt_default_config(tile=tile, batch=batch)) == N.BGT_OK
+    # one loader thread per batch slot: an 8-px tile has 64
+    assert N.bgt_validate_config(N.bgt_default_config(tile=8, batch=128)) == N.BGT_E_INVALID
 
 
 def test_prims_and_views_validation():
