@@ -1,44 +1,58 @@
 // Discontinuity-aware alpha blending (Sec. 3.2, Eq. 6-8) and its backward
 // pass (Supplementary Sec. C) on gfx950.
 //
-// One workgroup renders one TSxTS tile; each wave owns an 8x8 pixel block.
-// The tile's boundary points (sorted by primitive id) are staged in LDS and
-// split into runs of equal id.  For every run r the block builds
+// One workgroup renders one TSxTS tile; each wave owns an 8x8 pixel block
+// and each 16-lane row of a wave a 4x4 sub-block.  The tile's boundary
+// points (sorted by primitive id) are staged in LDS and split into runs of
+// equal id.  For every run r the block builds
 //     gamma*_r(q) = min over the run's points b of min(2^(|q-b|/sigma_b - 1), 1)
 // for all pixels q of the tile by a scatter-min from each point over the
 // pixels of its disc (LDS atomics), so the blend loop reads w from LDS
 // instead of searching boundary points per (pixel, Gaussian) pair; a
 // Gaussian of primitive g finds its run by binary search over the run ids.
-// Gaussians are then composited front to back in LDS-staged batches; a wave
-// skips any Gaussian whose pixel range misses its 8x8 block.
+// Gaussians are then composited front to back in LDS-staged batches.  A
+// ballot per sub-block marks the batch entries whose pixel range touches it,
+// and each row walks its own mask, so the four rows of a wave composite four
+// (possibly different) Gaussians per step; a Gaussian that misses a
+// sub-block costs that sub-block nothing.
 #include "bgt_internal.h"
 
 namespace bgt {
 
-// Per tile size: runs with an LDS gamma* map and boundary points staged in
-// LDS.  The budget keeps 5-6 workgroups per CU; on the 2000-patch sphere at
-// 16 px a tile has at most 13 runs and 157 points (the 20,000-patch box: 24
-// and 251).  Tiles beyond it take the slower paths, never a wrong one.
+// Runs with an LDS gamma* map per tile (forward, backward) and boundary
+// points staged in LDS.  The budget keeps 5-6 workgroups per CU at 16 px; on
+// the 2000-patch sphere at 16 px a tile has at most 13 runs (mean 4.4) and
+// 157 points (the 20,000-patch box: 24 and 251).  Runs and tiles beyond it
+// take the slower paths, never a wrong one.  The backward also keeps a
+// dl/dgamma* sum per mapped (run, pixel), so it maps fewer runs.
 template <int TS>
-struct RunMaps {
-    static constexpr int value = TS >= 32 ? 4 : 12;
+struct RunMapsFwd {
+    static constexpr int value = 12;
+};
+template <int TS>
+struct RunMapsBwd {
+    static constexpr int value = 12;
 };
 template <int TS>
 struct BoundaryCap {
     static constexpr int value = TS >= 32 ? 512 : (TS >= 16 ? 256 : 128);
 };
 
+// Thread layout: wave w owns the 8x8 block (w % SPR, w / SPR); lane l of it
+// the pixel (4 (q & 1) + (i & 3), 4 (q >> 1) + (i >> 2)) of that block, with
+// q = l / 16 its row (4x4 sub-block) and i = l % 16.
 template <int TS>
 struct TileGeom {
     static constexpr int NT = TS * TS;
-    static constexpr int SPR = TS / 8;  // 8x8 sub-blocks per row
+    static constexpr int SPR = TS / 8;  // 8x8 blocks per tile row
     __device__ static __forceinline__ void local_xy(int tid, int &lx, int &ly) {
-        const int wave = tid >> 6, lane = tid & 63;
-        lx = (wave % SPR) * 8 + (lane & 7);
-        ly = (wave / SPR) * 8 + (lane >> 3);
+        const int wave = tid >> 6, q = (tid >> 4) & 3, i = tid & 15;
+        lx = (wave % SPR) * 8 + (q & 1) * 4 + (i & 3);
+        ly = (wave / SPR) * 8 + (q >> 1) * 4 + (i >> 2);
     }
     __device__ static __forceinline__ int tid_of(int lx, int ly) {
-        return ((ly >> 3) * SPR + (lx >> 3)) * 64 + (ly & 7) * 8 + (lx & 7);
+        const int bx = lx & 7, by = ly & 7;
+        return ((ly >> 3) * SPR + (lx >> 3)) * 64 + ((by >> 2) * 2 + (bx >> 2)) * 16 + (by & 3) * 4 + (bx & 3);
     }
 };
 
@@ -47,16 +61,17 @@ struct TileGeom {
 // (bdx, bdy) of its projected position from that pixel's centre; distances
 // to pixel (x, y) are (x - bix) - bdx etc., an exact integer minus one float,
 // so every value depends only on the point and the pixel, never on the tile.
-template <int TS, typename MapT>
+template <int TS, int RM>
 struct BoundaryLds {
     static constexpr int CAP = BoundaryCap<TS>::value;
+    static constexpr int NMAP = RM;
     float bdx[CAP], bdy[CAP], bs[CAP];
     int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
     int bp[CAP], brun[CAP];
     int run_prim[CAP], run_start[CAP + 1];
     int wsum[33];
     int n_runs, nbl;
-    MapT map[RunMaps<TS>::value][TS * TS];
+    unsigned map[RM][TS * TS];  // gamma* bits per (run, pixel in thread order)
 };
 
 // A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
@@ -78,6 +93,12 @@ struct BatchLds {
 
 // -log2(e)/2: G = exp(-d^T Q d / 2) = 2^(kE d^T Q d)
 constexpr float kE = -0.5f * 1.44269504088896341f;
+
+// 2^e for the support exponent e in [log2(g_min), 0]: the hardware exp2
+// (no denormal range reduction is needed there).  Forward and backward use
+// this one function, so the backward's replay reproduces the forward's
+// transmittance bit for bit.
+__device__ __forceinline__ float support_exp2(float e) { return __builtin_amdgcn_exp2f(e); }
 
 // block-wide exclusive scan of int flags (blockDim multiple of 64)
 __device__ __forceinline__ int block_scan_excl(int x, int &total, int *ws) {
@@ -108,8 +129,8 @@ __device__ __forceinline__ int block_scan_excl(int x, int &total, int *ws) {
 }
 
 // Stage the tile's boundary points and find the runs of equal primitive id.
-template <int TS, typename MapT>
-__device__ __forceinline__ void stage_boundary(BoundaryLds<TS, MapT> &B, const StatePtrs &st, int bs0, int bc,
+template <typename BL>
+__device__ __forceinline__ void stage_boundary(BL &B, const StatePtrs &st, int bs0, int bc,
                                                int ox, int oy, const ViewInfo &vi) {
     const int nbl = bc < B.CAP ? bc : B.CAP;
     for (int e = threadIdx.x; e < nbl; e += blockDim.x) {
@@ -166,8 +187,8 @@ __device__ __forceinline__ float gamma_fn(float d, float sigma) {
 }
 
 // gamma* from the LDS points of run r (runs without a map); *arg = entry
-template <int TS, typename MapT>
-__device__ __forceinline__ float gamma_lds(const BoundaryLds<TS, MapT> &B, int r, int lx, int ly, int *arg) {
+template <typename BL>
+__device__ __forceinline__ float gamma_lds(const BL &B, int r, int lx, int ly, int *arg) {
     float best = 1.0f;
     *arg = -1;
     for (int e = B.run_start[r]; e < B.run_start[r + 1]; ++e) {
@@ -203,20 +224,17 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
     return best;
 }
 
-// Scatter-min of every staged point over the pixels of its disc.
-// MapT = unsigned (gamma bits) or unsigned long long (gamma bits << 32 | entry).
-template <int TS, typename MapT>
-__device__ __forceinline__ void build_gamma_maps(BoundaryLds<TS, MapT> &B) {
+// Scatter-min of every staged point over the pixels of its disc, into the
+// maps of the first B.NMAP runs (gamma bits compare as unsigned integers).
+template <int TS, typename BL>
+__device__ __forceinline__ void build_gamma_maps(BL &B) {
     using G = TileGeom<TS>;
-    const int nmap = B.n_runs < RunMaps<TS>::value ? B.n_runs : RunMaps<TS>::value;
-    for (int i = threadIdx.x; i < nmap * G::NT; i += blockDim.x) {
-        if (sizeof(MapT) == 4) B.map[i / G::NT][i % G::NT] = (MapT)0x3F800000u;
-        else B.map[i / G::NT][i % G::NT] = (MapT)(0x3F800000ull << 32) | (MapT)0xFFFFFFFFull;
-    }
+    const int nmap = B.n_runs < B.NMAP ? B.n_runs : B.NMAP;
+    for (int i = threadIdx.x; i < nmap * G::NT; i += blockDim.x) B.map[i / G::NT][i % G::NT] = 0x3F800000u;
     __syncthreads();
     for (int e = threadIdx.x; e < B.nbl; e += blockDim.x) {
         const int r = B.brun[e];
-        if (r >= RunMaps<TS>::value) continue;
+        if (r >= B.NMAP) continue;
         const int bix = lo16(B.bxy[e]), biy = hi16(B.bxy[e]);
         const float bdx = B.bdx[e], bdy = B.bdy[e], sg = B.bs[e];
         const float rf = sg + fabsf(bdx) + fabsf(bdy);
@@ -229,13 +247,7 @@ __device__ __forceinline__ void build_gamma_maps(BoundaryLds<TS, MapT> &B) {
                 const float d = bdist(dx, dy);
                 if (d < sg) {
                     const float g = gamma_fn(d, sg);
-                    if (g < 1.0f) {
-                        if (sizeof(MapT) == 4)
-                            atomicMin((unsigned *)&B.map[r][G::tid_of(x, y)], __float_as_uint(g));
-                        else
-                            atomicMin((unsigned long long *)&B.map[r][G::tid_of(x, y)],
-                                      ((unsigned long long)__float_as_uint(g) << 32) | (unsigned long long)e);
-                    }
+                    if (g < 1.0f) atomicMin(&B.map[r][G::tid_of(x, y)], __float_as_uint(g));
                 }
             }
     }
@@ -273,19 +285,48 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetc
     S.e[kk] = make_float4(kE * P.r0.z, 2.0f * kE * P.r0.w, kE * P.r1.x, P.r2.x);
     S.c[kk] = make_float4(P.r1.y, P.r1.z, P.r1.w, 0.f);
     const int g = __float_as_int(P.r2.y);
-    S.pr[kk] = make_int2(g, slow_b ? -2 : find_run(run_prim, n_runs, g));
+    // a tile whose boundary list overflowed the LDS stage has its last staged
+    // run cut short (n_runs counts complete runs only): a primitive not among
+    // them is searched in global memory
+    int r = find_run(run_prim, n_runs, g);
+    if (r < 0 && slow_b) r = -2;
+    S.pr[kk] = make_int2(g, r);
     S.xr[kk] = __float_as_int(P.r3.x);
     S.yr[kk] = __float_as_int(P.r3.y);
 }
 
-// does the pixel range (packed int16 pairs) touch the 8x8 block at (x0, y0)?
-__device__ __forceinline__ bool touches_block(int xr, int yr, int x0, int y0) {
-    return !(hi16(xr) < x0 || lo16(xr) > x0 + 7 || hi16(yr) < y0 || lo16(yr) > y0 + 7);
+// does the pixel range (packed int16 pairs) touch the 4x4 sub-block at (x0, y0)?
+__device__ __forceinline__ bool touches4(int xr, int yr, int x0, int y0) {
+    return !(hi16(xr) < x0 || lo16(xr) > x0 + 3 || hi16(yr) < y0 || lo16(yr) > y0 + 3);
 }
 
-// Nine sums over the wave at once, step-major, so that consecutive DPP adds
-// are independent (no hazard stalls between the steps of one sum).
-__device__ __forceinline__ void wave_sum9_to_63(float *v);
+// Which of the batch entries [c0, c0 + 64) (below n) touch this lane's 4x4
+// sub-block: one ballot per sub-block of the wave's 8x8 block at (wx0, wy0),
+// each lane keeping its own row's.
+template <int K>
+__device__ __forceinline__ unsigned long long row_mask(const int *xr, const int *yr, int c0, int n, int lane, int wx0,
+                                                       int wy0) {
+    const int j = c0 + lane, jj = j < K ? j : K - 1;
+    const bool in = j < n;
+    const int a = xr[jj], b = yr[jj];
+    const unsigned long long m0 = __ballot(in && touches4(a, b, wx0, wy0));
+    const unsigned long long m1 = __ballot(in && touches4(a, b, wx0 + 4, wy0));
+    const unsigned long long m2 = __ballot(in && touches4(a, b, wx0, wy0 + 4));
+    const unsigned long long m3 = __ballot(in && touches4(a, b, wx0 + 4, wy0 + 4));
+    const int q = lane >> 4;
+    return q == 0 ? m0 : (q == 1 ? m1 : (q == 2 ? m2 : m3));
+}
+
+// index of the lowest set bit of m; 0 when m is 0, so that a row with
+// nothing left reads the first entry of the half batch (always a staged,
+// finite record, which its lanes then ignore)
+__device__ __forceinline__ int low_bit(unsigned m) { return m ? __builtin_ctz(m) : 0; }
+
+// do all 16 lanes of this lane's row have the flag set?
+__device__ __forceinline__ bool row_all(bool f, int lane) {
+    return ((__ballot(f) >> (lane & 48)) & 0xFFFFull) == 0xFFFFull;
+}
+
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -293,32 +334,30 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
 
-// Sum over the 64 lanes with DPP: row shifts leave each 16-lane row's sum in
-// its lane 15, then two row broadcasts add rows 0-2 into lane 63.  Only lane
-// 63's result is meaningful (the other lanes hold partial sums).
-__device__ __forceinline__ float wave_sum_to_63(float v) {
-    v += dpp_f<0x111, 0xF>(v);  // row_shr:1
-    v += dpp_f<0x112, 0xF>(v);  // row_shr:2
-    v += dpp_f<0x114, 0xF>(v);  // row_shr:4
-    v += dpp_f<0x118, 0xF>(v);  // row_shr:8
-    v += dpp_f<0x142, 0xF>(v);  // row_bcast:15: lane 63 += lane 47 (row 2)
-    v += dpp_f<0x143, 0xF>(v);  // row_bcast:31: lane 63 += lane 31 (rows 0 + 1)
-    return v;
-}
-
+// Nine DPP adds of one step, step-major, so that consecutive adds are
+// independent (no hazard stalls between the steps of one sum).
 template <int CTRL>
 __device__ __forceinline__ void dpp_step9(float *v) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) v[i] += dpp_f<CTRL, 0xF>(v[i]);
 }
 
+// Nine sums over the whole wave: the row sums, then row 2 into row 3 and rows
+// 0 + 1 into row 3 (row broadcasts 15 and 31); lane 63 ends with the totals.
+__device__ __forceinline__ void row_sum9_to_15(float *v);
 __device__ __forceinline__ void wave_sum9_to_63(float *v) {
+    row_sum9_to_15(v);
+    dpp_step9<0x142>(v);  // row_bcast:15
+    dpp_step9<0x143>(v);  // row_bcast:31
+}
+
+// Nine sums over each 16-lane row at once (row shifts 1, 2, 4, 8): lane 15
+// of every row ends with its row's totals.
+__device__ __forceinline__ void row_sum9_to_15(float *v) {
     dpp_step9<0x111>(v);  // row_shr:1
     dpp_step9<0x112>(v);  // row_shr:2
     dpp_step9<0x114>(v);  // row_shr:4
     dpp_step9<0x118>(v);  // row_shr:8
-    dpp_step9<0x142>(v);  // row_bcast:15
-    dpp_step9<0x143>(v);  // row_bcast:31
 }
 
 // ------------------------------------------------------------ forward
@@ -326,7 +365,9 @@ __device__ __forceinline__ void wave_sum9_to_63(float *v) {
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, StatePtrs st, float *image) {
     using G = TileGeom<TS>;
-    __shared__ BoundaryLds<TS, unsigned> B;
+    using BL = BoundaryLds<TS, RunMapsFwd<TS>::value>;
+    constexpr int RM = BL::NMAP;
+    __shared__ BL B;
     __shared__ BatchLds<TS, K> S;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int v = view_of_tile(vt, t);
@@ -347,9 +388,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
-    stage_boundary<TS>(B, st, bs0, bc, ox, oy, vi);
+    stage_boundary(B, st, bs0, bc, ox, oy, vi);
     const bool slow_b = bc > BoundaryCap<TS>::value;
     if (slow_b && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_BIGBLIST], 1ull);
+    const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     build_gamma_maps<TS>(B);
 
     const int gs0 = st.g_start[t], gc = st.g_count[t];
@@ -362,70 +404,59 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, gc, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
         pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
         const int nk = min(K, gc - base);
         if (!__all(done)) {
-        for (int c0 = 0; c0 < K; c0 += 64) {
-            const int j = c0 + lane, jj = j < K ? j : K - 1;
-            unsigned long long mask = __ballot(j < nk && touches_block(S.xr[jj], S.yr[jj], wx0, wy0));
-            if (!mask) continue;
-            // software pipeline: the next Gaussian's LDS record is read while
-            // the current one is composited
-            int kk = c0 + __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            int2 pr = S.pr[kk];
-            float2 m = S.m[wave][kk];
-            float4 ex = S.e[kk];
-            float4 c = S.c[kk];
-            while (true) {
-                const int kn = mask ? c0 + __ffsll((long long)mask) - 1 : -1;
-                int2 pr_n = pr;
-                float2 m_n = m;
-                float4 ex_n = ex, c_n = c;
-                if (kn >= 0) {
-                    mask &= mask - 1;
-                    pr_n = S.pr[kn];
-                    m_n = S.m[wave][kn];
-                    ex_n = S.e[kn];
-                    c_n = S.c[kn];
-                }
-                const int g = pr.x, r = pr.y;
-                if (!done && (g == h || r != -1)) {  // else w = 0: no boundary point of g near this tile
-                    const float dx = qx - m.x, dy = qy - m.y;
-                    const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);
-                    if (e >= e_min) {
-                        float gam = 1.0f;
-                        if (r >= 0) {
+            for (int c0 = 0; c0 < nk; c0 += 64) {
+                unsigned long long mine = row_mask<K>(S.xr, S.yr, c0, nk, lane, wx0, wy0);
+                if (row_all(done, lane)) mine = 0;  // this row has stopped
+                for (int hb = 0; hb < 64 && c0 + hb < nk; hb += 32) {
+                    unsigned mm = (unsigned)(mine >> hb);
+                    while (__any(mm != 0u)) {
+                        // each row composites its own next entry: branch-free per
+                        // lane, a lane that does not composite it takes alpha = 0,
+                        // which leaves T and C bit-identical
+                        const bool act = mm != 0u;
+                        const int kk = c0 + hb + low_bit(mm);
+                        mm &= mm - 1u;
+                        const int2 pr = S.pr[kk];
+                        const float2 m = S.m[wave][kk];
+                        const float4 ex = S.e[kk];
+                        const float4 c = S.c[kk];
+                        const int g = pr.x, r = pr.y;  // uniform within the row
+                        const bool own = g == h;
+                        const float dx = qx - m.x, dy = qy - m.y;
+                        const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);
+                        // w = 0 without a boundary point of g near this tile, or outside the support
+                        bool live = act && !done && (own || r != -1) && e >= e_min;
+                        const bool mapped = r >= 0 && r < RM;
+                        float gam = __uint_as_float(B.map[min(max(r, 0), RM - 1)][tid]);
+                        gam = mapped ? gam : 1.0f;
+                        if (__any(live && r != -1 && !mapped)) {  // rare: runs without a map, big lists
                             int arg;
-                            gam = r < RunMaps<TS>::value ? __uint_as_float(B.map[r][tid])
-                                                         : gamma_lds<TS>(B, r, lx, ly, &arg);
-                        } else if (r == -2) {
-                            int arg;
-                            gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                            if (live && r >= RM) gam = gamma_lds(B, r, lx, ly, &arg);
+                            else if (live && r == -2) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
                         }
-                        const float w = g == h ? gam : 1.0f - gam;
-                        if (w > 0.0f) {
-                            float a = ex.w * w * exp2f(e);
-                            a = a > amax ? amax : a;
-                            const float ta = T * a;
-                            C0 += ta * c.x;
-                            C1 += ta * c.y;
-                            C2 += ta * c.z;
-                            T = T * (1.0f - a);
-                            if (T < tmin) { done = true; last = base + kk + 1; }
-                        }
+                        const float w = own ? gam : 1.0f - gam;
+                        live = live && w > 0.0f;
+                        float a = ex.w * w * support_exp2(e);
+                        a = a > amax ? amax : a;
+                        a = live ? a : 0.0f;
+                        const float ta = T * a;
+                        C0 += ta * c.x;
+                        C1 += ta * c.y;
+                        C2 += ta * c.z;
+                        T = T * (1.0f - a);
+                        if (live && T < tmin) { done = true; last = base + kk + 1; }
                     }
                 }
-                if (kn < 0) break;
-                kk = kn; pr = pr_n; m = m_n; ex = ex_n; c = c_n;
             }
         }
-        }
         __syncthreads();  // everyone is done with this batch
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     if (inside) {
         image[3 * (int64_t)pix + 0] = C0 + T * k.bg[0];
@@ -443,33 +474,39 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 // forward colour minus the running prefix, and
 //   dl/dc_i = T_i a_i dl/dC,  dl/da_i = dl/dC . (T_i c_i - S_i / (1 - a_i)),
 //   dl/dw = dl/da a / w (Supplementary Sec. C), G = exp(-d^T Q d / 2).
-// Per Gaussian the 9 gradient values are summed over the wave with DPP and
-// over the waves in LDS, then added to global memory once per tile.  The
+// Per Gaussian the 9 gradient values are summed over each row with DPP and
+// over rows and waves in LDS, then added to global memory once per tile.  The
 // boundary terms accumulate per (run, pixel) and go to the minimising
 // boundary point at the end of the tile.
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
     using G = TileGeom<TS>;
-    constexpr int RM = RunMaps<TS>::value;
-    __shared__ BoundaryLds<TS, unsigned> B;
+    using BL = BoundaryLds<TS, RunMapsBwd<TS>::value>;
+    constexpr int RM = BL::NMAP;
+    __shared__ BL B;
     // the batch stage and its gradient sums are dead once the list is done;
     // the per-point boundary sums reuse their space
+    // per-row gradient sums of the staged entries: the rows of a wave walk
+    // different entries, and one LDS add instruction from the four row
+    // leaders then never has two lanes on one address (a stride of K*9+1
+    // words also spreads them over the banks)
+    constexpr int AST = K * 9 + 1;
     struct LoopLds {
         BatchLds<TS, K> S;
-        float acc[K][9];
+        float acc[K * 9];
     };
     union TailLds {
         LoopLds loop;
         float bacc[BoundaryCap<TS>::value][3];
     };
     __shared__ TailLds U;
+    float dgr[RM];  // sums of dl/dgamma* per mapped run at this pixel (uniform index: indexed registers)
+#pragma unroll
+    for (int i = 0; i < RM; ++i) dgr[i] = 0.f;
     __shared__ int max_last;
     BatchLds<TS, K> &S = U.loop.S;
-    float(&acc)[K][9] = U.loop.acc;
-    float dgam[RM];  // per-run sums of dl/dgamma* at this pixel (registers, uniform index)
-#pragma unroll
-    for (int i = 0; i < RM; ++i) dgam[i] = 0.f;
+    float *acc = U.loop.acc;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
@@ -495,7 +532,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     if (tid == 0) max_last = 0;
-    for (int i = tid; i < K * 9; i += blockDim.x) (&acc[0][0])[i] = 0.f;
+    for (int i = tid; i < K * 9; i += blockDim.x) acc[i] = 0.f;
     __syncthreads();
     atomicMax(&max_last, mylast);
     int wave_last = mylast;  // last list entry any lane of this wave replays
@@ -503,8 +540,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     for (int o = 32; o >= 1; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
-    stage_boundary<TS>(B, st, bs0, bc, ox, oy, vi);  // (syncs)
+    stage_boundary(B, st, bs0, bc, ox, oy, vi);  // (syncs)
     const bool slow_b = bc > BoundaryCap<TS>::value;
+    const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     build_gamma_maps<TS>(B);
 
     const int gs0 = st.g_start[t];
@@ -516,104 +554,97 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, nlast, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
         const int cur_gp = pf.gp;
         pf.issue(st, gs0, nlast, base + K, tid, K);  // next batch's records, in flight during the replay
-        const int nk = min(K, nlast - base);
-        for (int c0 = 0; c0 < K && base + c0 < wave_last; c0 += 64) {
+        const int nkw = min(min(K, nlast - base), wave_last - base);  // entries this wave replays
+        for (int c0 = 0; c0 < nkw; c0 += 64) {
             const int j = c0 + lane, jj = j < K ? j : K - 1;
-            unsigned long long mask =
-                __ballot(j < nk && base + j < wave_last && touches_block(S.xr[jj], S.yr[jj], wx0, wy0));
+            unsigned long long mask = __ballot(j < nkw && !(hi16(S.xr[jj]) < wx0 || lo16(S.xr[jj]) > wx0 + 7 ||
+                                                             hi16(S.yr[jj]) < wy0 || lo16(S.yr[jj]) > wy0 + 7));
             while (mask) {
-                const int kk = c0 + __ffsll((long long)mask) - 1;
+                const int kk = c0 + __ffsll((long long)mask) - 1;  // wave-uniform
                 mask &= mask - 1;
-                float d_mx = 0.f, d_my = 0.f, d_qa = 0.f, d_qb = 0.f, d_qc = 0.f, d_c0 = 0.f, d_c1 = 0.f, d_c2 = 0.f,
-                      d_o = 0.f;
-                bool contrib = false;
                 const int2 prk = S.pr[kk];
                 const int g = prk.x;
-                const int r = __builtin_amdgcn_readfirstlane(prk.y);  // wave-uniform
-                if (base + kk < mylast && (g == h || r != -1)) {
-                    const float2 m = S.m[wave][kk];
-                    const float4 ex = S.e[kk];
-                    const float dx = qx - m.x, dy = qy - m.y;
-                    const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
-                    if (e >= e_min) {
-                        float gam = 1.0f;
-                        int arg = -1;
+                const int r = __builtin_amdgcn_readfirstlane(prk.y);
+                const float2 m = S.m[wave][kk];
+                const float4 ex = S.e[kk];
+                const float4 c = S.c[kk];
+                const bool own = g == h;
+                const float dx = qx - m.x, dy = qy - m.y;
+                const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
+                bool live = base + kk < mylast && (own || r != -1) && e >= e_min;
+                const bool mapped = r >= 0 && r < RM;
+                float gam = 1.0f;
+                int arg = -1;
+                if (mapped) {
+                    gam = __uint_as_float(B.map[r][tid]);
+                } else if (r >= 0) {
+                    if (live) gam = gamma_lds(B, r, lx, ly, &arg);
+                } else if (r == -2) {
+                    if (live) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                }
+                const float w = own ? gam : 1.0f - gam;
+                live = live && w > 0.0f;
+                if (!__any(live)) continue;
+                const float o = ex.w;
+                const float Gv = support_exp2(e);
+                const float raw = o * w * Gv;
+                const bool clamped = raw > amax;
+                float a = clamped ? amax : raw;
+                a = live ? a : 0.0f;
+                const float ta = T * a;
+                const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
+                P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+                const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
+                                     g2 * (T * c.z - (im2 - P2) * inv);
+                T = T * (1.0f - a);
+                const bool smooth = live && !clamped;
+                const float d_o = smooth ? dalpha * w * Gv : 0.0f;
+                const float dG = d_o * o;
+                const float qa = ex.x * (1.0f / kE), qb = ex.y * (0.5f / kE), qc = ex.z * (1.0f / kE);
+                const float d_mx = dG * (qa * dx + qb * dy);
+                const float d_my = dG * (qb * dx + qc * dy);
+                const float d_qa = -0.5f * dG * dx * dx;
+                const float d_qb = -dG * dx * dy;
+                const float d_qc = -0.5f * dG * dy * dy;
+                if (r != -1) {
+                    const float dgm = (smooth && gam < 1.0f) ? (own ? 1.0f : -1.0f) * dalpha * o * Gv : 0.0f;
+                    if (mapped) {
+                        dgr[r] += dgm;
+                    } else if (dgm != 0.0f && arg >= 0) {
+                        float ddx, ddy, sg;
+                        const int bpix = (int)st.b_list[bs0 + arg];
                         if (r >= 0) {
-                            gam = r < RM ? __uint_as_float(B.map[r][tid]) : gamma_lds<TS>(B, r, lx, ly, &arg);
-                        } else if (r == -2) {
-                            gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                            ddx = (float)(lx - lo16(B.bxy[arg])) - B.bdx[arg];
+                            ddy = (float)(ly - hi16(B.bxy[arg])) - B.bdy[arg];
+                            sg = B.bs[arg];
+                        } else {
+                            const float4 r0 = st.rec[(int64_t)bpix * 4];
+                            const int lp = bpix - vi.px_off;
+                            ddx = (float)(px - lp % vi.W) - r0.x;
+                            ddy = (float)(py - lp / vi.W) - r0.y;
+                            sg = st.rec[(int64_t)bpix * 4 + 2].z;
                         }
-                        const float w = g == h ? gam : 1.0f - gam;
-                        if (w > 0.0f) {
-                            contrib = true;
-                            // conic back from its exponent form
-                            const float4 q = make_float4(ex.x * (1.0f / kE), ex.y * (0.5f / kE), ex.z * (1.0f / kE), ex.w);
-                            const float Gv = exp2f(e);
-                            const float o = q.w;
-                            const float raw = o * w * Gv;
-                            const bool clamped = raw > amax;
-                            const float a = clamped ? amax : raw;
-                            const float ta = T * a;
-                            const float4 c = S.c[kk];
-                            d_c0 = ta * g0; d_c1 = ta * g1; d_c2 = ta * g2;
-                            P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
-                            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-                            const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
-                                                 g2 * (T * c.z - (im2 - P2) * inv);
-                            T = T * (1.0f - a);
-                            if (!clamped) {
-                                d_o = dalpha * w * Gv;
-                                const float dG = d_o * o;  // dl/dG * G
-                                d_mx = dG * (q.x * dx + q.y * dy);
-                                d_my = dG * (q.y * dx + q.z * dy);
-                                d_qa = -0.5f * dG * dx * dx;
-                                d_qb = -dG * dx * dy;
-                                d_qc = -0.5f * dG * dy * dy;
-                                if (r != -1 && gam < 1.0f) {
-                                    const float dgm = (g == h ? 1.0f : -1.0f) * dalpha * o * Gv;
-                                    if (r >= 0 && r < RM) {
-                                        dgam[r] += dgm;  // r is wave-uniform: indexed register access
-                                    } else if (arg >= 0) {
-                                        // no map for this run: push the boundary-point gradient now
-                                        float ddx, ddy, sg;
-                                        const int bpix = (int)st.b_list[bs0 + arg];
-                                        if (r >= 0) {
-                                            ddx = (float)(lx - lo16(B.bxy[arg])) - B.bdx[arg];
-                                            ddy = (float)(ly - hi16(B.bxy[arg])) - B.bdy[arg];
-                                            sg = B.bs[arg];
-                                        } else {
-                                            const float4 r0 = st.rec[(int64_t)bpix * 4];
-                                            const int lp = bpix - vi.px_off;
-                                            ddx = (float)(px - lp % vi.W) - r0.x;
-                                            ddy = (float)(py - lp / vi.W) - r0.y;
-                                            sg = st.rec[(int64_t)bpix * 4 + 2].z;
-                                        }
-                                        const float d = sqrtf(ddx * ddx + ddy * ddy);
-                                        const float dd = dgm * LN2 / sg * gam;
-                                        float *dst = st.dgauss + (int64_t)bpix * 12;
-                                        if (d > 0.f) {
-                                            unsafeAtomicAdd(&dst[0], -dd * ddx / d);
-                                            unsafeAtomicAdd(&dst[1], -dd * ddy / d);
-                                        }
-                                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
-                                    }
-                                }
-                            }
+                        const float d = sqrtf(ddx * ddx + ddy * ddy);
+                        const float dd = dgm * LN2 / sg * gam;
+                        float *dst = st.dgauss + (int64_t)bpix * 12;
+                        if (d > 0.f) {
+                            unsafeAtomicAdd(&dst[0], -dd * ddx / d);
+                            unsafeAtomicAdd(&dst[1], -dd * ddy / d);
                         }
+                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
                     }
                 }
-                if (__any(contrib)) {
-                    float vals[9] = {d_mx, d_my, d_qa, d_qb, d_qc, d_c0, d_c1, d_c2, d_o};
-                    wave_sum9_to_63(vals);
-                    if (lane == 63) {
+                float vals[9] = {d_mx, d_my, d_qa, d_qb, d_qc, d_c0, d_c1, d_c2, d_o};
+                wave_sum9_to_63(vals);
+                if (lane == 63) {
 #pragma unroll
-                        for (int f = 0; f < 9; ++f) atomicAdd(&acc[kk][f], vals[f]);
-                    }
+                    for (int f = 0; f < 9; ++f) atomicAdd(&acc[kk * 9 + f], vals[f]);
                 }
             }
         }
@@ -621,14 +652,15 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         if (tid < K && cur_gp >= 0) {  // each loader flushes its own slot, then stages the next batch
 #pragma unroll
             for (int f = 0; f < 9; ++f) {
-                const float val = acc[tid][f];
+                float *a = acc + tid * 9 + f;
+                const float val = a[0];
                 if (val != 0.f) {
                     unsafeAtomicAdd(&st.dgauss[(int64_t)cur_gp * 12 + f], val);
-                    acc[tid][f] = 0.f;
+                    a[0] = 0.f;
                 }
             }
         }
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, B.n_runs, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (first, i.e. lowest raster
@@ -640,10 +672,11 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int nmap = B.n_runs < RM ? B.n_runs : RM;
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-        const float dg = dgam[r];
-        if (r >= nmap || dg == 0.f) continue;
+        const float dg = dgr[r];
+        if (r >= nmap) continue;
+        if (dg == 0.f) continue;
         int e = -1;
-        const float gam = gamma_lds<TS>(B, r, lx, ly, &e);
+        const float gam = gamma_lds(B, r, lx, ly, &e);
         if (e < 0 || !(gam < 1.0f)) continue;
         const float ddx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], ddy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
         const float sg = B.bs[e];

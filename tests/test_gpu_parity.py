@@ -117,6 +117,29 @@ def test_gradient_parity(name):
         assert e <= GRAD_TOL, k
 
 
+@pytest.mark.parametrize("W,tile", [(300, 16), (200, 32)])
+def test_boundary_lists_over_the_lds_stage(W, tile):
+    """Tiles whose boundary list is longer than the LDS stage holds (the dense
+    20,000-patch box at a small size): runs staged in full are read from LDS,
+    the others from global memory; image and gradients still match."""
+    G.log(f"[edge] boundary lists over the LDS stage: box20k {W}x{W} tile {tile}")
+    sc, _, _ = S.workload("box20k_cubic")
+    cams = S.make_cameras([(0.0, 0.0, 8.0)], [(W, W)])
+    cfg = G.oracle_config(tile=tile)
+    img_ref, frames = oracle.render_views(sc, cams, cfg)
+    gi = G.l1_cotangent(img_ref, S.l1_target(cams.num_pixels))
+    g = G.run_gpu(sc, cams, tile=tile, grad_images=gi, lean=True)
+    assert g["counters"][7] > 0, "no tile overflowed the boundary stage"
+    err = np.abs(g["images"] - img_ref).max()
+    G.log(f"    {g['counters'][7]} tiles over the stage; image max abs err {err:.3e}")
+    assert err <= IMG_TOL
+    ref = oracle.grad_views(frames, gi)
+    for k in ref:
+        e = G.grad_error(g["grads"][k], ref[k])
+        G.log(f"    {k}: {e:.3e}")
+        assert e <= GRAD_TOL, k
+
+
 def test_batched_equals_per_view():
     """All views in one call give bit-identical images to one call per view."""
     G.log("[batched_vs_per_view] sphere_small")
