@@ -334,30 +334,47 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
 
-// Nine DPP adds of one step, step-major, so that consecutive adds are
-// independent (no hazard stalls between the steps of one sum).
-template <int CTRL>
-__device__ __forceinline__ void dpp_step9(float *v) {
+// Row reduce-scatter of nine per-lane values: butterflies over lane bits 0
+// (quad_perm [1,0,3,2]), 1 (quad_perm [2,3,0,1]) and 3 (row_ror:8) each halve
+// the set of values a lane carries (v[0..7]; v[8] is summed in every lane),
+// then row_shr:4 folds bit 2.  Afterwards, in every 16-lane row, the lane
+// with bit 2 set and bits (b3, b1, b0) holds the row total of
+// v[4 b3 + 2 b1 + b0] in v[0], and every lane with bit 2 set the row total
+// of v[8] in v[8]: 26 VALU operations instead of 36 for nine plain row sums.
+__device__ __forceinline__ void row_reduce_scatter9(float *v, int lane) {
+    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b3 = (lane & 8) != 0;
+    float u[4];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) v[i] += dpp_f<CTRL, 0xF>(v[i]);
+    for (int k = 0; k < 4; ++k) {
+        const float keep = b0 ? v[2 * k + 1] : v[2 * k], send = b0 ? v[2 * k] : v[2 * k + 1];
+        u[k] = keep + dpp_f<0xB1, 0xF>(send);
+    }
+    float s8 = v[8] + dpp_f<0xB1, 0xF>(v[8]);
+    float w[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const float keep = b1 ? u[2 * m + 1] : u[2 * m], send = b1 ? u[2 * m] : u[2 * m + 1];
+        w[m] = keep + dpp_f<0x4E, 0xF>(send);
+    }
+    s8 += dpp_f<0x4E, 0xF>(s8);
+    const float keep = b3 ? w[1] : w[0], send = b3 ? w[0] : w[1];
+    float x = keep + dpp_f<0x128, 0xF>(send);
+    s8 += dpp_f<0x128, 0xF>(s8);
+    x += dpp_f<0x114, 0xF>(x);  // row_shr:4
+    s8 += dpp_f<0x114, 0xF>(s8);
+    v[0] = x;
+    v[8] = s8;
 }
 
-// Nine sums over the whole wave: the row sums, then row 2 into row 3 and rows
-// 0 + 1 into row 3 (row broadcasts 15 and 31); lane 63 ends with the totals.
-__device__ __forceinline__ void row_sum9_to_15(float *v);
-__device__ __forceinline__ void wave_sum9_to_63(float *v) {
-    row_sum9_to_15(v);
-    dpp_step9<0x142>(v);  // row_bcast:15
-    dpp_step9<0x143>(v);  // row_bcast:31
-}
-
-// Nine sums over each 16-lane row at once (row shifts 1, 2, 4, 8): lane 15
-// of every row ends with its row's totals.
-__device__ __forceinline__ void row_sum9_to_15(float *v) {
-    dpp_step9<0x111>(v);  // row_shr:1
-    dpp_step9<0x112>(v);  // row_shr:2
-    dpp_step9<0x114>(v);  // row_shr:4
-    dpp_step9<0x118>(v);  // row_shr:8
+// Sum over the four rows, in every row: swapping a value with itself across
+// the wave halves (v_permlane32_swap) and then across neighbouring rows
+// (v_permlane16_swap) hands each lane the partner's value in one of the two
+// results, so their sum plus nothing else is the pair total.
+__device__ __forceinline__ float cross_row_sum(float x) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
 // ------------------------------------------------------------ forward
@@ -487,14 +504,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     __shared__ BL B;
     // the batch stage and its gradient sums are dead once the list is done;
     // the per-point boundary sums reuse their space
-    // per-row gradient sums of the staged entries: the rows of a wave walk
-    // different entries, and one LDS add instruction from the four row
-    // leaders then never has two lanes on one address (a stride of K*9+1
-    // words also spreads them over the banks)
-    constexpr int AST = K * 9 + 1;
     struct LoopLds {
         BatchLds<TS, K> S;
-        float acc[K * 9];
+        float acc[K * 9];  // gradient sums of the staged entries
     };
     union TailLds {
         LoopLds loop;
@@ -640,11 +652,17 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
                     }
                 }
+                // wave totals, scattered over the lanes of row 0 with bit 2 set,
+                // go to the entry's LDS sums: nine single-lane adds in two
+                // instructions
                 float vals[9] = {d_mx, d_my, d_qa, d_qb, d_qc, d_c0, d_c1, d_c2, d_o};
-                wave_sum9_to_63(vals);
-                if (lane == 63) {
-#pragma unroll
-                    for (int f = 0; f < 9; ++f) atomicAdd(&acc[kk * 9 + f], vals[f]);
+                row_reduce_scatter9(vals, lane);
+                vals[0] = cross_row_sum(vals[0]);
+                vals[8] = cross_row_sum(vals[8]);
+                if (lane < 16 && (lane & 4)) {
+                    float *dst = acc + kk * 9;
+                    atomicAdd(&dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)], vals[0]);
+                    if (lane == 4) atomicAdd(&dst[8], vals[8]);
                 }
             }
         }
