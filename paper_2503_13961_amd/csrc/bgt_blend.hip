@@ -617,17 +617,15 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 T = T * (1.0f - a);
                 const bool smooth = live && !clamped;
                 const float d_o = smooth ? dalpha * w * Gv : 0.0f;
-                const float dG = d_o * o;
-                const float qa = ex.x * (1.0f / kE), qb = ex.y * (0.5f / kE), qc = ex.z * (1.0f / kE);
-                const float d_mx = dG * (qa * dx + qb * dy);
-                const float d_my = dG * (qb * dx + qc * dy);
-                const float d_qa = -0.5f * dG * dx * dx;
-                const float d_qb = -dG * dx * dy;
-                const float d_qc = -0.5f * dG * dy * dy;
+                const float dG = d_o * o;  // dl/dG * G
+                // dl/dmu = Q sum dG d and dl/dQ = -1/2 sum dG d d^T over the
+                // pixels (d = q - mu): the sums are taken of the moments, and
+                // the Gaussian's conic is applied once per Gaussian after them
+                const float gx = dG * dx, gy = dG * dy;
                 if (r != -1) {
                     const float dgm = (smooth && gam < 1.0f) ? (own ? 1.0f : -1.0f) * dalpha * o * Gv : 0.0f;
                     if (mapped) {
-                        dgr[r] += dgm;
+                        if (__any(dgm != 0.0f)) dgr[r] += dgm;  // only near the run's boundary points
                     } else if (dgm != 0.0f && arg >= 0) {
                         float ddx, ddy, sg;
                         const int bpix = (int)st.b_list[bs0 + arg];
@@ -646,8 +644,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         const float dd = dgm * LN2 / sg * gam;
                         float *dst = st.dgauss + (int64_t)bpix * 12;
                         if (d > 0.f) {
-                            unsafeAtomicAdd(&dst[0], -dd * ddx / d);
-                            unsafeAtomicAdd(&dst[1], -dd * ddy / d);
+                            unsafeAtomicAdd(&dst[10], -dd * ddx / d);
+                            unsafeAtomicAdd(&dst[11], -dd * ddy / d);
                         }
                         unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
                     }
@@ -655,7 +653,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 // wave totals, scattered over the lanes of row 0 with bit 2 set,
                 // go to the entry's LDS sums: nine single-lane adds in two
                 // instructions
-                float vals[9] = {d_mx, d_my, d_qa, d_qb, d_qc, d_c0, d_c1, d_c2, d_o};
+                float vals[9] = {gx, gy, gx * dx, gx * dy, gy * dy, d_c0, d_c1, d_c2, d_o};
                 row_reduce_scatter9(vals, lane);
                 vals[0] = cross_row_sum(vals[0]);
                 vals[8] = cross_row_sum(vals[8]);
@@ -711,8 +709,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         const float a0 = bacc[e][0], a1 = bacc[e][1], a2 = bacc[e][2];
         if (a0 == 0.f && a1 == 0.f && a2 == 0.f) continue;
         float *dst = st.dgauss + (int64_t)st.b_list[bs0 + e] * 12;
-        if (a0 != 0.f) unsafeAtomicAdd(&dst[0], a0);
-        if (a1 != 0.f) unsafeAtomicAdd(&dst[1], a1);
+        if (a0 != 0.f) unsafeAtomicAdd(&dst[10], a0);
+        if (a1 != 0.f) unsafeAtomicAdd(&dst[11], a1);
         if (a2 != 0.f) unsafeAtomicAdd(&dst[9], a2);
     }
 }

@@ -102,6 +102,22 @@ __device__ __forceinline__ void subtri_corners(int L, int s, int *m) {
     }
 }
 
+// the same corners with their lattice coordinates (a, b)
+__device__ __forceinline__ void subtri_corners_ab(int L, int s, int *m, int *ca, int *cb) {
+    const int up = L * (L + 1) / 2;
+    int a = 0;
+    if (s < up) {
+        while (s >= L - a) { s -= L - a; ++a; }
+        ca[0] = a; cb[0] = s; ca[1] = a + 1; cb[1] = s; ca[2] = a; cb[2] = s + 1;
+    } else {
+        s -= up;
+        while (s >= L - 1 - a) { s -= L - 1 - a; ++a; }
+        ca[0] = a + 1; cb[0] = s; ca[1] = a + 1; cb[1] = s + 1; ca[2] = a; cb[2] = s + 1;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[c] = lattice_index(L, ca[c], cb[c]);
+}
+
 template <int DEG>
 __global__ void k_tessellate(Consts k, PrimPtrs pr, double *wverts, float *verts_out) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
@@ -366,39 +382,61 @@ template <int DEG>
 __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
     const int lane = threadIdx.x & 63;
+    // the 8x8 block is wave-uniform, so its view is found with scalar loads
+    const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     int v, x, y;
-    const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
+    const bool act = block8_pixel(vt, blk, lane, v, x, y);
     bool fg = false, isb = false;
     int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;  // tile rectangles
     const ViewInfo vi = vt.v[v];
     if (act) {
         const int lp = y * vi.W + x, pix = vi.px_off + lp;
-        const unsigned long long z = st.zbuf[pix];
+        // the pixel's z-buffer word and its in-image 4-neighbours' (an edge
+        // pixel reads itself in place of a missing neighbour), loaded together
+        const unsigned long long *zr = st.zbuf + vi.px_off;
+        const int nl = x > 0 ? lp - 1 : lp, nr = x + 1 < vi.W ? lp + 1 : lp;
+        const int nu = y > 0 ? lp - vi.W : lp, nd = y + 1 < vi.H ? lp + vi.W : lp;
+        const unsigned long long z = zr[lp], z0 = zr[nl], z1 = zr[nr], z2 = zr[nu], z3 = zr[nd];
         const int tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
+        // B: a neighbour shows another primitive (or the background); taken
+        // here so that all five words are waited for at once
+        const int pc = zb_prim(z, k.L2);
+        const bool bnd = zb_prim(z0, k.L2) != pc || zb_prim(z1, k.L2) != pc || zb_prim(z2, k.L2) != pc ||
+                         zb_prim(z3, k.L2) != pc;
         st.I_tri[pix] = tri;
         uint8_t flags = 0;
         float2 uvo = make_float2(0.f, 0.f);
         if (tri >= 0) {
             const int p = tri / k.L2, s = tri % k.L2;
-            const unsigned long long *zr = st.zbuf + vi.px_off;
-            bool bnd = false;
-            if (x > 0 && zb_prim(zr[lp - 1], k.L2) != p) bnd = true;
-            if (x + 1 < vi.W && zb_prim(zr[lp + 1], k.L2) != p) bnd = true;
-            if (y > 0 && zb_prim(zr[lp - vi.W], k.L2) != p) bnd = true;
-            if (y + 1 < vi.H && zb_prim(zr[lp + vi.W], k.L2) != p) bnd = true;
-            // perspective-correct barycentrics in the winning flat triangle
-            int m[3];
-            subtri_corners(k.L, s, m);
+            // every gather of this pixel is issued before the first is used:
+            // the winning triangle's corners, the patch's control points, its
+            // rotation-scale setup and opacity
+            int m[3], ca[3], cb[3];
+            subtri_corners_ab(k.L, s, m, ca, cb);
             const VertRec *vv = st.verts + (int64_t)v * k.VL * k.P;
+            VertRec vr[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vr[c] = vv[(int64_t)m[c] * k.P + p];
+            float cpt[3][NCP], cco[3][NCP];
+#pragma unroll
+            for (int c = 0; c < NCP; ++c)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    cpt[dd][c] = pr.ctrl[((int64_t)dd * NCP + c) * k.P + p];
+                    cco[dd][c] = pr.color[((int64_t)dd * NCP + c) * k.P + p];
+                }
+            const double *M = st.psetup + (int64_t)p * 10;
+            double Mv[10];
+#pragma unroll
+            for (int i = 0; i < 10; ++i) Mv[i] = M[i];
+            const float opa = pr.opacity[p];
+            // perspective-correct barycentrics in the winning flat triangle
             double vx[3], vy[3], viz[3], lu[3], lv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const VertRec r = vv[(int64_t)m[c] * k.P + p];
-                vx[c] = r.x; vy[c] = r.y; viz[c] = r.iz;
-                int a, b;
-                lattice_node(k.L, m[c], a, b);
-                lu[c] = (double)a / k.L;
-                lv[c] = (double)b / k.L;
+                vx[c] = vr[c].x; vy[c] = vr[c].y; viz[c] = vr[c].iz;
+                lu[c] = (double)ca[c] / k.L;
+                lv[c] = (double)cb[c] / k.L;
             }
             const double qx = x + 0.5, qy = y + 0.5;
             const double d = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
@@ -425,8 +463,8 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             for (int c = 0; c < NCP; ++c)
 #pragma unroll
                 for (int dd = 0; dd < 3; ++dd) {
-                    S[dd] += B[c] * (double)pr.ctrl[((int64_t)dd * NCP + c) * k.P + p];
-                    col[dd] += B[c] * (double)pr.color[((int64_t)dd * NCP + c) * k.P + p];
+                    S[dd] += B[c] * (double)cpt[dd][c];
+                    col[dd] += B[c] * (double)cco[dd][c];
                 }
             const Cam c = load_cam(cams, v);
             double t[3];
@@ -443,10 +481,6 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 }
                 // Eq. 5 with a resolution-1 attribute map: M = Rq diag(s) of the patch;
                 // V = Tm M, Sigma2D = V V^T + low-pass
-                const double *M = st.psetup + (int64_t)p * 10;
-                double Mv[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) Mv[i] = M[i];
                 double V0[3], V1[3];
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
@@ -465,7 +499,7 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 int bi0 = 1, bi1 = 0, bj0 = 1, bj1 = 0;
                 if (bnd) {
                     // isotropic boundary Gaussian of scale r_b: r_b^2 J J^T + low-pass
-                    const double r2 = M[9];
+                    const double r2 = Mv[9];
                     const double ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
                     const double mb = r2 * (J02 * J12);
                     const double mc = r2 * (J11 * J11 + J12 * J12) + k.dilation;
@@ -481,7 +515,7 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 rec[0] = make_float4((float)(mux - (x + 0.5)), (float)(muy - (y + 0.5)), (float)(SC * idet),
                                      (float)(-SB * idet));
                 rec[1] = make_float4((float)(SA * idet), (float)col[0], (float)col[1], (float)col[2]);
-                rec[2] = make_float4(pr.opacity[p], __int_as_float(p), sigma, (float)tz);
+                rec[2] = make_float4(opa, __int_as_float(p), sigma, (float)tz);
                 rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
                                      __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
                 st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;

@@ -51,13 +51,16 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
         int v0, x0, y0;
         if (block8_pixel(vt, wblock, lane, v0, x0, y0)) pix = vt.v[v0].px_off + y0 * vt.v[v0].W + x0;
         if (pix >= 0 && (st.pflags[pix] & PF_VALID)) {
+            // the blend sums: moments m0..m4 = sum dG (dx, dy, dx dx, dx dy, dy dy)
+            // of dl/dG G, colour, opacity, boundary radius and position
             const float *g = st.dgauss + (int64_t)pix * 12;
-            const float dmux = g[0], dmuy = g[1], dqa = g[2], dqb = g[3], dqc = g[4];
+            const float m0 = g[0], m1 = g[1];
+            const float dqa = -0.5f * g[2], dqb = -g[3], dqc = -0.5f * g[4];
             dcol[0] = g[5]; dcol[1] = g[6]; dcol[2] = g[7];
             dop = g[8];
-            const float dsig = g[9];
-            if (dmux != 0.f || dmuy != 0.f || dqa != 0.f || dqb != 0.f || dqc != 0.f || dcol[0] != 0.f ||
-                dcol[1] != 0.f || dcol[2] != 0.f || dop != 0.f || dsig != 0.f) {
+            const float dsig = g[9], dbx = g[10], dby = g[11];
+            if (m0 != 0.f || m1 != 0.f || dqa != 0.f || dqb != 0.f || dqc != 0.f || dcol[0] != 0.f ||
+                dcol[1] != 0.f || dcol[2] != 0.f || dop != 0.f || dsig != 0.f || dbx != 0.f || dby != 0.f) {
                 act = true;
                 prim = st.I_tri[pix] / k.L2;
                 const int p = prim;
@@ -108,7 +111,10 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 const float SB = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
                 const float SC = V[3] * V[3] + V[4] * V[4] + V[5] * V[5] + k.dilation;
                 // conic = inverse: a = C/det, b = -B/det, c = A/det
-                const float det = SA * SC - SB * SB, id2 = 1.f / (det * det);
+                const float det = SA * SC - SB * SB, idet = 1.f / det, id2 = idet * idet;
+                // dl/dmu = Q (m0, m1) plus the boundary point's own position gradient
+                const float dmux = (SC * m0 - SB * m1) * idet + dbx;
+                const float dmuy = (SA * m1 - SB * m0) * idet + dby;
                 const float dA = (-SC * SC * dqa + SB * SC * dqb - SB * SB * dqc) * id2;
                 const float dB = (2.f * SB * SC * dqa - (SA * SC + SB * SB) * dqb + 2.f * SA * SB * dqc) * id2;
                 const float dC = (-SB * SB * dqa + SA * SB * dqb - SA * SA * dqc) * id2;
