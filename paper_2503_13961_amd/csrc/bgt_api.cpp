@@ -35,7 +35,7 @@ struct Shape {
     Consts k;
     int64_t N, NT;
     int64_t off[BGT_STATE_FIELDS];
-    int64_t wverts_off, psetup_off, bigsort_off;
+    int64_t wverts_off, patch_off, bigsort_off;
 };
 
 bgt_status fail(bgt_ctx *ctx, bgt_status st, const char *msg) {
@@ -109,7 +109,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     const int64_t nb_scan = (NT + 1023) / 1024;
     int64_t o = 0;
     auto put = [&](int f, int64_t bytes) { sh.off[f] = o; o = align256(o + bytes); };
-    put(F_COUNTERS, C_NUM * 8);
+    put(F_COUNTERS, kCounterWords * 8);
     put(F_ZBUF, 8 * N);
     put(F_ITRI, 4 * N);
     put(F_IUV, 8 * N);
@@ -123,8 +123,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
         const int64_t wbytes = 24 * (int64_t)k.VL * k.P;
         sh.off[F_VERTS] = o;
         sh.wverts_off = align256(o + vbytes);
-        sh.psetup_off = align256(sh.wverts_off + wbytes);
-        o = align256(sh.psetup_off + 80 * (int64_t)k.P);
+        sh.patch_off = align256(sh.wverts_off + wbytes);
+        o = align256(sh.patch_off + 4 * (int64_t)patch_dw(k.ncp) * k.P);
     }
     put(F_GCOUNT, 4 * NT);
     put(F_GSTART, 4 * NT);
@@ -161,7 +161,7 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.last = (int32_t *)(b + sh.off[F_LAST]);
     p.verts = (VertRec *)(b + sh.off[F_VERTS]);
     p.wverts = (double *)(b + sh.wverts_off);
-    p.psetup = (double *)(b + sh.psetup_off);
+    p.patch = (float *)(b + sh.patch_off);
     p.g_count = (int32_t *)(b + sh.off[F_GCOUNT]);
     p.g_start = (int32_t *)(b + sh.off[F_GSTART]);
     p.g_cursor = (int32_t *)(b + sh.off[F_GCURSOR]);
@@ -338,7 +338,8 @@ bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     const StatePtrs sp = state_ptrs(sh, state);
     const PrimPtrs pp = prim_ptrs(prims);
     hipError_t e;
-    if ((e = launch_fill_u64((unsigned long long *)sp.counters, 0ull, C_NUM, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    if ((e = launch_fill_u64((unsigned long long *)sp.counters, 0ull, kCounterWords, st)) != hipSuccess)
+        return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_u64(sp.zbuf, 0ull, sh.N, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_i32(sp.g_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_i32(sp.b_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
@@ -407,19 +408,24 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
 }
 
 bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters, void *stream) {
-    if (!ctx || !state || !counters || state_bytes < (size_t)(C_NUM * 8)) return BGT_E_INVALID;
+    if (!ctx || !state || !counters || state_bytes < (size_t)(kCounterWords * 8)) return BGT_E_INVALID;
     bgt_status s;
     if ((s = use_device(ctx)) != BGT_OK) return s;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
-    int64_t c[C_NUM];
+    int64_t c[kCounterWords];
     e = hipMemcpy(c, state, sizeof(c), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy");
+    int64_t fg = 0, nb = 0;
+    for (int i = 0; i < kStripes; ++i) {
+        fg += c[C_NUM + i * kStripeStride];
+        nb += c[C_NUM + i * kStripeStride + 1];
+    }
     counters[0] = c[C_OVERFLOW];
     counters[1] = c[C_GPAIRS];
     counters[2] = c[C_BPAIRS];
-    counters[3] = c[C_FG];
-    counters[4] = c[C_BOUNDARY];
+    counters[3] = fg;
+    counters[4] = nb;
     counters[5] = c[C_BIGTRI];
     counters[6] = c[C_BIGSORT];
     counters[7] = c[C_BIGBLIST];

@@ -157,11 +157,22 @@ hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts
 
 // ------------------------------------------------------------ per-patch setup
 
-// Eq. 5 with a resolution-1 attribute map: one rotation and scale per patch.
-// psetup[p] = (Rq diag(exp(log_scale)) row-major (9), r_b^2) in FP64.
-__global__ void k_prim_setup(Consts k, PrimPtrs pr, double *psetup) {
+// Per-patch record (layout at patch_dw): the control and colour points and
+// the opacity copied as they are, and Eq. 5 with a resolution-1 attribute
+// map, one rotation and scale per patch: R(q/|q|) diag(exp(log_scale)) and
+// r_b^2 = (r_ref / sharpness)^2 in FP64.
+__global__ void k_prim_setup(Consts k, PrimPtrs pr, float *patch) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= k.P) return;
+    const int ncp = k.ncp;
+    float *o = patch + (int64_t)p * patch_dw(ncp);
+    for (int c = 0; c < ncp; ++c)
+        for (int d = 0; d < 3; ++d) {
+            o[3 * c + d] = pr.ctrl[((int64_t)d * ncp + c) * k.P + p];
+            o[3 * ncp + 3 * c + d] = pr.color[((int64_t)d * ncp + c) * k.P + p];
+        }
+    o[6 * ncp] = pr.opacity[p];
+    o[6 * ncp + 1] = 0.f;
     double q[4], qn = 0.0;
 #pragma unroll
     for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
@@ -175,13 +186,14 @@ __global__ void k_prim_setup(Consts k, PrimPtrs pr, double *psetup) {
     double sc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) sc[d] = exp((double)pr.log_scale[(int64_t)d * k.T * k.P + p]);
-    double *o = psetup + (int64_t)p * 10;
+    double *m = (double *)(o + patch_m_off(ncp));
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) o[3 * r + c] = Rq[3 * r + c] * sc[c];
+        for (int c = 0; c < 3; ++c) m[3 * r + c] = Rq[3 * r + c] * sc[c];
     const double rb = (double)k.r_ref / (double)pr.sharp[p];
-    o[9] = rb * rb;
+    m[9] = rb * rb;
+    for (int i = patch_m_off(ncp) + 20; i < patch_dw(ncp); ++i) o[i] = 0.f;
 }
 
 // ------------------------------------------------------------ projection
@@ -379,8 +391,10 @@ __device__ __forceinline__ void centre_range(double c, double r, int n, int &lo,
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st) {
+__global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st,
+                                             const float *__restrict__ patch) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    constexpr int PD = patch_dw(NCP), MO = patch_m_off(NCP);
     const int lane = threadIdx.x & 63;
     // the 8x8 block is wave-uniform, so its view is found with scalar loads
     const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -389,83 +403,91 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
     bool fg = false, isb = false;
     int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;  // tile rectangles
     const ViewInfo vi = vt.v[v];
+    const int lp = y * vi.W + x, pix = vi.px_off + lp;
+    // the pixel's z-buffer word and its in-image 4-neighbours' (an edge pixel
+    // reads itself in place of a missing neighbour), loaded together
+    int tri = -1, p = -1;
+    bool bnd = false;
     if (act) {
-        const int lp = y * vi.W + x, pix = vi.px_off + lp;
-        // the pixel's z-buffer word and its in-image 4-neighbours' (an edge
-        // pixel reads itself in place of a missing neighbour), loaded together
         const unsigned long long *zr = st.zbuf + vi.px_off;
         const int nl = x > 0 ? lp - 1 : lp, nr = x + 1 < vi.W ? lp + 1 : lp;
         const int nu = y > 0 ? lp - vi.W : lp, nd = y + 1 < vi.H ? lp + vi.W : lp;
         const unsigned long long z = zr[lp], z0 = zr[nl], z1 = zr[nr], z2 = zr[nu], z3 = zr[nd];
-        const int tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
-        // B: a neighbour shows another primitive (or the background); taken
-        // here so that all five words are waited for at once
-        const int pc = zb_prim(z, k.L2);
-        const bool bnd = zb_prim(z0, k.L2) != pc || zb_prim(z1, k.L2) != pc || zb_prim(z2, k.L2) != pc ||
-                         zb_prim(z3, k.L2) != pc;
+        tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
+        // B: a neighbour shows another primitive (or the background)
+        p = zb_prim(z, k.L2);
+        bnd = zb_prim(z0, k.L2) != p || zb_prim(z1, k.L2) != p || zb_prim(z2, k.L2) != p || zb_prim(z3, k.L2) != p;
+    }
+    // perspective-correct barycentrics in the winning flat triangle and the
+    // Bernstein weights there (foreground lanes)
+    double B[NCP];
+    float2 uvo = make_float2(0.f, 0.f);
+    if (tri >= 0) {
+        const int s = tri % k.L2;
+        int m[3], ca[3], cb[3];
+        subtri_corners_ab(k.L, s, m, ca, cb);
+        const VertRec *vv = st.verts + (int64_t)v * k.VL * k.P;
+        double vx[3], vy[3], viz[3], lu[3], lv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const VertRec r = vv[(int64_t)m[c] * k.P + p];
+            vx[c] = r.x; vy[c] = r.y; viz[c] = r.iz;
+            lu[c] = (double)ca[c] / k.L;
+            lv[c] = (double)cb[c] / k.L;
+        }
+        const double qx = x + 0.5, qy = y + 0.5;
+        const double d = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
+        // screen-space barycentrics (edge functions / area), then weights lambda_k / z_k
+        double beta[3];
+        if (d != 0.0) {
+            beta[0] = ((vx[2] - vx[1]) * (qy - vy[1]) - (vy[2] - vy[1]) * (qx - vx[1])) * viz[0];
+            beta[1] = ((vx[0] - vx[2]) * (qy - vy[2]) - (vy[0] - vy[2]) * (qx - vx[2])) * viz[1];
+            beta[2] = ((vx[1] - vx[0]) * (qy - vy[0]) - (vy[1] - vy[0]) * (qx - vx[0])) * viz[2];
+        } else {
+            beta[0] = viz[0]; beta[1] = viz[1]; beta[2] = viz[2];
+        }
+        // the common factor 1/area cancels in the normalisation
+        const double iws = 1.0 / (beta[0] + beta[1] + beta[2]);
+        double u = 0.0, vb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { u += beta[c] * iws * lu[c]; vb += beta[c] * iws * lv[c]; }
+        uvo = make_float2((float)u, (float)vb);
+        bernstein<DEG>(u, vb, 1.0 - u - vb, B);
+    }
+    // Eq. 3 (position) and Eq. 4 (diffuse colour) with the patch records read
+    // through the scalar unit: an 8x8 block sees a few patches, the wave walks
+    // its distinct ids (wave-uniform), the lanes of each id sum their points
+    // against its record and keep its rotation-scale setup and opacity
+    double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0};
+    float Rm[21];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) Rm[i] = 0.f;
+    for (unsigned long long todo = __ballot(p >= 0); todo;) {
+        const int pu = __builtin_amdgcn_readlane(p, __ffsll((long long)todo) - 1);
+        const bool mine = p == pu;
+        todo &= ~__ballot(mine);
+        const float *src = patch + (int64_t)pu * PD;
+        if (mine) {
+#pragma unroll
+            for (int c = 0; c < NCP; ++c)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    S[dd] += B[c] * (double)src[3 * c + dd];
+                    col[dd] += B[c] * (double)src[3 * NCP + 3 * c + dd];
+                }
+#pragma unroll
+            for (int i = 0; i < 20; ++i) Rm[i] = src[MO + i];
+            Rm[20] = src[6 * NCP];
+        }
+    }
+    if (act) {
         st.I_tri[pix] = tri;
         uint8_t flags = 0;
-        float2 uvo = make_float2(0.f, 0.f);
         if (tri >= 0) {
-            const int p = tri / k.L2, s = tri % k.L2;
-            // every gather of this pixel is issued before the first is used:
-            // the winning triangle's corners, the patch's control points, its
-            // rotation-scale setup and opacity
-            int m[3], ca[3], cb[3];
-            subtri_corners_ab(k.L, s, m, ca, cb);
-            const VertRec *vv = st.verts + (int64_t)v * k.VL * k.P;
-            VertRec vr[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) vr[c] = vv[(int64_t)m[c] * k.P + p];
-            float cpt[3][NCP], cco[3][NCP];
-#pragma unroll
-            for (int c = 0; c < NCP; ++c)
-#pragma unroll
-                for (int dd = 0; dd < 3; ++dd) {
-                    cpt[dd][c] = pr.ctrl[((int64_t)dd * NCP + c) * k.P + p];
-                    cco[dd][c] = pr.color[((int64_t)dd * NCP + c) * k.P + p];
-                }
-            const double *M = st.psetup + (int64_t)p * 10;
             double Mv[10];
 #pragma unroll
-            for (int i = 0; i < 10; ++i) Mv[i] = M[i];
-            const float opa = pr.opacity[p];
-            // perspective-correct barycentrics in the winning flat triangle
-            double vx[3], vy[3], viz[3], lu[3], lv[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                vx[c] = vr[c].x; vy[c] = vr[c].y; viz[c] = vr[c].iz;
-                lu[c] = (double)ca[c] / k.L;
-                lv[c] = (double)cb[c] / k.L;
-            }
-            const double qx = x + 0.5, qy = y + 0.5;
-            const double d = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
-            // screen-space barycentrics (edge functions / area), then weights lambda_k / z_k
-            double beta[3];
-            if (d != 0.0) {
-                beta[0] = ((vx[2] - vx[1]) * (qy - vy[1]) - (vy[2] - vy[1]) * (qx - vx[1])) * viz[0];
-                beta[1] = ((vx[0] - vx[2]) * (qy - vy[2]) - (vy[0] - vy[2]) * (qx - vx[2])) * viz[1];
-                beta[2] = ((vx[1] - vx[0]) * (qy - vy[0]) - (vy[1] - vy[0]) * (qx - vx[0])) * viz[2];
-            } else {
-                beta[0] = viz[0]; beta[1] = viz[1]; beta[2] = viz[2];
-            }
-            // the common factor 1/area cancels in the normalisation
-            const double iws = 1.0 / (beta[0] + beta[1] + beta[2]);
-            double u = 0.0, vb = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { u += beta[c] * iws * lu[c]; vb += beta[c] * iws * lv[c]; }
-            uvo = make_float2((float)u, (float)vb);
-            // Eq. 3 (position) and Eq. 4 (diffuse colour)
-            double B[NCP];
-            bernstein<DEG>(u, vb, 1.0 - u - vb, B);
-            double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int c = 0; c < NCP; ++c)
-#pragma unroll
-                for (int dd = 0; dd < 3; ++dd) {
-                    S[dd] += B[c] * (double)cpt[dd][c];
-                    col[dd] += B[c] * (double)cco[dd][c];
-                }
+            for (int i = 0; i < 10; ++i) Mv[i] = __hiloint2double(__float_as_int(Rm[2 * i + 1]), __float_as_int(Rm[2 * i]));
+            const float opa = Rm[20];
             const Cam c = load_cam(cams, v);
             double t[3];
             cam_apply(c, S, t);
@@ -539,8 +561,9 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
     });
     const unsigned long long mf = __ballot(fg), mb = __ballot(isb);
     if (lane == 0) {
-        if (mf) atomicAdd((unsigned long long *)&st.counters[C_FG], (unsigned long long)__popcll(mf));
-        if (mb) atomicAdd((unsigned long long *)&st.counters[C_BOUNDARY], (unsigned long long)__popcll(mb));
+        unsigned long long *slot = (unsigned long long *)&st.counters[C_NUM + (blk % kStripes) * kStripeStride];
+        if (mf) atomicAdd(&slot[0], (unsigned long long)__popcll(mf));
+        if (mb) atomicAdd(&slot[1], (unsigned long long)__popcll(mb));
     }
 }
 
@@ -565,15 +588,15 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s) {
-    hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)((k.P + 255) / 256)), dim3(256), 0, s, k, pr, st.psetup);
+    hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)((k.P + 255) / 256)), dim3(256), 0, s, k, pr, st.patch);
     {
         dim3 grid((unsigned)((vt.total_b8 + 3) / 4)), block(256);  // one wave per 8x8 block
         switch (k.degree) {
-            case 1: hipLaunchKernelGGL(k_gen<1>, grid, block, 0, s, k, vt, pr, cams, st); break;
-            case 2: hipLaunchKernelGGL(k_gen<2>, grid, block, 0, s, k, vt, pr, cams, st); break;
-            case 3: hipLaunchKernelGGL(k_gen<3>, grid, block, 0, s, k, vt, pr, cams, st); break;
-            case 4: hipLaunchKernelGGL(k_gen<4>, grid, block, 0, s, k, vt, pr, cams, st); break;
-            case 5: hipLaunchKernelGGL(k_gen<5>, grid, block, 0, s, k, vt, pr, cams, st); break;
+            case 1: hipLaunchKernelGGL(k_gen<1>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
+            case 2: hipLaunchKernelGGL(k_gen<2>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
+            case 3: hipLaunchKernelGGL(k_gen<3>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
+            case 4: hipLaunchKernelGGL(k_gen<4>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
+            case 5: hipLaunchKernelGGL(k_gen<5>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
             default: return hipErrorInvalidValue;
         }
     }

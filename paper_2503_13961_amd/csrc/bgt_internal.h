@@ -20,8 +20,8 @@ enum Counter {
     C_OVERFLOW = 0,   // bit0 gauss pairs, bit1 boundary pairs, bit2 big-triangle queue
     C_GPAIRS = 1,
     C_BPAIRS = 2,
-    C_FG = 3,
-    C_BOUNDARY = 4,
+    C_FG = 3,        // (foreground and boundary pixels are tallied in the
+    C_BOUNDARY = 4,  //  striped slots below and summed by bgt_query)
     C_BIGTRI = 5,
     C_BIGSORT = 6,
     C_BIGBLIST = 7,
@@ -29,6 +29,12 @@ enum Counter {
     C_BIGSORT_QB = 9,
     C_NUM = 16
 };
+// The per-wave foreground and boundary tallies go to kStripes slots 64 bytes
+// apart (slot = 8x8 block index mod kStripes) after the C_NUM counters:
+// 160,000 waves adding to one address serialize on it.
+constexpr int kStripes = 64;
+constexpr int kStripeStride = 8;  // int64 words per slot
+constexpr int kCounterWords = C_NUM + kStripes * kStripeStride;
 
 // per-pixel flags
 constexpr uint8_t PF_VALID = 1;     // the pixel has a Gaussian
@@ -126,6 +132,16 @@ struct GradPtrs {
 };
 
 // per-view projected lattice vertex
+// Packed per-patch record in dwords, written by k_prim_setup so that the
+// generation pass reads a patch with a few scalar loads:
+//   [0, 3 NCP)      control points, [c][d]
+//   [3 NCP, 6 NCP)  colour control points, [c][d]
+//   6 NCP           opacity, then one pad dword
+//   6 NCP + 2 ...   ten doubles: R(q) diag(e^s) row-major, then r_b^2
+// rounded up to 16 dwords.
+__host__ __device__ constexpr int patch_dw(int ncp) { return (6 * ncp + 22 + 15) / 16 * 16; }
+__host__ __device__ constexpr int patch_m_off(int ncp) { return 6 * ncp + 2; }
+
 struct VertRec {
     double x, y, iz;       // unsnapped projection and 1/z
     int32_t X, Y;          // 1/256-px fixed point; X == INT32_MIN marks a culled vertex
@@ -150,7 +166,7 @@ struct StatePtrs {
     int32_t *last;
     VertRec *verts;        // [V][VL][P]
     double *wverts;        // [VL][P][3] world lattice
-    double *psetup;        // [P][10] Rq diag(s) (row-major) and r_b^2 per patch
+    float *patch;          // [P][patch_dw(ncp)] packed per-patch record (see patch_dw)
     int32_t *g_count, *g_start, *g_cursor;
     int32_t *b_count, *b_start, *b_cursor;
     unsigned long long *g_keys, *b_keys;
