@@ -45,6 +45,11 @@
  *   - I_id, I_uv and B are frozen in the backward pass.
  */
 #include <math.h>
+
+/* boundary distances below this many pixels are the cone point of |q - b| */
+#define D_KINK 1e-6
+/* boundary distance ratios d/sigma closer than this are ties (gamma_star) */
+#define ARG_TIE 1e-5
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -619,18 +624,24 @@ static double gamma_fn(double d, double sigma) {
 
 /* gamma* of primitive g at pixel centre (qx,qy): the smallest gamma over the
  * boundary points of g listed for this tile; returns 1 when none is within
- * range.  *arg receives the pixel index of the minimiser (lowest index on
- * ties) or -1. */
+ * range.  *arg receives the point the gradient of gamma* is routed to, or -1
+ * when none is within range: the points are scanned in raster order and a
+ * point takes over only when its d/sigma is below the current one's by more
+ * than ARG_TIE, so near-equal ratios (the pixel-centred boundary points of a
+ * planar patch are at equal distances, with radii that differ in the sixth
+ * digit) are ties that go to the lower raster index. */
 static double gamma_star(const orc_frame *f, int tile, int g, double qx, double qy, int *arg) {
-    double best = 1.0;
+    double best = 1.0, rbest = 1.0;
     *arg = -1;
     for (int e = f->b_start[tile]; e < f->b_start[tile + 1]; ++e) {
         int bp = f->b_list[e];
         const double *r = &f->rec[(size_t)bp * GR_N];
         if ((int)r[GR_PRIM] != g) continue;
         double dx = qx - r[GR_MUX], dy = qy - r[GR_MUY];
-        double gm = gamma_fn(sqrt(dx * dx + dy * dy), r[GR_SIGMA]);
-        if (gm < best || (gm == best && gm < 1.0 && bp < *arg)) { best = gm; *arg = bp; }
+        double d = sqrt(dx * dx + dy * dy), ratio = d / r[GR_SIGMA];
+        double gm = gamma_fn(d, r[GR_SIGMA]);
+        if (gm < best) best = gm;
+        if (ratio < 1.0 && (*arg < 0 || ratio < rbest - ARG_TIE)) { rbest = ratio; *arg = bp; }
     }
     return best;
 }
@@ -795,7 +806,11 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
                     double bx = qx - rb[GR_MUX], by = qy - rb[GR_MUY];
                     double d = sqrt(bx * bx + by * by), sg = rb[GR_SIGMA];
                     double dd = dgam * ln2 / sg * c->gamma;
-                    if (d > 0.0) {
+                    /* |q - b| has its cone point at d = 0, where the subgradient
+                     * taken is 0; a boundary point that sits on its own pixel
+                     * centre (every boundary pixel of a planar patch) lands
+                     * there up to rounding, so d below D_KINK counts as 0 */
+                    if (d > D_KINK) {
                         atomic_add(&gb[DG_MUX], -dd * bx / d);   /* dd/db = -(q-b)/d */
                         atomic_add(&gb[DG_MUY], -dd * by / d);
                     }

@@ -16,6 +16,7 @@
 // (possibly different) Gaussians per step; a Gaussian that misses a
 // sub-block costs that sub-block nothing.
 #include "bgt_internal.h"
+#include "bgt_wave.h"
 
 namespace bgt {
 
@@ -90,6 +91,14 @@ struct BatchLds {
     int2 pr[K];                 // primitive id, run index
     int xr[K], yr[K];
 };
+
+// |q - b| has its cone point at d = 0, where the subgradient taken is 0; a
+// boundary point on its own pixel centre (every boundary pixel of a planar
+// patch) lands there up to rounding, so distances below kDKink pixels count
+// as 0 for the position gradient
+constexpr float kDKink = 1e-6f;
+// boundary distance ratios d/sigma closer than this are ties (gamma_lds)
+constexpr float kArgTie = 1e-5f;
 
 // -log2(e)/2: G = exp(-d^T Q d / 2) = 2^(kE d^T Q d)
 constexpr float kE = -0.5f * 1.44269504088896341f;
@@ -186,15 +195,21 @@ __device__ __forceinline__ float gamma_fn(float d, float sigma) {
     return g < 1.0f ? g : 1.0f;
 }
 
-// gamma* from the LDS points of run r (runs without a map); *arg = entry
+// gamma* from the LDS points of run r (the exact minimum, bit-identical to
+// the map), and in *arg the entry its gradient is routed to: scanned in index
+// (raster) order, an entry takes over only when its d/sigma is below the
+// current one's by more than kArgTie, so near-equal ratios are ties that go
+// to the lower index; -1 when no point is within range
 template <typename BL>
 __device__ __forceinline__ float gamma_lds(const BL &B, int r, int lx, int ly, int *arg) {
-    float best = 1.0f;
+    float best = 1.0f, rbest = 1.0f;
     *arg = -1;
     for (int e = B.run_start[r]; e < B.run_start[r + 1]; ++e) {
         const float dx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], dy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
-        const float g = gamma_fn(bdist(dx, dy), B.bs[e]);
-        if (g < best) { best = g; *arg = e; }
+        const float d = bdist(dx, dy), q = __fdiv_rn(d, B.bs[e]);
+        const float g = gamma_fn(d, B.bs[e]);
+        if (g < best) best = g;
+        if (q < 1.0f && (*arg < 0 || q < rbest - kArgTie)) { rbest = q; *arg = e; }
     }
     return best;
 }
@@ -209,7 +224,7 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
         const int pm = __float_as_int(st.rec[(int64_t)st.b_list[bs0 + mid] * 4 + 2].y);
         if (pm < g) lo = mid + 1; else hi = mid;
     }
-    float best = 1.0f;
+    float best = 1.0f, rbest = 1.0f;
     *arg = -1;
     for (int e = lo; e < bc; ++e) {
         const int bpix = (int)st.b_list[bs0 + e];
@@ -218,8 +233,10 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
         const float4 r0 = st.rec[(int64_t)bpix * 4];
         const int lp = bpix - vi.px_off;
         const float dx = (float)(px - lp % vi.W) - r0.x, dy = (float)(py - lp / vi.W) - r0.y;
-        const float gm = gamma_fn(bdist(dx, dy), r2.z);
-        if (gm < best) { best = gm; *arg = e; }
+        const float d = bdist(dx, dy), q = __fdiv_rn(d, r2.z);
+        const float gm = gamma_fn(d, r2.z);
+        if (gm < best) best = gm;
+        if (q < 1.0f && (*arg < 0 || q < rbest - kArgTie)) { rbest = q; *arg = e; }
     }
     return best;
 }
@@ -328,11 +345,6 @@ __device__ __forceinline__ bool row_all(bool f, int lane) {
 }
 
 
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_f(float v) {
-    // bound_ctrl: lanes whose source is outside the row/wave read 0
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
-}
 
 // Row reduce-scatter of nine per-lane values: butterflies over lane bits 0
 // (quad_perm [1,0,3,2]), 1 (quad_perm [2,3,0,1]) and 3 (row_ror:8) each halve
@@ -643,7 +655,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         const float d = sqrtf(ddx * ddx + ddy * ddy);
                         const float dd = dgm * LN2 / sg * gam;
                         float *dst = st.dgauss + (int64_t)bpix * 12;
-                        if (d > 0.f) {
+                        if (d > kDKink) {
                             unsafeAtomicAdd(&dst[10], -dd * ddx / d);
                             unsafeAtomicAdd(&dst[11], -dd * ddy / d);
                         }
@@ -698,7 +710,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         const float sg = B.bs[e];
         const float d = sqrtf(ddx * ddx + ddy * ddy);
         const float dd = dg * LN2 / sg * gam;
-        if (d > 0.f) {
+        if (d > kDKink) {
             atomicAdd(&bacc[e][0], -dd * ddx / d);
             atomicAdd(&bacc[e][1], -dd * ddy / d);
         }

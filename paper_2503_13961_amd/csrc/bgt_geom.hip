@@ -193,7 +193,11 @@ __global__ void k_prim_setup(Consts k, PrimPtrs pr, float *patch) {
         for (int c = 0; c < 3; ++c) m[3 * r + c] = Rq[3 * r + c] * sc[c];
     const double rb = (double)k.r_ref / (double)pr.sharp[p];
     m[9] = rb * rb;
-    for (int i = patch_m_off(ncp) + 20; i < patch_dw(ncp); ++i) o[i] = 0.f;
+    float *raw = o + patch_q_off(ncp);
+    for (int d = 0; d < 4; ++d) raw[d] = pr.quat[(int64_t)d * k.T * k.P + p];
+    for (int d = 0; d < 3; ++d) raw[4 + d] = pr.log_scale[(int64_t)d * k.T * k.P + p];
+    raw[7] = pr.sharp[p];
+    for (int i = patch_q_off(ncp) + 8; i < patch_dw(ncp); ++i) o[i] = 0.f;
 }
 
 // ------------------------------------------------------------ projection

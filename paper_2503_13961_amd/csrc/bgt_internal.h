@@ -138,9 +138,11 @@ struct GradPtrs {
 //   [3 NCP, 6 NCP)  colour control points, [c][d]
 //   6 NCP           opacity, then one pad dword
 //   6 NCP + 2 ...   ten doubles: R(q) diag(e^s) row-major, then r_b^2
+//   6 NCP + 22 ...  raw quaternion (4), log-scale (3), sharpness (1)
 // rounded up to 16 dwords.
-__host__ __device__ constexpr int patch_dw(int ncp) { return (6 * ncp + 22 + 15) / 16 * 16; }
+__host__ __device__ constexpr int patch_dw(int ncp) { return (6 * ncp + 30 + 15) / 16 * 16; }
 __host__ __device__ constexpr int patch_m_off(int ncp) { return 6 * ncp + 2; }
+__host__ __device__ constexpr int patch_q_off(int ncp) { return 6 * ncp + 22; }
 
 struct VertRec {
     double x, y, iz;       // unsnapped projection and 1/z

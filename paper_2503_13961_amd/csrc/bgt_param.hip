@@ -7,14 +7,9 @@
 // pixel block; pixels of the same primitive are summed across the wave
 // (segmented by primitive id) before one atomic per parameter.
 #include "bgt_internal.h"
+#include "bgt_wave.h"
 
 namespace bgt {
-
-__device__ __forceinline__ float wsum(float x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
 
 template <int DEG>
 __device__ __forceinline__ void bern_f(float u, float v, float w, float *B) {
@@ -33,12 +28,31 @@ __device__ __forceinline__ void bern_f(float u, float v, float w, float *B) {
         }
 }
 
+// One chunk of up to 64 of a wave's NV per-lane values (from `value`, taken
+// on the lanes where `mine`): reduce-scattered over the wave, then each lane
+// holding a total adds it to its target.
+template <int BASE, int NV, typename V, typename T>
+__device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int gl, int lane) {
+    constexpr int N = NV - BASE < 64 ? NV - BASE : 64;
+    float v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = mine ? value(BASE + i) : 0.f;
+    wave_reduce_scatter<N>(v, lane);
+    const int j = BASE + scatter_index(lane);
+    if (j < BASE + N && v[0] != 0.f) unsafeAtomicAdd(target(j, gl), v[0]);
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimPtrs pr, const float *cams,
-                                                  StatePtrs st, GradPtrs gr) {
+                                                  StatePtrs st, GradPtrs gr, const float *__restrict__ patch) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    constexpr int PD = patch_dw(NCP), QO = patch_q_off(NCP);
+    // values per pixel: control points, colour control points, log-scale,
+    // quaternion, opacity, sharpness
+    constexpr int NV = 6 * NCP + 9;
     const int lane = threadIdx.x & 63;
-    const int wblock = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // global 8x8 block
+    // global 8x8 block (wave-uniform: its view is found with scalar loads)
+    const int wblock = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     // locate the view and pixel of this lane
     int pix = -1, prim = -1;
     float dS[3] = {0.f, 0.f, 0.f}, dcol[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
@@ -47,22 +61,56 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
 #pragma unroll
     for (int c = 0; c < NCP; ++c) B[c] = 0.f;
     bool act = false;
+    float g[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) g[i] = 0.f;
+    int v0 = 0;
     {
-        int v0, x0, y0;
+        int x0, y0;
         if (block8_pixel(vt, wblock, lane, v0, x0, y0)) pix = vt.v[v0].px_off + y0 * vt.v[v0].W + x0;
         if (pix >= 0 && (st.pflags[pix] & PF_VALID)) {
             // the blend sums: moments m0..m4 = sum dG (dx, dy, dx dx, dx dy, dy dy)
             // of dl/dG G, colour, opacity, boundary radius and position
-            const float *g = st.dgauss + (int64_t)pix * 12;
+            const float4 *gp = (const float4 *)(st.dgauss + (int64_t)pix * 12);
+            const float4 a = gp[0], b = gp[1], c = gp[2];
+            g[0] = a.x; g[1] = a.y; g[2] = a.z; g[3] = a.w; g[4] = b.x; g[5] = b.y;
+            g[6] = b.z; g[7] = b.w; g[8] = c.x; g[9] = c.y; g[10] = c.z; g[11] = c.w;
+            bool nz = false;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) nz = nz || g[i] != 0.f;
+            if (nz) {
+                act = true;
+                prim = st.I_tri[pix] / k.L2;
+            }
+        }
+    }
+    // the patches of this wave through the scalar unit: the wave walks its
+    // distinct ids and each lane keeps its own patch's points and attributes
+    float cp[3 * NCP], raw[8];
+#pragma unroll
+    for (int i = 0; i < 3 * NCP; ++i) cp[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) raw[i] = 0.f;
+    for (unsigned long long todo = __ballot(act); todo;) {
+        const int pu = __builtin_amdgcn_readlane(prim, __ffsll((long long)todo) - 1);
+        const bool mine = act && prim == pu;
+        todo &= ~__ballot(mine);
+        const float *src = patch + (int64_t)pu * PD;
+        if (mine) {
+#pragma unroll
+            for (int i = 0; i < 3 * NCP; ++i) cp[i] = src[i];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) raw[i] = src[QO + i];
+        }
+    }
+    {
+        if (act) {
             const float m0 = g[0], m1 = g[1];
             const float dqa = -0.5f * g[2], dqb = -g[3], dqc = -0.5f * g[4];
             dcol[0] = g[5]; dcol[1] = g[6]; dcol[2] = g[7];
             dop = g[8];
             const float dsig = g[9], dbx = g[10], dby = g[11];
-            if (m0 != 0.f || m1 != 0.f || dqa != 0.f || dqb != 0.f || dqc != 0.f || dcol[0] != 0.f ||
-                dcol[1] != 0.f || dcol[2] != 0.f || dop != 0.f || dsig != 0.f || dbx != 0.f || dby != 0.f) {
-                act = true;
-                prim = st.I_tri[pix] / k.L2;
+            {
                 const int p = prim;
                 const float2 uv = st.I_uv[pix];
                 bern_f<DEG>(uv.x, uv.y, 1.f - uv.x - uv.y, B);
@@ -70,9 +118,8 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
 #pragma unroll
                 for (int c = 0; c < NCP; ++c)
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) S[d] += B[c] * pr.ctrl[((int64_t)d * NCP + c) * k.P + p];
-                const int v = view_of_pixel(vt, pix);
-                const float *cm = cams + 16 * v;
+                    for (int d = 0; d < 3; ++d) S[d] += B[c] * cp[3 * c + d];
+                const float *cm = cams + 16 * v0;
                 float W[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) W[i] = cm[i];
@@ -88,7 +135,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 // rotation and scale of the patch (resolution-1 attribute map)
                 float q[4], qn = 0.f;
 #pragma unroll
-                for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
+                for (int d = 0; d < 4; ++d) { q[d] = raw[d]; qn += q[d] * q[d]; }
                 qn = sqrtf(qn);
                 const float qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
                 const float R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
@@ -96,7 +143,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                                     2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
                 float s[3];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] = __expf(pr.log_scale[(int64_t)d * k.T * k.P + p]);
+                for (int d = 0; d < 3; ++d) s[d] = __expf(raw[4 + d]);
                 float M[9];  // R diag(s)
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
@@ -159,7 +206,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 float dJ12 = dTm[3] * W[6] + dTm[4] * W[7] + dTm[5] * W[8];
                 if (dsig != 0.f) {
                     // sigma = 3 sqrt(lambda_max(r_b^2 J J^T + low-pass)), r_b = r_ref / sharpness
-                    const float sh = pr.sharp[p];
+                    const float sh = raw[7];
                     const float rb = k.r_ref / sh, r2 = rb * rb;
                     const float ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
                     const float mb = r2 * J02 * J12;
@@ -196,33 +243,31 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             }
         }
     }
-    // segmented reduction over the wave by primitive id, one atomic per value
-    unsigned long long pending = __ballot(act);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const int gl = __shfl(prim, leader, 64);
+    // per primitive present in the wave: a reduce-scatter of its NV sums over
+    // the wave, then one multi-lane atomic add per 64 values
+    auto value = [&](int j) -> float {  // j is a compile-time constant after unrolling
+        if (j < 3 * NCP) return B[j % NCP] * dS[j / NCP];
+        if (j < 6 * NCP) return B[(j - 3 * NCP) % NCP] * dcol[(j - 3 * NCP) / NCP];
+        const int r = j - 6 * NCP;
+        if (r < 3) return dls[r];
+        if (r < 7) return dq[r - 3];
+        return r == 7 ? dop : dsh;
+    };
+    auto target = [&](int j, int gl) -> float * {
+        if (j < 3 * NCP) return gr.ctrl + (int64_t)j * k.P + gl;  // [d][c] with j = d NCP + c
+        if (j < 6 * NCP) return gr.color + (int64_t)(j - 3 * NCP) * k.P + gl;
+        const int r = j - 6 * NCP;
+        if (r < 3) return gr.log_scale + (int64_t)r * k.T * k.P + gl;
+        if (r < 7) return gr.quat + (int64_t)(r - 3) * k.T * k.P + gl;
+        return r == 7 ? gr.opacity + gl : gr.sharp + gl;
+    };
+    for (unsigned long long pending = __ballot(act); pending;) {
+        const int gl = __builtin_amdgcn_readlane(prim, __ffsll((long long)pending) - 1);
         const bool mine = act && prim == gl;
-        const unsigned long long mm = __ballot(mine);
-        const bool one = __popcll(mm) == 1;
-        auto red = [&](float x, float *dst) {
-            const float vsum = one ? __shfl(x, leader, 64) : wsum(mine ? x : 0.f);
-            if (lane == leader && vsum != 0.f) unsafeAtomicAdd(dst, vsum);
-        };
-#pragma unroll
-        for (int c = 0; c < NCP; ++c)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                red(B[c] * dS[d], &gr.ctrl[((int64_t)d * NCP + c) * k.P + gl]);
-                red(B[c] * dcol[d], &gr.color[((int64_t)d * NCP + c) * k.P + gl]);
-            }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) red(dls[d], &gr.log_scale[(int64_t)d * k.T * k.P + gl]);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) red(dq[d], &gr.quat[(int64_t)d * k.T * k.P + gl]);
-        red(dop, &gr.opacity[gl]);
-        red(dsh, &gr.sharp[gl]);
-        pending &= ~mm;
-        if (mine) act = false;
+        pending &= ~__ballot(mine);
+        reduce_chunk<0, NV>(value, target, mine, gl, lane);
+        if constexpr (NV > 64) reduce_chunk<64, NV>(value, target, mine, gl, lane);
+        if constexpr (NV > 128) reduce_chunk<128, NV>(value, target, mine, gl, lane);
     }
 }
 
@@ -231,11 +276,11 @@ hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs
     const int nblk = vt.total_b8;
     dim3 grid((unsigned)((nblk + 3) / 4)), block(256);
     switch (k.degree) {
-        case 1: hipLaunchKernelGGL(k_param_bwd<1>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
-        case 2: hipLaunchKernelGGL(k_param_bwd<2>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
-        case 3: hipLaunchKernelGGL(k_param_bwd<3>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
-        case 4: hipLaunchKernelGGL(k_param_bwd<4>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
-        case 5: hipLaunchKernelGGL(k_param_bwd<5>, grid, block, 0, s, k, vt, pr, cams, st, gr); break;
+        case 1: hipLaunchKernelGGL(k_param_bwd<1>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
+        case 2: hipLaunchKernelGGL(k_param_bwd<2>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
+        case 3: hipLaunchKernelGGL(k_param_bwd<3>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
+        case 4: hipLaunchKernelGGL(k_param_bwd<4>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
+        case 5: hipLaunchKernelGGL(k_param_bwd<5>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -19,6 +19,11 @@ GRAD_TOL = 1e-3
 
 
 def _workload(name):
+    if name.startswith("degree"):  # small random scenes of every Bezier degree
+        n = int(name[len("degree"):])
+        sc = S.random_triangles(P=24, degree=n, seed=10 + n)
+        cams = S.make_cameras([(0.2, -0.1, 4.0), (2.5, 1.5, 2.8)], [(72, 56), (45, 61)])
+        return sc, cams
     if name == "ragged":
         sc = S.random_triangles(P=24, degree=3, seed=4)
         cams = S.make_cameras([(0.1, 0.2, 4.0), (3.0, 1.0, 2.5)], [(37, 29), (1, 17)])
@@ -28,7 +33,7 @@ def _workload(name):
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
-@pytest.mark.parametrize("name", ["tiny", "random64", "sphere_small", "ragged"])
+@pytest.mark.parametrize("name", ["tiny", "random64", "sphere_small", "ragged", "degree1", "degree5"])
 def test_stage_parity(name, tile):
     """Index map, boundary set, Gaussians, tile lists and images per view."""
     G.log(f"[stage_parity] workload={name} tile={tile}")
@@ -100,7 +105,7 @@ def test_full_size_sphere_image():
     assert err <= IMG_TOL
 
 
-@pytest.mark.parametrize("name", ["random64", "sphere_small", "ragged"])
+@pytest.mark.parametrize("name", ["random64", "sphere_small", "ragged", "degree1", "degree4", "degree5"])
 def test_gradient_parity(name):
     """Backward against the oracle's analytic FP64 gradient (itself pinned by
     finite differences) for an L1 loss to a random target."""

@@ -507,8 +507,8 @@ def test_degree_elevated_scene_renders_the_same(orc):
 
 # ---------------------------------------------------------------- backward
 
-def _fd_setup(orc):
-    sc = S.random_triangles(P=4, degree=2, seed=7, opacity=0.8)
+def _fd_setup(orc, degree=2):
+    sc = S.random_triangles(P=4, degree=degree, seed=7, opacity=0.8)
     sc.log_scale[:] += 1.2      # larger Gaussians: more overlap per pixel
     # wide boundary Gaussians (r_b = 1e-2 / s ~ 0.1) so the projected radius
     # depends on the off-axis Jacobian as much as on the low-pass
@@ -518,10 +518,13 @@ def _fd_setup(orc):
     return sc, cams.cams[0], 26, 21, cfg
 
 
-def test_gradient_matches_finite_differences(orc):
+@pytest.mark.parametrize("degree", [2, 1])
+def test_gradient_matches_finite_differences(orc, degree):
     """Backward (Suppl. C and the EWA chain) against FP64 central differences
-    of the oracle's own forward with I_id, I_uv and B frozen."""
-    sc, cam, W, Ht, cfg = _fd_setup(orc)
+    of the oracle's own forward with I_id, I_uv and B frozen.  Planar
+    (degree-1) patches put every boundary point on its own pixel centre, the
+    cone point of |q - b|, where the central difference is the 0 subgradient."""
+    sc, cam, W, Ht, cfg = _fd_setup(orc, degree)
     fr0 = orc.Frame(sc, cam, W, Ht, cfg)
     it, iu, isb, _ = fr0.raster()
     assert isb.sum() > 20
