@@ -345,11 +345,33 @@ __global__ void k_raster(Consts k, ViewTable vt, const VertRec *verts, unsigned 
     }
     const uint32_t tri = (uint32_t)(p * k.L2 + s);
     unsigned long long *zb = zbuf + vi.px_off;
-    for (int j = ts.j0; j <= ts.j1; ++j)
+    // The edge functions are affine in the pixel centre: stepped exactly in
+    // int64 from the bbox corner.
+    const int64_t px0 = 256 * (int64_t)ts.i0 + 128, py0 = 256 * (int64_t)ts.j0 + 128;
+    int64_t Er[3], sx[3], sy[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        Er[c] = edge_fn(ts.X[a], ts.Y[a], ts.X[b], ts.Y[b], px0, py0);
+        sx[c] = -256 * (ts.Y[b] - ts.Y[a]);  // +1 pixel in x
+        sy[c] = 256 * (ts.X[b] - ts.X[a]);   // +1 pixel in y
+    }
+    for (int j = ts.j0; j <= ts.j1; ++j) {
+        int64_t E0 = Er[0], E1 = Er[1], E2 = Er[2];
         for (int i = ts.i0; i <= ts.i1; ++i) {
-            const unsigned long long c = raster_pixel(ts, i, j, tri);
-            if (c) atomicMax(&zb[(int64_t)j * vi.W + i], c);
+            const bool in = (E0 > 0 || (E0 == 0 && ts.own[0])) && (E1 > 0 || (E1 == 0 && ts.own[1])) &&
+                            (E2 > 0 || (E2 == 0 && ts.own[2]));
+            if (in) {
+                const double key =
+                    fma((double)E2, ts.iz[2], fma((double)E1, ts.iz[1], (double)E0 * ts.iz[0])) / (double)ts.A;
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
+                const unsigned long long c = ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - tri);
+                atomicMax(&zb[(int64_t)j * vi.W + i], c);
+            }
+            E0 += sx[0]; E1 += sx[1]; E2 += sx[2];
         }
+        Er[0] += sy[0]; Er[1] += sy[1]; Er[2] += sy[2];
+    }
 }
 
 // Triangles with a large bounding box: one block each, pixels over threads.
