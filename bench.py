@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--workload", default="sphere2k_16v_800")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip timing the variant without blending coefficients")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=16, help="views in the oracle's timed sample")
     ap.add_argument("--profile-run", action="store_true",
@@ -342,6 +343,18 @@ def main():
                            "grad_max_rel_diff": gdiff}
         log(f"[bench] per-view: {ms_pv:.3f} ms/step; images equal {same}; grad diff {gdiff:.2e}")
         del pv, gpv
+    if not args.no_variants:
+        # the ablation variant without blending coefficients (w = 1): same
+        # scene and kernels, no boundary points, lists or gamma* maps
+        from paper_2503_13961_amd import native as N
+        vs = Step(Renderer(0, tile=tile, batch=batch, flags=N.BGT_FLAG_NO_BOUNDARY), scene.degree, params, camt, wh,
+                  target)
+        gv = capture(vs)
+        ms_v = time_replays(gv, args.steps, args.warmup)
+        out["variants"] = {"no_boundary": {"ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+                                           "what": "w = 1 for every Gaussian (ablation w/o B)"}}
+        log(f"[bench] variant without blending coefficients: {ms_v:.3f} ms/step")
+        del vs, gv
     stages = stage_profile(step)
     out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
     log(f"[bench] stages {out['stage_ms']}")

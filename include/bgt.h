@@ -55,6 +55,13 @@ typedef enum {
 } bgt_status;
 
 #define BGT_MAX_VIEWS 64
+
+/* bgt_config.flags.  BGT_FLAG_NO_BOUNDARY renders the variant without
+ * blending coefficients of the ablation study (Sec. 4.4, Table 3, "w/o B"):
+ * every Gaussian composites with w = 1 in Eq. 8, whatever primitive the pixel
+ * belongs to; no boundary points are extracted (the boundary set and its
+ * tile lists are empty) and the sharpness gradient is 0. */
+#define BGT_FLAG_NO_BOUNDARY 1
 #define BGT_MAX_DEGREE 5
 
 typedef struct bgt_ctx bgt_ctx;
@@ -89,7 +96,7 @@ typedef struct {
     int32_t tess_level;    /* L, sub-triangles per patch L^2, 1..8 (default 4) */
     int32_t tile;          /* blending tile side: 8, 16 or 32 (default 16) */
     int32_t batch;         /* Gaussians staged per LDS batch: 32, 64 or 128, at most tile*tile */
-    int32_t flags;         /* reserved, 0 */
+    int32_t flags;         /* BGT_FLAG_* bits (default 0) */
     float z_near;          /* cull distance along the optical axis (0.2) */
     float g_min;           /* Gaussian support: G >= g_min (2^-15) */
     float t_min;           /* stop once transmittance < t_min (2^-15) */

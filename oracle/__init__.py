@@ -73,7 +73,7 @@ class _Scene(C.Structure):
 class _Config(C.Structure):
     _fields_ = [("L", C.c_int), ("tile", C.c_int), ("z_near", C.c_double), ("g_min", C.c_double),
                 ("t_min", C.c_double), ("alpha_max", C.c_double), ("dilation", C.c_double),
-                ("r_ref", C.c_double), ("bg", C.c_double * 3)]
+                ("r_ref", C.c_double), ("bg", C.c_double * 3), ("no_boundary", C.c_int)]
 
 
 @dataclass
@@ -88,10 +88,11 @@ class Config:
     dilation: float = 0.3
     r_ref: float = 1e-2
     bg: tuple = (0.0, 0.0, 0.0)
+    no_boundary: bool = False  # the ablation variant without blending coefficients (w = 1)
 
     def c(self) -> _Config:
         return _Config(self.L, self.tile, self.z_near, self.g_min, self.t_min, self.alpha_max,
-                       self.dilation, self.r_ref, (C.c_double * 3)(*self.bg))
+                       self.dilation, self.r_ref, (C.c_double * 3)(*self.bg), int(self.no_boundary))
 
     @property
     def kappa2(self) -> float:

@@ -73,6 +73,7 @@ typedef struct {
     int L, tile;
     double z_near, g_min, t_min, alpha_max, dilation, r_ref;
     double bg[3];
+    int no_boundary;     /* the ablation variant without blending coefficients */
 } orc_config;
 
 /* per-pixel Gaussian record (doubles) */
@@ -359,6 +360,10 @@ static int prim_at(const orc_frame *f, int x, int y) {
 }
 
 static void find_boundary(orc_frame *f) {
+    if (f->cfg.no_boundary) {  /* no boundary points without blending coefficients */
+        memset(f->is_b, 0, (size_t)f->W * f->H);
+        return;
+    }
     for (int y = 0; y < f->H; ++y)
         for (int x = 0; x < f->W; ++x) {
             int h = prim_at(f, x, y), b = 0;
@@ -673,9 +678,14 @@ static int blend_pixel(const orc_frame *f, size_t pix, double *C, double *Tfin, 
         double power = r[GR_QA] * dx * dx + 2.0 * r[GR_QB] * dx * dy + r[GR_QC] * dy * dy;
         if (power > f->kappa2) continue;
         int g = (int)r[GR_PRIM];
-        int barg;
-        double gs = gamma_star(f, tile, g, qx, qy, &barg);
-        double w = (g == h) ? gs : 1.0 - gs;   /* Eq. 6 */
+        int barg = -1;
+        double gs = 1.0, w = 1.0;
+        /* Eq. 6; w = 1 throughout in the variant without blending
+         * coefficients (ablation study, "w/o B") */
+        if (!f->cfg.no_boundary) {
+            gs = gamma_star(f, tile, g, qx, qy, &barg);
+            w = (g == h) ? gs : 1.0 - gs;
+        }
         if (w <= 0.0) continue;
         double G = exp(-0.5 * power);
         double o = (double)f->sc.opacity[g];

@@ -68,6 +68,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     k.P = pr->num_prims;
     k.T = pr->attr_res * (pr->attr_res + 1) / 2;
     k.batch = c.batch;
+    k.flags = c.flags;
     k.z_near = c.z_near;
     k.g_min = c.g_min;
     k.t_min = c.t_min;

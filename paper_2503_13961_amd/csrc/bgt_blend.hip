@@ -428,6 +428,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     bool done = !inside;
     int last = gc;
     const float amax = k.alpha_max, tmin = k.t_min;
+    const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
     // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
     const float e_min = kE * k.kappa2;
     SlotPrefetch pf;
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         const float4 ex = S.e[kk];
                         const float4 c = S.c[kk];
                         const int g = pr.x, r = pr.y;  // uniform within the row
-                        const bool own = g == h;
+                        const bool own = g == h || nob;  // w = 1 for all without coefficients
                         const float dx = qx - m.x, dy = qy - m.y;
                         const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);
                         // w = 0 without a boundary point of g near this tile, or outside the support
@@ -573,6 +574,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int nlast = max_last;
     float T = 1.0f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
     const float amax = k.alpha_max;
+    const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
     const float e_min = kE * k.kappa2;
     const float LN2 = 0.69314718055994531f;
     SlotPrefetch pf;
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 const float2 m = S.m[wave][kk];
                 const float4 ex = S.e[kk];
                 const float4 c = S.c[kk];
-                const bool own = g == h;
+                const bool own = g == h || nob;  // w = 1 for all without coefficients
                 const float dx = qx - m.x, dy = qy - m.y;
                 const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
                 bool live = base + kk < mylast && (own || r != -1) && e >= e_min;

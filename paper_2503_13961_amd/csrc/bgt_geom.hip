@@ -442,7 +442,9 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
         tri = z == 0ull ? -1 : (int)(0xFFFFFFu - (uint32_t)(z & 0xFFFFFFull));
         // B: a neighbour shows another primitive (or the background)
         p = zb_prim(z, k.L2);
-        bnd = zb_prim(z0, k.L2) != p || zb_prim(z1, k.L2) != p || zb_prim(z2, k.L2) != p || zb_prim(z3, k.L2) != p;
+        // (none in the variant without blending coefficients)
+        bnd = !(k.flags & BGT_FLAG_NO_BOUNDARY) &&
+              (zb_prim(z0, k.L2) != p || zb_prim(z1, k.L2) != p || zb_prim(z2, k.L2) != p || zb_prim(z3, k.L2) != p);
     }
     // perspective-correct barycentrics in the winning flat triangle and the
     // Bernstein weights there (foreground lanes)

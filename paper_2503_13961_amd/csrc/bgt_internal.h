@@ -115,7 +115,7 @@ __device__ __forceinline__ void for_tiles_grouped(int tx0, int tx1, int ty0, int
 struct Consts {
     int32_t L, L2, VL, tile;
     int32_t degree, ncp, P, T;
-    int32_t batch, pad0;
+    int32_t batch, flags;  // flags: BGT_FLAG_* of the configuration
     float z_near, g_min, t_min, alpha_max, dilation, r_ref;
     float bg[3];
     float kappa2;          // 2 ln(1/g_min), float

@@ -30,7 +30,7 @@ bgt_status bgt_validate_config(const bgt_config *c) {
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return BGT_E_INVALID;
     if (c->batch != 32 && c->batch != 64 && c->batch != 128) return BGT_E_INVALID;
     if (c->batch > c->tile * c->tile) return BGT_E_INVALID;  // one loader thread per batch slot
-    if (c->flags != 0) return BGT_E_INVALID;
+    if ((c->flags & ~BGT_FLAG_NO_BOUNDARY) != 0) return BGT_E_INVALID;
     if (!(c->z_near > 0.0f) || !isfinite(c->z_near)) return BGT_E_INVALID;
     if (!(c->g_min > 0.0f && c->g_min < 1.0f)) return BGT_E_INVALID;
     if (!(c->t_min >= 0.0f && c->t_min < 1.0f)) return BGT_E_INVALID;

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libbgt.so")
 
 BGT_OK, BGT_E_INVALID, BGT_E_NOMEM, BGT_E_OVERFLOW, BGT_E_HIP, BGT_E_UNSUPPORTED = range(6)
 BGT_MAX_VIEWS = 64
+BGT_FLAG_NO_BOUNDARY = 1  # bgt_config.flags: the variant without blending coefficients (w = 1)
 BGT_STATE_FIELDS = 24
 STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey", "T_final", "last",
                      "verts", "g_count", "g_start", "g_cursor", "b_count", "b_start", "b_cursor",

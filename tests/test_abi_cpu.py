@@ -39,6 +39,9 @@ def test_default_config_is_valid_and_checks_reject_bad_values():
         assert N.bgt_validate_config(N.bgt_default_config(tile=tile, batch=batch)) == N.BGT_OK
     # one loader thread per batch slot: an 8-px tile has 64
     assert N.bgt_validate_config(N.bgt_default_config(tile=8, batch=128)) == N.BGT_E_INVALID
+    # flags: only the no-boundary bit is defined
+    assert N.bgt_validate_config(N.bgt_default_config(flags=N.BGT_FLAG_NO_BOUNDARY)) == N.BGT_OK
+    assert N.bgt_validate_config(N.bgt_default_config(flags=2)) == N.BGT_E_INVALID
 
 
 def test_prims_and_views_validation():

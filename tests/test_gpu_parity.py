@@ -145,6 +145,36 @@ def test_boundary_lists_over_the_lds_stage(W, tile):
         assert e <= GRAD_TOL, k
 
 
+@pytest.mark.parametrize("name", ["random64", "sphere_small", "degree3"])
+def test_without_coefficients_parity(name):
+    """The ablation variant without blending coefficients (w = 1 for every
+    Gaussian): no boundary points, index map bit-exact, image 1e-4 and
+    gradients 1e-3 against the oracle run in the same mode."""
+    from paper_2503_13961_amd import native as N
+    G.log(f"[no_boundary] workload={name}")
+    sc, cams = _workload(name)
+    cfg = G.oracle_config(tile=16, no_boundary=True)
+    img_ref, frames = oracle.render_views(sc, cams, cfg)
+    gi = G.l1_cotangent(img_ref, S.l1_target(cams.num_pixels))
+    g = G.run_gpu(sc, cams, tile=16, grad_images=gi, flags=N.BGT_FLAG_NO_BOUNDARY)
+    assert g["status"] == 0, g["counters"]
+    assert not (g["pflags"] & 2).any() and not g["b_count"].any()
+    po = G.view_offsets(cams)
+    for v, fr in enumerate(frames):
+        np.testing.assert_array_equal(g["I_tri"][po[v]:po[v + 1]], fr.raster()[0])
+    err = np.abs(g["images"] - img_ref).max()
+    G.log(f"    image max abs err {err:.3e}")
+    assert err <= IMG_TOL
+    ref = oracle.grad_views(frames, gi)
+    assert not g["grads"]["sharpness"].any()
+    for k in ref:
+        if k == "sharpness":
+            continue
+        e = G.grad_error(g["grads"][k], ref[k])
+        G.log(f"    {k}: {e:.3e}")
+        assert e <= GRAD_TOL, k
+
+
 def test_batched_equals_per_view():
     """All views in one call give bit-identical images to one call per view."""
     G.log("[batched_vs_per_view] sphere_small")

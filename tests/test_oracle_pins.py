@@ -443,6 +443,44 @@ def test_blending_invariants(orc):
         assert (img[pix] >= cols.min(0) - 1e-12).all() and (img[pix] <= cols.max(0) + 1e-12).all()
 
 
+def test_without_coefficients_composites_every_covering_gaussian(orc):
+    """Ablation variant without blending coefficients (Sec. 4.4, "w/o B"):
+    w = 1, so a pixel composites every Gaussian whose support reaches it, in
+    depth order, with alpha = min(alpha_max, o G) -- checked by brute force over
+    all Gaussians of the view (no tiles), and the boundary set is empty."""
+    sc, cams, _ = S.workload("tiny")
+    W, Ht = (int(v) for v in cams.wh[0])
+    cfg = orc.Config(tile=8, no_boundary=True)
+    fr = orc.Frame(sc, cams.cams[0], W, Ht, cfg)
+    _, _, isb, valid = fr.raster()
+    assert not isb.any()
+    assert not len(fr.lists(1)[1])
+    rec = fr.records()
+    G = orc.GR
+    gpix = np.nonzero(valid)[0]
+    key = np.array([int(np.float64(z).view(np.uint64)) >> 24 for z in rec[gpix, G["DEPTH"]]])
+    order = gpix[np.lexsort((gpix, key))]
+    img, T, _, nc = fr.render()
+    checked = 0
+    for pix in range(0, W * Ht, 7):
+        qx, qy = pix % W + 0.5, pix // W + 0.5
+        r = rec[order]
+        dx, dy = qx - r[:, G["MUX"]], qy - r[:, G["MUY"]]
+        pw = r[:, G["QA"]] * dx * dx + 2 * r[:, G["QB"]] * dx * dy + r[:, G["QC"]] * dy * dy
+        cov = pw <= cfg.kappa2
+        g, al, Tt, w = fr.trace(pix)
+        want = order[cov][:len(g)]
+        np.testing.assert_array_equal(g, want)
+        assert (w == 1.0).all()
+        o = sc.opacity[r[cov][:len(g), G["PRIM"]].astype(int)].astype(np.float64)
+        a = np.minimum(cfg.alpha_max, o * np.exp(-0.5 * pw[cov][:len(g)]))
+        assert np.allclose(al, a, rtol=0, atol=1e-15)
+        if T[pix] >= cfg.t_min:
+            assert len(g) == cov.sum()   # no early stop: every covering Gaussian
+        checked += len(g) > 0
+    assert checked > 30
+
+
 def test_tile_lists_cover_support(orc):
     """Rendering acceleration: each tile lists every Gaussian whose support
     reaches one of its pixel centres, front to back; boundary points listed
@@ -507,27 +545,29 @@ def test_degree_elevated_scene_renders_the_same(orc):
 
 # ---------------------------------------------------------------- backward
 
-def _fd_setup(orc, degree=2):
+def _fd_setup(orc, degree=2, no_boundary=False):
     sc = S.random_triangles(P=4, degree=degree, seed=7, opacity=0.8)
     sc.log_scale[:] += 1.2      # larger Gaussians: more overlap per pixel
     # wide boundary Gaussians (r_b = 1e-2 / s ~ 0.1) so the projected radius
     # depends on the off-axis Jacobian as much as on the low-pass
     sc.sharpness[:] = np.array([0.08, 0.1, 0.12, 0.15], np.float32)
     cams = S.make_cameras([(0.3, 0.2, 3.2)], [(26, 21)])
-    cfg = orc.Config(tile=8, g_min=1e-300, t_min=0.0)
+    cfg = orc.Config(tile=8, g_min=1e-300, t_min=0.0, no_boundary=no_boundary)
     return sc, cams.cams[0], 26, 21, cfg
 
 
-@pytest.mark.parametrize("degree", [2, 1])
-def test_gradient_matches_finite_differences(orc, degree):
+@pytest.mark.parametrize("degree,no_boundary", [(2, False), (1, False), (2, True)])
+def test_gradient_matches_finite_differences(orc, degree, no_boundary):
     """Backward (Suppl. C and the EWA chain) against FP64 central differences
     of the oracle's own forward with I_id, I_uv and B frozen.  Planar
     (degree-1) patches put every boundary point on its own pixel centre, the
-    cone point of |q - b|, where the central difference is the 0 subgradient."""
-    sc, cam, W, Ht, cfg = _fd_setup(orc, degree)
+    cone point of |q - b|, where the central difference is the 0 subgradient.
+    Without blending coefficients (w = 1) there is no boundary term, and the
+    sharpness gradient is 0."""
+    sc, cam, W, Ht, cfg = _fd_setup(orc, degree, no_boundary)
     fr0 = orc.Frame(sc, cam, W, Ht, cfg)
     it, iu, isb, _ = fr0.raster()
-    assert isb.sum() > 20
+    assert (isb.sum() == 0) if no_boundary else (isb.sum() > 20)
     rng = np.random.default_rng(1)
     gimg = rng.normal(size=(W * Ht, 3))
     an = fr0.grad(gimg)
@@ -537,7 +577,9 @@ def test_gradient_matches_finite_differences(orc, degree):
         return float((img * gimg).sum())
 
     checked = 0
-    for name in ("ctrl", "color_ctrl", "log_scale", "quat", "opacity", "sharpness"):
+    if no_boundary:
+        assert not an["sharpness"].any()
+    for name in ("ctrl", "color_ctrl", "log_scale", "quat", "opacity") + (() if no_boundary else ("sharpness",)):
         arr = getattr(sc, name)
         flat = np.argsort(-np.abs(an[name]).ravel())[:6]       # largest entries of each
         flat = np.concatenate([flat, rng.choice(arr.size, 3, replace=False)])
@@ -558,7 +600,7 @@ def test_gradient_matches_finite_differences(orc, degree):
                 continue   # a kink was crossed (gamma saturation / argmin switch)
             assert abs(fds[1] - a) <= 1e-5 * max(abs(a), 1e-2 * scale), (name, idx, fds, a)
             checked += 1
-    assert checked >= 45
+    assert checked >= (38 if no_boundary else 45)
 
 
 def test_gradient_closed_forms_single_gaussian(orc):
