@@ -57,7 +57,7 @@ typedef enum {
 #define BGT_MAX_VIEWS 64
 
 /* bgt_config.flags.  BGT_FLAG_NO_BOUNDARY renders the variant without
- * blending coefficients of the ablation study (Sec. 4.4, Table 3, "w/o B"):
+ * blending coefficients of the ablation study (Sec. 4.3, Table 3, "w/o B"):
  * every Gaussian composites with w = 1 in Eq. 8, whatever primitive the pixel
  * belongs to; no boundary points are extracted (the boundary set and its
  * tile lists are empty) and the sharpness gradient is 0. */

@@ -444,7 +444,7 @@ def test_blending_invariants(orc):
 
 
 def test_without_coefficients_composites_every_covering_gaussian(orc):
-    """Ablation variant without blending coefficients (Sec. 4.4, "w/o B"):
+    """Ablation variant without blending coefficients (Sec. 4.3, "w/o B"):
     w = 1, so a pixel composites every Gaussian whose support reaches it, in
     depth order, with alpha = min(alpha_max, o G) -- checked by brute force over
     all Gaussians of the view (no tiles), and the boundary set is empty."""
