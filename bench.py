@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the variant without blending coefficients")
+    ap.add_argument("--no-train-step", action="store_true",
+                    help="skip timing the optimisation step (fwd + Eq. 9 loss + bwd + Adam)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=16, help="views in the oracle's timed sample")
     ap.add_argument("--profile-run", action="store_true",
@@ -355,6 +357,30 @@ def main():
                                            "what": "w = 1 for every Gaussian (ablation w/o B)"}}
         log(f"[bench] variant without blending coefficients: {ms_v:.3f} ms/step")
         del vs, gv
+    if not args.no_train_step:
+        # one optimisation iteration of Sec. 3.3 on the same views: forward,
+        # Eq. 9 (L2 + D-SSIM) against the target images, backward, Adam
+        from paper_2503_13961_amd.train import TrainStep
+
+        class FixedSceneTrainStep(TrainStep):
+            """Restores the parameters before each step, so that every timed
+            replay renders the workload's scene (the random target would
+            otherwise drive the scales and opacities away from it)."""
+
+            def __call__(self):
+                for k, v in params.items():
+                    self.params[k].copy_(v)
+                return super().__call__()
+
+        ts = FixedSceneTrainStep(Renderer(0, tile=tile, batch=batch), scene.degree,
+                                 {k: v.clone() for k, v in params.items()}, camt, wh, target)
+        gt = capture(ts)
+        ms_t = time_replays(gt, args.steps, args.warmup)
+        out["training_step"] = {"ms_per_step": round(ms_t, 4), "value": round(npx / (ms_t * 1e-3) / 1e6, 2),
+                                "what": "forward + Eq. 9 loss (L2 + D-SSIM) + backward + Adam, one graph; "
+                                        "parameters restored from a copy first (six small device copies)"}
+        log(f"[bench] training step: {ms_t:.3f} ms")
+        del ts, gt
     stages = stage_profile(step)
     out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
     log(f"[bench] stages {out['stage_ms']}")

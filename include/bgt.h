@@ -164,6 +164,47 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
 bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters,
                      void *stream);
 
+/* ---- One training step around the renderer (Sec. 3.3) ----------------- */
+
+/* Photometric loss of Eq. 9, L = (1 - lambda) L2 + lambda D-SSIM (the paper
+ * uses lambda = 0.2), over the packed images of all views.  L2 is the mean
+ * squared error over every pixel and channel; D-SSIM = 1 - SSIM, SSIM being
+ * the mean structural similarity (Wang et al. 2004: 11x11 Gaussian window of
+ * standard deviation 1.5, C1 = 0.01^2, C2 = 0.03^2) per channel and view,
+ * with the window zero outside each view.  images and targets are
+ * [sum W H][3] device arrays; loss (device, float[3]) receives L, L2 and SSIM;
+ * grad_images (device, same layout as images, may be NULL) receives dL/dC,
+ * overwritten.  `workspace` is caller-owned device memory of at least
+ * bgt_loss_workspace_size bytes (three per-pixel maps and the partial sums).
+ * Only views->n_views and views->wh are read.  Deterministic: the sums are
+ * taken in a fixed order. */
+bgt_status bgt_loss_workspace_size(const bgt_views *views, size_t *bytes);
+bgt_status bgt_loss(bgt_ctx *ctx, const bgt_views *views, const float *images, const float *targets,
+                    float lambda, float *loss, float *grad_images, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
+/* One Adam update (Kingma and Ba 2015, Algorithm 1, with bias correction)
+ * of up to BGT_MAX_ADAM_GROUPS parameter arrays, each with its own learning
+ * rate: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), in FP64 with
+ * float storage.  The paper does not name its optimiser; Adam is the one of
+ * the 3DGS framework it builds on.  `groups` is a host array; every pointer in
+ * it is device memory of n floats (param, m and v updated in place, grad
+ * read).  `step` (device int32) holds the number of updates already taken:
+ * this call uses t = *step + 1 and then stores t, so a captured graph can
+ * replay it. */
+#define BGT_MAX_ADAM_GROUPS 8
+typedef struct {
+    float *param;
+    const float *grad;
+    float *m, *v;
+    int64_t n;
+    float lr;
+    int32_t reserved;
+} bgt_adam_group;
+bgt_status bgt_adam_step(bgt_ctx *ctx, const bgt_adam_group *groups, int32_t n_groups, float beta1,
+                         float beta2, float eps, int32_t *step, void *stream);
+
 /* Optional stage timing.  While enabled, the context records a pair of HIP
  * events around each stage it enqueues; bgt_stage_times synchronizes on the
  * last recorded event and returns (host ms[BGT_NUM_STAGES]) the duration of

@@ -220,6 +220,41 @@ struct StageTimer {
     }
 };
 
+// the loss pass's tile table and workspace split (three float maps, then
+// the per-workgroup partial sums)
+bgt_status loss_table(const bgt_views *vw, float lambda, LossTable &lt, int64_t &maps_bytes, int64_t &ws_bytes) {
+    if (!vw || vw->n_views < 1 || vw->n_views > BGT_MAX_VIEWS || !vw->wh) return BGT_E_INVALID;
+    if (!(lambda >= 0.f && lambda <= 1.f)) return BGT_E_INVALID;
+    memset(&lt, 0, sizeof(lt));
+    lt.n = vw->n_views;
+    int64_t px = 0, tiles = 0;
+    for (int v = 0; v < vw->n_views; ++v) {
+        const int W = vw->wh[2 * v], H = vw->wh[2 * v + 1];
+        if (W < 1 || H < 1 || W > 16384 || H > 16384) return BGT_E_INVALID;
+        int tx, nt;
+        loss_tiles(W, H, &tx, &nt);
+        lt.W[v] = W;
+        lt.H[v] = H;
+        lt.tiles_x[v] = tx;
+        lt.tile_off[v] = (int32_t)tiles;
+        lt.px_off[v] = (int32_t)px;
+        px += (int64_t)W * H;
+        tiles += nt;
+        if (px >= ((int64_t)1 << 30)) return BGT_E_INVALID;
+    }
+    lt.tile_off[vw->n_views] = (int32_t)tiles;
+    lt.total_tiles = (int32_t)tiles;
+    lt.total_px = (int32_t)px;
+    double sum = 0.0;
+    for (int k = 0; k < 11; ++k) sum += (lt.taps[k] = exp(-(double)((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)));
+    for (int k = 0; k < 11; ++k) lt.taps[k] /= sum;
+    lt.inv_n = 1.0 / (3.0 * (double)px);
+    lt.lam = lambda;
+    maps_bytes = align256(3 * 3 * px * (int64_t)sizeof(float));
+    ws_bytes = maps_bytes + align256(2 * tiles * (int64_t)sizeof(double));
+    return BGT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -405,6 +440,62 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         StageTimer tm(ctx, 5, st);
         if ((e = launch_param_bwd(k, sh.vt, pp, views->cams, sp, gp, st)) != hipSuccess) return hip_fail(ctx, e, "param_bwd");
     }
+    return BGT_OK;
+}
+
+bgt_status bgt_loss_workspace_size(const bgt_views *views, size_t *bytes) {
+    if (!bytes) return BGT_E_INVALID;
+    LossTable lt;
+    int64_t maps, ws;
+    bgt_status s = loss_table(views, 0.f, lt, maps, ws);
+    if (s != BGT_OK) return s;
+    *bytes = (size_t)ws;
+    return BGT_OK;
+}
+
+bgt_status bgt_loss(bgt_ctx *ctx, const bgt_views *views, const float *images, const float *targets,
+                    float lambda, float *loss, float *grad_images, void *workspace, size_t workspace_bytes,
+                    void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    LossTable lt;
+    int64_t maps, ws;
+    bgt_status s = loss_table(views, lambda, lt, maps, ws);
+    if (s != BGT_OK) return fail(ctx, s, "invalid views or lambda outside [0, 1]");
+    if (!images || !targets || !loss || !workspace) return fail(ctx, BGT_E_INVALID, "null buffer");
+    if ((int64_t)workspace_bytes < ws) return fail(ctx, BGT_E_NOMEM, "loss workspace too small");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    char *w = (char *)workspace;
+    hipError_t e = launch_loss(lt, images, targets, loss, grad_images, (float *)w, (double *)(w + maps),
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "loss");
+    return BGT_OK;
+}
+
+bgt_status bgt_adam_step(bgt_ctx *ctx, const bgt_adam_group *groups, int32_t n_groups, float beta1,
+                         float beta2, float eps, int32_t *step, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    if (n_groups < 0 || n_groups > BGT_MAX_ADAM_GROUPS || (n_groups > 0 && !groups) || !step)
+        return fail(ctx, BGT_E_INVALID, "bad group list or step counter");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f) || isinf(eps))
+        return fail(ctx, BGT_E_INVALID, "betas must lie in [0, 1) and eps be finite and >= 0");
+    AdamTable at;
+    memset(&at, 0, sizeof(at));
+    at.n = n_groups;
+    for (int g = 0; g < n_groups; ++g) {
+        const bgt_adam_group &G = groups[g];
+        if (G.n < 0 || !isfinite(G.lr)) return fail(ctx, BGT_E_INVALID, "bad group size or learning rate");
+        if (G.n > 0 && (!G.param || !G.grad || !G.m || !G.v)) return fail(ctx, BGT_E_INVALID, "null group array");
+        at.off[g + 1] = at.off[g] + G.n;
+        at.param[g] = G.param;
+        at.grad[g] = G.grad;
+        at.m[g] = G.m;
+        at.v[g] = G.v;
+        at.lr[g] = G.lr;
+    }
+    bgt_status s;
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    hipError_t e = launch_adam(at, beta1, beta2, eps, step, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "adam");
     return BGT_OK;
 }
 

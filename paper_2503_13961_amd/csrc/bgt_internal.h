@@ -183,6 +183,30 @@ __device__ __forceinline__ int pack16(int lo, int hi) { return (lo & 0xFFFF) | (
 __device__ __forceinline__ int lo16(int v) { return (int)(int16_t)(v & 0xFFFF); }
 __device__ __forceinline__ int hi16(int v) { return v >> 16; }
 
+// ---------------------------------------------------------------- training step
+
+constexpr double kSsimC1 = 0.01 * 0.01, kSsimC2 = 0.03 * 0.03;
+
+// views of the loss pass: 32x16 output tiles, view-major
+struct LossTable {
+    int32_t n, total_tiles, total_px, pad;
+    int32_t W[BGT_MAX_VIEWS], H[BGT_MAX_VIEWS], tiles_x[BGT_MAX_VIEWS];
+    int32_t tile_off[BGT_MAX_VIEWS + 1], px_off[BGT_MAX_VIEWS];
+    double taps[11];   // normalised Gaussian window, sigma 1.5
+    double inv_n;      // 1 / (3 * total pixels)
+    double lam;        // weight of the D-SSIM term
+};
+
+struct AdamTable {
+    int32_t n, pad;
+    int64_t off[BGT_MAX_ADAM_GROUPS + 1];  // element offsets of the groups
+    float *param[BGT_MAX_ADAM_GROUPS];
+    const float *grad[BGT_MAX_ADAM_GROUPS];
+    float *m[BGT_MAX_ADAM_GROUPS];
+    float *v[BGT_MAX_ADAM_GROUPS];
+    double lr[BGT_MAX_ADAM_GROUPS];
+};
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts, float *verts_out,
@@ -201,5 +225,9 @@ hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+void loss_tiles(int W, int H, int *tiles_x, int *tiles);
+hipError_t launch_loss(const LossTable &lt, const float *x, const float *y, float *loss, float *grad, float *maps,
+                       double *partial, hipStream_t s);
+hipError_t launch_adam(const AdamTable &at, double b1, double b2, double eps, int32_t *step, hipStream_t s);
 
 }  // namespace bgt

@@ -22,7 +22,7 @@ STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
            "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query", "bgt_profile",
-           "bgt_stage_times"]
+           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_adam_step"]
 BGT_NUM_STAGES = 6
 STAGE_NAMES = ["raster", "generation", "binning", "blend_fwd", "blend_bwd", "param_bwd"]
 
@@ -63,6 +63,13 @@ class bgt_config(C.Structure):
         return d
 
 
+class bgt_adam_group(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_float), ("reserved", C.c_int32)]
+
+
+BGT_MAX_ADAM_GROUPS = 8
+
 _lib = None
 
 
@@ -91,6 +98,10 @@ def lib():
         L.bgt_render_bwd.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), vp, vp, vp, C.c_size_t,
                                      C.POINTER(bgt_grads), vp]
         L.bgt_query.argtypes = [vp, vp, C.c_size_t, i64p, vp]
+        L.bgt_loss_workspace_size.argtypes = [C.POINTER(bgt_views), C.POINTER(C.c_size_t)]
+        L.bgt_loss.argtypes = [vp, C.POINTER(bgt_views), vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]
+        L.bgt_adam_step.argtypes = [vp, C.POINTER(bgt_adam_group), C.c_int32, C.c_float, C.c_float, C.c_float,
+                                    vp, vp]
         L.bgt_profile.argtypes = [vp, C.c_int]
         L.bgt_stage_times.argtypes = [vp, C.POINTER(C.c_float)]
         _lib = L
@@ -178,6 +189,26 @@ def bgt_query(ctx, state_ptr, state_bytes, stream=0):
     if st not in (BGT_OK, BGT_E_OVERFLOW):
         raise BgtError(st, bgt_last_error(ctx))
     return st, [int(x) for x in out]
+
+
+def bgt_loss_workspace_size(views: bgt_views) -> int:
+    n = C.c_size_t()
+    st = lib().bgt_loss_workspace_size(C.byref(views), C.byref(n))
+    if st != BGT_OK:
+        raise BgtError(st, "invalid views")
+    return int(n.value)
+
+
+def bgt_loss(ctx, views, images_ptr, targets_ptr, lam, loss_ptr, grad_images_ptr, workspace_ptr, workspace_bytes,
+             stream=0) -> int:
+    return _check(ctx, lib().bgt_loss(ctx, C.byref(views), images_ptr, targets_ptr, lam, loss_ptr, grad_images_ptr,
+                                      workspace_ptr, workspace_bytes, stream))
+
+
+def bgt_adam_step(ctx, groups, beta1, beta2, eps, step_ptr, stream=0) -> int:
+    """groups: sequence of bgt_adam_group (host)."""
+    arr = (bgt_adam_group * max(len(groups), 1))(*groups)
+    return _check(ctx, lib().bgt_adam_step(ctx, arr, len(groups), beta1, beta2, eps, step_ptr, stream))
 
 
 def bgt_profile(ctx, enable: bool) -> int:

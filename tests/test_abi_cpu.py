@@ -91,3 +91,39 @@ def test_create_rejects_bad_device_and_config():
     h = C.c_void_p()
     assert N.lib().bgt_create(None, -1, C.byref(h)) == N.BGT_OK
     N.bgt_destroy(h)
+
+
+def test_training_step_entry_points_validate_on_the_host():
+    """bgt_loss sizes its workspace (three float maps per pixel-channel and
+    two doubles per 32x16 tile) and both training entry points reject bad
+    arguments, and any work on a host-only context, before enqueuing."""
+    wh = np.array([[800, 800], [37, 29]], np.int32)
+    vw = N.make_views(wh, None)
+    px = 800 * 800 + 37 * 29
+    tiles = 25 * 50 + 2 * 2
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+    assert N.bgt_loss_workspace_size(vw) == a256(9 * 4 * px) + a256(16 * tiles)
+    with pytest.raises(N.BgtError):
+        N.bgt_loss_workspace_size(N.make_views(np.array([[0, 5]], np.int32), None))
+    ctx = N.bgt_create(N.bgt_default_config(), -1)
+    try:
+        ws = N.bgt_loss_workspace_size(vw)
+        for lam, nbytes, status in ((1.5, ws, N.BGT_E_INVALID), (0.2, ws - 1, N.BGT_E_NOMEM),
+                                    (0.2, ws, N.BGT_E_INVALID)):
+            with pytest.raises(N.BgtError) as e:
+                N.bgt_loss(ctx, vw, 1, 1, lam, 1, 1, 1, nbytes, 0)
+            assert e.value.status == status
+        assert "host-only" in N.bgt_last_error(ctx)
+        g = N.bgt_adam_group(1, 1, 1, 1, 10, 1e-3, 0)
+        for groups, b1, b2, eps in (([g], 1.0, 0.999, 1e-15), ([g], 0.9, -0.1, 1e-15), ([g], 0.9, 0.999, -1.0),
+                                    ([g] * 9, 0.9, 0.999, 1e-15),
+                                    ([N.bgt_adam_group(None, 1, 1, 1, 10, 1e-3, 0)], 0.9, 0.999, 1e-15),
+                                    ([g], 0.9, 0.999, 1e-15)):
+            with pytest.raises(N.BgtError) as e:
+                N.bgt_adam_step(ctx, groups, b1, b2, eps, 1, 0)
+            assert e.value.status == N.BGT_E_INVALID
+        assert "host-only" in N.bgt_last_error(ctx)
+    finally:
+        N.bgt_destroy(ctx)
