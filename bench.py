@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the variant without blending coefficients")
+    ap.add_argument("--no-densify", action="store_true", help="skip timing the splitting-and-pruning kernels")
     ap.add_argument("--no-train-step", action="store_true",
                     help="skip timing the optimisation step (fwd + Eq. 9 loss + bwd + Adam)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -381,6 +382,29 @@ def main():
                                         "parameters restored from a copy first (six small device copies)"}
         log(f"[bench] training step: {ms_t:.3f} ms")
         del ts, gt
+    if not args.no_densify:
+        # splitting and pruning: statistics of one rendered batch (every
+        # iteration), then the decision and the rebuilt arrays (every few
+        # hundred iterations in the paper's schedule)
+        from paper_2503_13961_amd import densify as DZ
+        pst = DZ.PrimStats(scene.num_prims, dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        pst.accumulate(r, scene.degree, params, camt, wh, step.state, target, step.grads)
+        e0.record()
+        for _ in range(args.steps):
+            pst.accumulate(r, scene.degree, params, camt, wh, step.state, target, step.grads)
+        e1.record()
+        new, action = DZ.densify(r, scene.degree, params, pst)
+        e2.record()
+        torch.cuda.synchronize()
+        acts = np.bincount(action.cpu().numpy(), minlength=3)
+        out["densify"] = {"stats_ms": round(e0.elapsed_time(e1) / args.steps, 4),
+                          "plan_apply_ms": round(e1.elapsed_time(e2), 4),
+                          "keep_split_prune": [int(x) for x in acts], "prims_after": int(new["opacity"].shape[0]),
+                          "what": "statistics of one 16-view batch (visibility, texels, edge prior, gradient "
+                                  "norms); decision + rebuilt arrays (includes one host read of the count)"}
+        log(f"[bench] densify: {out['densify']}")
+        del pst, new
     stages = stage_profile(step)
     out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
     log(f"[bench] stages {out['stage_ms']}")

@@ -205,6 +205,68 @@ typedef struct {
 bgt_status bgt_adam_step(bgt_ctx *ctx, const bgt_adam_group *groups, int32_t n_groups, float beta1,
                          float beta2, float eps, int32_t *step, void *stream);
 
+/* ---- Splitting and pruning (Sec. 3.3; implementation details) ---------- */
+
+/* Per-patch statistics, device arrays of P entries (views_seen: one), all
+ * accumulated across calls until the caller clears them (zero fill). */
+typedef struct {
+    int32_t *views_seen;   /* [1] views rendered since the last clear */
+    int32_t *vis_views;    /* views in which the patch wins at least one pixel */
+    uint64_t *tex;         /* visibility texture: bit s set once flat sub-triangle s was seen */
+    uint64_t *view_bits;   /* scratch of one call (left zero) */
+    float *grad_sum;       /* sum over visible calls of the mean |dL/dp| of the control points */
+    int32_t *grad_cnt;     /* number of those calls */
+    float *edge_sum;       /* sum of the edge prior over the patch's pixels */
+    int32_t *edge_cnt;     /* number of those pixels */
+} bgt_prim_stats;
+
+/* Thresholds of the implementation details (defaults in brackets). */
+typedef struct {
+    float tau_g;   /* split: mean position gradient above (0.0018) */
+    float tau_b;   /* split: mean edge prior above (13.0) */
+    float tau_v;   /* prune: visibility count ratio below (0.08) */
+    float tau_r;   /* prune: visibility texture ratio below (0.4) */
+    float tau_a;   /* prune: area below (3e-4) */
+    float tau_s;   /* prune: aspect ratio above (10) */
+} bgt_densify_config;
+void bgt_default_densify_config(bgt_densify_config *cfg);
+
+/* Adds one rendered batch of views to the statistics: for each view, the
+ * patches that win a pixel of I_id and the flat sub-triangles seen (from the
+ * forward pass's state of the same prims and views); with `targets` (the
+ * training images, [sum W H][3], or NULL) the edge prior, the Sobel gradient
+ * magnitude of their grey level on a 0..255 scale (0 on view borders),
+ * summed over each patch's pixels; with `grads` (the backward pass's
+ * output, or NULL) the mean |dL/dp| of each visible patch's control points.
+ * The tessellation level must be at most 8 (L^2 <= 64 texels). */
+bgt_status bgt_stats_accumulate(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                                const void *state, size_t state_bytes, const float *targets,
+                                const bgt_grads *grads, const bgt_prim_stats *stats, void *stream);
+
+/* Decision per patch (device action[P]: 0 keep, 1 split, 2 prune).  A patch
+ * is pruned when its visibility count ratio is below tau_v, its visibility
+ * texture ratio below tau_r, its area (four planar triangles through the
+ * corner and edge-midpoint surface points) below tau_a, or its aspect ratio
+ * (longest corner edge over the corner triangle's height on it) above
+ * tau_s; otherwise split when its mean position gradient exceeds tau_g or
+ * its mean edge prior exceeds tau_b.  dst_index[P] (device) receives each
+ * patch's first slot in the rebuilt arrays and count[0] (device) their
+ * length. */
+bgt_status bgt_densify_plan(bgt_ctx *ctx, const bgt_prims *prims, const bgt_prim_stats *stats,
+                            const bgt_densify_config *cfg, int32_t *action, int32_t *dst_index,
+                            int32_t *count, void *stream);
+
+/* Rebuilt parameter arrays (layouts as in bgt_prims, with dst_prims
+ * patches): kept patches are copied, a split patch is replaced by its four
+ * children cut at the edge midpoints (corner u, corner v, corner w, middle),
+ * whose control and colour nets are blossoms of the parent's, so each child
+ * reproduces its part of the parent exactly; the other attributes are
+ * copied.  dst_prims must equal the count from bgt_densify_plan (slots at or
+ * beyond it are not written).  dst holds device arrays written in full. */
+bgt_status bgt_densify_apply(bgt_ctx *ctx, const bgt_prims *prims, const int32_t *action,
+                             const int32_t *dst_index, int32_t dst_prims, const bgt_grads *dst,
+                             void *stream);
+
 /* Optional stage timing.  While enabled, the context records a pair of HIP
  * events around each stage it enqueues; bgt_stage_times synchronizes on the
  * last recorded event and returns (host ms[BGT_NUM_STAGES]) the duration of

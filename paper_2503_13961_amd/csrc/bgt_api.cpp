@@ -443,6 +443,106 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     return BGT_OK;
 }
 
+bgt_status bgt_stats_accumulate(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
+                                const void *state, size_t state_bytes, const float *targets,
+                                const bgt_grads *grads, const bgt_prim_stats *stats, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    Shape sh;
+    bgt_status s = make_shape(ctx, prims, views, sh);
+    if (s != BGT_OK) return s;
+    if (!state || !stats) return fail(ctx, BGT_E_INVALID, "null pointer argument");
+    if (!stats->views_seen || !stats->vis_views || !stats->tex || !stats->view_bits || !stats->grad_sum ||
+        !stats->grad_cnt || !stats->edge_sum || !stats->edge_cnt)
+        return fail(ctx, BGT_E_INVALID, "null statistics array");
+    if (grads && !grads->ctrl) return fail(ctx, BGT_E_INVALID, "null control-point gradient");
+    if (sh.k.L2 > 64) return fail(ctx, BGT_E_UNSUPPORTED, "visibility texture needs L^2 <= 64");
+    if (state_bytes < (size_t)sh.off[F_END]) return fail(ctx, BGT_E_NOMEM, "state buffer too small");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    const StatePtrs stp = state_ptrs(sh, const_cast<void *>(state));
+    StatsPtrs sp;
+    sp.views_seen = stats->views_seen;
+    sp.vis_views = stats->vis_views;
+    sp.tex = (unsigned long long *)stats->tex;
+    sp.view_bits = (unsigned long long *)stats->view_bits;
+    sp.grad_sum = stats->grad_sum;
+    sp.grad_cnt = stats->grad_cnt;
+    sp.edge_sum = stats->edge_sum;
+    sp.edge_cnt = stats->edge_cnt;
+    hipError_t e = launch_stats(sh.k, sh.vt, stp.I_tri, targets, grads ? grads->ctrl : nullptr, sp,
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stats");
+    return BGT_OK;
+}
+
+bgt_status bgt_densify_plan(bgt_ctx *ctx, const bgt_prims *prims, const bgt_prim_stats *stats,
+                            const bgt_densify_config *cfg, int32_t *action, int32_t *dst_index,
+                            int32_t *count, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    bgt_status s = bgt_validate_prims(prims, &ctx->cfg);
+    if (s != BGT_OK) return fail(ctx, s, "invalid or unsupported prims");
+    if (!stats || !cfg || !action || !dst_index || !count) return fail(ctx, BGT_E_INVALID, "null pointer argument");
+    if (!stats->views_seen || !stats->vis_views || !stats->tex || !stats->grad_sum || !stats->grad_cnt ||
+        !stats->edge_sum || !stats->edge_cnt)
+        return fail(ctx, BGT_E_INVALID, "null statistics array");
+    const float t[6] = {cfg->tau_g, cfg->tau_b, cfg->tau_v, cfg->tau_r, cfg->tau_a, cfg->tau_s};
+    for (float x : t)
+        if (!isfinite(x)) return fail(ctx, BGT_E_INVALID, "thresholds must be finite");
+    if (ctx->cfg.tess_level > 8) return fail(ctx, BGT_E_UNSUPPORTED, "visibility texture needs L^2 <= 64");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    Consts k;
+    memset(&k, 0, sizeof(k));
+    k.L = ctx->cfg.tess_level;
+    k.L2 = k.L * k.L;
+    k.degree = prims->degree;
+    k.ncp = (prims->degree + 1) * (prims->degree + 2) / 2;
+    k.P = prims->num_prims;
+    StatsPtrs sp;
+    sp.views_seen = stats->views_seen;
+    sp.vis_views = stats->vis_views;
+    sp.tex = (unsigned long long *)stats->tex;
+    sp.view_bits = (unsigned long long *)stats->view_bits;
+    sp.grad_sum = stats->grad_sum;
+    sp.grad_cnt = stats->grad_cnt;
+    sp.edge_sum = stats->edge_sum;
+    sp.edge_cnt = stats->edge_cnt;
+    const DensifyRule rule = {cfg->tau_g, cfg->tau_b, cfg->tau_v, cfg->tau_r, cfg->tau_a, cfg->tau_s};
+    hipError_t e = launch_plan(k, prims->ctrl, sp, rule, action, dst_index, count, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "densify plan");
+    return BGT_OK;
+}
+
+bgt_status bgt_densify_apply(bgt_ctx *ctx, const bgt_prims *prims, const int32_t *action,
+                             const int32_t *dst_index, int32_t dst_prims, const bgt_grads *dst,
+                             void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    bgt_status s = bgt_validate_prims(prims, &ctx->cfg);
+    if (s != BGT_OK) return fail(ctx, s, "invalid or unsupported prims");
+    if (!action || !dst_index || !dst) return fail(ctx, BGT_E_INVALID, "null pointer argument");
+    if (dst_prims < 0 || (int64_t)dst_prims > 4 * (int64_t)prims->num_prims)
+        return fail(ctx, BGT_E_INVALID, "dst_prims outside [0, 4 P]");
+    if (dst_prims > 0 && (!dst->ctrl || !dst->color_ctrl || !dst->log_scale || !dst->quat || !dst->opacity ||
+                          !dst->sharpness))
+        return fail(ctx, BGT_E_INVALID, "null output array");
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    if (dst_prims == 0) return BGT_OK;
+    Consts k;
+    memset(&k, 0, sizeof(k));
+    k.degree = prims->degree;
+    k.ncp = (prims->degree + 1) * (prims->degree + 2) / 2;
+    k.P = prims->num_prims;
+    k.T = prims->attr_res * (prims->attr_res + 1) / 2;
+    GradPtrs gp;
+    gp.ctrl = dst->ctrl;
+    gp.color = dst->color_ctrl;
+    gp.log_scale = dst->log_scale;
+    gp.quat = dst->quat;
+    gp.opacity = dst->opacity;
+    gp.sharp = dst->sharpness;
+    hipError_t e = launch_apply(k, prim_ptrs(prims), action, dst_index, dst_prims, gp, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "densify apply");
+    return BGT_OK;
+}
+
 bgt_status bgt_loss_workspace_size(const bgt_views *views, size_t *bytes) {
     if (!bytes) return BGT_E_INVALID;
     LossTable lt;

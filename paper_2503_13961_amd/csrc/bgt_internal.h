@@ -207,6 +207,22 @@ struct AdamTable {
     double lr[BGT_MAX_ADAM_GROUPS];
 };
 
+// ---------------------------------------------------------------- splitting and pruning
+
+struct StatsPtrs {
+    int32_t *views_seen;
+    int32_t *vis_views;
+    unsigned long long *tex, *view_bits;
+    float *grad_sum;
+    int32_t *grad_cnt;
+    float *edge_sum;
+    int32_t *edge_cnt;
+};
+
+struct DensifyRule {
+    double tau_g, tau_b, tau_v, tau_r, tau_a, tau_s;
+};
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts, float *verts_out,
@@ -228,6 +244,12 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void loss_tiles(int W, int H, int *tiles_x, int *tiles);
 hipError_t launch_loss(const LossTable &lt, const float *x, const float *y, float *loss, float *grad, float *maps,
                        double *partial, hipStream_t s);
+hipError_t launch_stats(const Consts &k, const ViewTable &vt, const int32_t *I_tri, const float *targets,
+                        const float *d_ctrl, const StatsPtrs &sp, hipStream_t s);
+hipError_t launch_plan(const Consts &k, const float *ctrl, const StatsPtrs &sp, const DensifyRule &rule,
+                       int32_t *action, int32_t *dst_index, int32_t *count, hipStream_t s);
+hipError_t launch_apply(const Consts &k, const PrimPtrs &src, const int32_t *action, const int32_t *dst_index,
+                        int Pd, const GradPtrs &dst, hipStream_t s);
 hipError_t launch_adam(const AdamTable &at, double b1, double b2, double eps, int32_t *step, hipStream_t s);
 
 }  // namespace bgt

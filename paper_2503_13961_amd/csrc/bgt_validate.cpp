@@ -24,6 +24,16 @@ void bgt_default_config(bgt_config *c) {
     c->bpair_factor = 2.0f;
 }
 
+void bgt_default_densify_config(bgt_densify_config *c) {
+    if (!c) return;
+    c->tau_g = 0.0018f;
+    c->tau_b = 13.0f;
+    c->tau_v = 0.08f;
+    c->tau_r = 0.4f;
+    c->tau_a = 3e-4f;
+    c->tau_s = 10.0f;
+}
+
 bgt_status bgt_validate_config(const bgt_config *c) {
     if (!c) return BGT_E_INVALID;
     if (c->tess_level < 1 || c->tess_level > 8) return BGT_E_INVALID;

@@ -22,7 +22,8 @@ STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
            "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query", "bgt_profile",
-           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_adam_step"]
+           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_adam_step",
+           "bgt_default_densify_config", "bgt_stats_accumulate", "bgt_densify_plan", "bgt_densify_apply"]
 BGT_NUM_STAGES = 6
 STAGE_NAMES = ["raster", "generation", "binning", "blend_fwd", "blend_bwd", "param_bwd"]
 
@@ -70,6 +71,17 @@ class bgt_adam_group(C.Structure):
 
 BGT_MAX_ADAM_GROUPS = 8
 
+
+class bgt_prim_stats(C.Structure):
+    _fields_ = [("views_seen", C.c_void_p), ("vis_views", C.c_void_p), ("tex", C.c_void_p),
+                ("view_bits", C.c_void_p), ("grad_sum", C.c_void_p), ("grad_cnt", C.c_void_p),
+                ("edge_sum", C.c_void_p), ("edge_cnt", C.c_void_p)]
+
+
+class bgt_densify_config(C.Structure):
+    _fields_ = [("tau_g", C.c_float), ("tau_b", C.c_float), ("tau_v", C.c_float), ("tau_r", C.c_float),
+                ("tau_a", C.c_float), ("tau_s", C.c_float)]
+
 _lib = None
 
 
@@ -102,6 +114,13 @@ def lib():
         L.bgt_loss.argtypes = [vp, C.POINTER(bgt_views), vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]
         L.bgt_adam_step.argtypes = [vp, C.POINTER(bgt_adam_group), C.c_int32, C.c_float, C.c_float, C.c_float,
                                     vp, vp]
+        L.bgt_default_densify_config.argtypes = [C.POINTER(bgt_densify_config)]
+        L.bgt_default_densify_config.restype = None
+        L.bgt_stats_accumulate.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_views), vp, C.c_size_t, vp,
+                                           C.POINTER(bgt_grads), C.POINTER(bgt_prim_stats), vp]
+        L.bgt_densify_plan.argtypes = [vp, C.POINTER(bgt_prims), C.POINTER(bgt_prim_stats),
+                                       C.POINTER(bgt_densify_config), vp, vp, vp, vp]
+        L.bgt_densify_apply.argtypes = [vp, C.POINTER(bgt_prims), vp, vp, C.c_int32, C.POINTER(bgt_grads), vp]
         L.bgt_profile.argtypes = [vp, C.c_int]
         L.bgt_stage_times.argtypes = [vp, C.POINTER(C.c_float)]
         _lib = L
@@ -209,6 +228,33 @@ def bgt_adam_step(ctx, groups, beta1, beta2, eps, step_ptr, stream=0) -> int:
     """groups: sequence of bgt_adam_group (host)."""
     arr = (bgt_adam_group * max(len(groups), 1))(*groups)
     return _check(ctx, lib().bgt_adam_step(ctx, arr, len(groups), beta1, beta2, eps, step_ptr, stream))
+
+
+def bgt_default_densify_config(**overrides) -> bgt_densify_config:
+    c = bgt_densify_config()
+    lib().bgt_default_densify_config(C.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def bgt_stats_accumulate(ctx, prims, views, state_ptr, state_bytes, targets_ptr, grads, stats: bgt_prim_stats,
+                         stream=0) -> int:
+    """grads: bgt_grads or None; targets_ptr: device pointer or None."""
+    return _check(ctx, lib().bgt_stats_accumulate(ctx, C.byref(prims), C.byref(views), state_ptr, state_bytes,
+                                                  targets_ptr, C.byref(grads) if grads is not None else None,
+                                                  C.byref(stats), stream))
+
+
+def bgt_densify_plan(ctx, prims, stats: bgt_prim_stats, cfg: bgt_densify_config, action_ptr, dst_index_ptr,
+                     count_ptr, stream=0) -> int:
+    return _check(ctx, lib().bgt_densify_plan(ctx, C.byref(prims), C.byref(stats), C.byref(cfg), action_ptr,
+                                              dst_index_ptr, count_ptr, stream))
+
+
+def bgt_densify_apply(ctx, prims, action_ptr, dst_index_ptr, dst_prims, dst: bgt_grads, stream=0) -> int:
+    return _check(ctx, lib().bgt_densify_apply(ctx, C.byref(prims), action_ptr, dst_index_ptr, dst_prims,
+                                               C.byref(dst), stream))
 
 
 def bgt_profile(ctx, enable: bool) -> int:
