@@ -57,7 +57,11 @@ def lib():
         L.orc_frame_render.restype = C.c_int
         L.orc_pixel_trace.argtypes = [C.c_void_p, C.c_int, C.c_int, ip, dp, dp, dp]
         L.orc_pixel_trace.restype = C.c_int
-        L.orc_frame_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_frame_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_sh_basis.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_sh_basis.restype = None
+        L.orc_theta.argtypes = [C.c_int, C.c_double, C.c_double, ip, dp]
+        L.orc_theta.restype = C.c_int
         L.orc_frame_grad.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -67,7 +71,8 @@ def lib():
 class _Scene(C.Structure):
     _fields_ = [("degree", C.c_int), ("num_prims", C.c_int), ("attr_res", C.c_int),
                 ("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p), ("log_scale", C.c_void_p),
-                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sharpness", C.c_void_p)]
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sharpness", C.c_void_p),
+                ("sh_degree", C.c_int), ("sh", C.c_void_p)]
 
 
 class _Config(C.Structure):
@@ -113,10 +118,28 @@ def _ip(a):
 
 def _c_scene(scene):
     keep = {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in scene.arrays().items()}
+    shd = int(getattr(scene, "sh_degree", 0))
     s = _Scene(scene.degree, scene.num_prims, scene.attr_res,
                *(keep[k].ctypes.data for k in ("ctrl", "color_ctrl", "log_scale", "quat",
-                                               "opacity", "sharpness")))
+                                               "opacity", "sharpness")),
+               shd, keep["sh"].ctypes.data if shd > 0 else None)
     return s, keep
+
+
+def theta(R, u, v):
+    """Texel indices and weights of Eq. 5's interpolation at (u, v)."""
+    ti, tw = np.zeros(3, np.int32), np.zeros(3)
+    n = lib().orc_theta(int(R), float(u), float(v), _ip(ti), _dp(tw))
+    return ti[:n], tw[:n]
+
+
+def sh_basis(D, d):
+    """Real SH of bands 1..D at the unit vector d and their Cartesian
+    gradients ([K], [K][3])."""
+    K = (D + 1) ** 2 - 1
+    Y, dY = np.zeros(max(K, 1)), np.zeros((max(K, 1), 3))
+    lib().orc_sh_basis(D, float(d[0]), float(d[1]), float(d[2]), _dp(Y), _dp(dY))
+    return Y[:K], dY[:K]
 
 
 def bernstein(n, u, v, w):
@@ -233,12 +256,16 @@ class Frame:
         ncp = (sc.degree + 1) * (sc.degree + 2) // 2
         P = sc.num_prims
         gi = np.ascontiguousarray(grad_image, dtype=np.float64).reshape(self.npx, 3)
+        T = sc.attr_res * (sc.attr_res + 1) // 2
+        shd = int(getattr(sc, "sh_degree", 0))
         out = dict(ctrl=np.zeros((3, ncp, P)), color_ctrl=np.zeros((3, ncp, P)),
-                   log_scale=np.zeros((3, 1, P)), quat=np.zeros((4, 1, P)),
+                   log_scale=np.zeros((3, T, P)), quat=np.zeros((4, T, P)),
                    opacity=np.zeros(P), sharpness=np.zeros(P))
+        if shd > 0:
+            out["sh"] = np.zeros((3, (shd + 1) ** 2 - 1, P))
         rc = lib().orc_frame_grad(self._h, _dp(gi), _dp(out["ctrl"]), _dp(out["color_ctrl"]),
                                   _dp(out["log_scale"]), _dp(out["quat"]), _dp(out["opacity"]),
-                                  _dp(out["sharpness"]))
+                                  _dp(out["sharpness"]), _dp(out["sh"]) if shd > 0 else None)
         if rc:
             raise ValueError("grad failed")
         return out

@@ -67,6 +67,8 @@
 typedef struct {
     int degree, num_prims, attr_res;
     const float *ctrl, *color_ctrl, *log_scale, *quat, *opacity, *sharpness;
+    int sh_degree;       /* bands 1..sh_degree of view-dependent colour (0: none) */
+    const float *sh;     /* [3][K][P], K = (sh_degree+1)^2 - 1 */
 } orc_scene;
 
 typedef struct {
@@ -386,16 +388,115 @@ static void quat_to_rot(const double *q, double *R) {
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
 }
 
-/* prim attributes from the resolution-1 attribute map (constant texel) */
-static void prim_attr(const orc_frame *f, int p, double *log_s, double *qn, double *qnorm) {
+/* Theta of Eq. 5: a resolution-R attribute map holds one texel per node
+ * (a, b), a + b <= R - 1, of the barycentric lattice of level R - 1 (texel
+ * index in the lattice order, a outer); (u, v) takes the linear
+ * interpolation of the three texels of the lattice triangle that contains
+ * it.  R = 1 is the single texel.  Returns the number of texels used. */
+static int theta_weights(int R, double u, double v, int *ti, double *tw) {
+    if (R == 1) { ti[0] = 0; tw[0] = 1.0; return 1; }
+    int m = R - 1;
+    double U = m * u, V = m * v;
+    int ia = (int)floor(U), ib = (int)floor(V);
+    if (ia < 0) ia = 0;
+    if (ib < 0) ib = 0;
+    if (ia > m - 1) ia = m - 1;
+    if (ib > m - 1) ib = m - 1;
+    if (ia + ib > m - 1) ib = m - 1 - ia;   /* on the hypotenuse */
+    double fu = U - ia, fv = V - ib;
+    if (fu + fv <= 1.0) {                   /* "up" lattice triangle */
+        ti[0] = lattice_index(m, ia, ib);     tw[0] = 1.0 - fu - fv;
+        ti[1] = lattice_index(m, ia + 1, ib); tw[1] = fu;
+        ti[2] = lattice_index(m, ia, ib + 1); tw[2] = fv;
+    } else {                                /* "down" lattice triangle */
+        ti[0] = lattice_index(m, ia + 1, ib);     tw[0] = 1.0 - fv;
+        ti[1] = lattice_index(m, ia, ib + 1);     tw[1] = 1.0 - fu;
+        ti[2] = lattice_index(m, ia + 1, ib + 1); tw[2] = fu + fv - 1.0;
+    }
+    return 3;
+}
+
+int orc_theta(int R, double u, double v, int32_t *ti, double *tw) {
+    int t[3];
+    int n = theta_weights(R, u, v, t, tw);
+    for (int e = 0; e < n; ++e) ti[e] = t[e];
+    return n;
+}
+
+/* rotation and scale of the Gaussian at (u, v) of patch p: the attribute
+ * maps interpolated by Theta (log-scales and the raw quaternion, which is
+ * then normalised) */
+static void pixel_attr(const orc_frame *f, int p, double u, double v, double *log_s, double *qn, double *qnorm,
+                       int *ti, double *tw, int *nt) {
     int P = f->sc.num_prims;
     int T = f->sc.attr_res * (f->sc.attr_res + 1) / 2;
-    for (int d = 0; d < 3; ++d) log_s[d] = f->sc.log_scale[((size_t)d * T) * P + p];
-    double q[4], nn = 0.0;
-    for (int d = 0; d < 4; ++d) { q[d] = f->sc.quat[((size_t)d * T) * P + p]; nn += q[d] * q[d]; }
+    *nt = theta_weights(f->sc.attr_res, u, v, ti, tw);
+    double q[4] = {0, 0, 0, 0}, nn = 0.0;
+    for (int d = 0; d < 3; ++d) log_s[d] = 0.0;
+    for (int e = 0; e < *nt; ++e) {
+        for (int d = 0; d < 3; ++d) log_s[d] += tw[e] * f->sc.log_scale[((size_t)d * T + ti[e]) * P + p];
+        for (int d = 0; d < 4; ++d) q[d] += tw[e] * f->sc.quat[((size_t)d * T + ti[e]) * P + p];
+    }
+    for (int d = 0; d < 4; ++d) nn += q[d] * q[d];
     nn = sqrt(nn);
     for (int d = 0; d < 4; ++d) qn[d] = q[d] / nn;
     *qnorm = nn;
+}
+
+/* Real spherical harmonics of bands 1..D (Condon-Shortley phase, m = -l..l
+ * within a band) at the unit vector d, and their Cartesian gradients
+ * dY[k][0..2] of the same polynomials.  The colour of a Gaussian adds
+ * sum_k Y_k(d) sh_k to Eq. 4's diffuse colour, d pointing from the camera
+ * centre to S_q. */
+static int sh_count(int D) { return (D + 1) * (D + 1) - 1; }
+
+static void sh_basis(int D, const double *d, double *Y, double (*dY)[3]) {
+    const double pi = 3.14159265358979323846;
+    double x = d[0], y = d[1], z = d[2];
+    int k = 0;
+    if (D >= 1) {
+        double c = sqrt(3.0 / (4.0 * pi));
+        Y[k] = -c * y; if (dY) { dY[k][0] = 0; dY[k][1] = -c; dY[k][2] = 0; } ++k;
+        Y[k] = c * z;  if (dY) { dY[k][0] = 0; dY[k][1] = 0; dY[k][2] = c; } ++k;
+        Y[k] = -c * x; if (dY) { dY[k][0] = -c; dY[k][1] = 0; dY[k][2] = 0; } ++k;
+    }
+    if (D >= 2) {
+        double a = 0.5 * sqrt(15.0 / pi), b = 0.25 * sqrt(5.0 / pi), c = 0.25 * sqrt(15.0 / pi);
+        Y[k] = a * x * y;  if (dY) { dY[k][0] = a * y; dY[k][1] = a * x; dY[k][2] = 0; } ++k;
+        Y[k] = -a * y * z; if (dY) { dY[k][0] = 0; dY[k][1] = -a * z; dY[k][2] = -a * y; } ++k;
+        Y[k] = b * (2 * z * z - x * x - y * y);
+        if (dY) { dY[k][0] = -2 * b * x; dY[k][1] = -2 * b * y; dY[k][2] = 4 * b * z; } ++k;
+        Y[k] = -a * x * z; if (dY) { dY[k][0] = -a * z; dY[k][1] = 0; dY[k][2] = -a * x; } ++k;
+        Y[k] = c * (x * x - y * y); if (dY) { dY[k][0] = 2 * c * x; dY[k][1] = -2 * c * y; dY[k][2] = 0; } ++k;
+    }
+    if (D >= 3) {
+        double a = 0.25 * sqrt(35.0 / (2 * pi)), b = 0.5 * sqrt(105.0 / pi), c = 0.25 * sqrt(21.0 / (2 * pi));
+        double e = 0.25 * sqrt(7.0 / pi), g = 0.25 * sqrt(105.0 / pi);
+        Y[k] = -a * y * (3 * x * x - y * y);
+        if (dY) { dY[k][0] = -6 * a * x * y; dY[k][1] = -a * (3 * x * x - 3 * y * y); dY[k][2] = 0; } ++k;
+        Y[k] = b * x * y * z;
+        if (dY) { dY[k][0] = b * y * z; dY[k][1] = b * x * z; dY[k][2] = b * x * y; } ++k;
+        Y[k] = -c * y * (4 * z * z - x * x - y * y);
+        if (dY) { dY[k][0] = 2 * c * x * y; dY[k][1] = -c * (4 * z * z - x * x - 3 * y * y); dY[k][2] = -8 * c * y * z; } ++k;
+        Y[k] = e * z * (2 * z * z - 3 * x * x - 3 * y * y);
+        if (dY) { dY[k][0] = -6 * e * x * z; dY[k][1] = -6 * e * y * z; dY[k][2] = e * (6 * z * z - 3 * x * x - 3 * y * y); } ++k;
+        Y[k] = -c * x * (4 * z * z - x * x - y * y);
+        if (dY) { dY[k][0] = -c * (4 * z * z - 3 * x * x - y * y); dY[k][1] = 2 * c * x * y; dY[k][2] = -8 * c * x * z; } ++k;
+        Y[k] = g * z * (x * x - y * y);
+        if (dY) { dY[k][0] = 2 * g * x * z; dY[k][1] = -2 * g * y * z; dY[k][2] = g * (x * x - y * y); } ++k;
+        Y[k] = -a * x * (x * x - 3 * y * y);
+        if (dY) { dY[k][0] = -a * (3 * x * x - 3 * y * y); dY[k][1] = 6 * a * x * y; dY[k][2] = 0; } ++k;
+    }
+}
+
+void orc_sh_basis(int D, double x, double y, double z, double *Y, double *dY) {
+    double d[3] = {x, y, z};
+    sh_basis(D, d, Y, (double (*)[3])dY);
+}
+
+/* camera centre in world coordinates, -R^T t */
+static void cam_centre(const double *cam, double *C) {
+    for (int c = 0; c < 3; ++c) C[c] = -(cam[c] * cam[9] + cam[3 + c] * cam[10] + cam[6 + c] * cam[11]);
 }
 
 static void gen_gaussians(orc_frame *f) {
@@ -417,6 +518,17 @@ static void gen_gaussians(orc_frame *f) {
         prim_points(f->sc.color_ctrl, ncp, P, p, cc);
         orc_surface(n, cp, u, v, w, S);   /* Eq. 3 */
         orc_surface(n, cc, u, v, w, col); /* Eq. 4 */
+        if (f->sc.sh_degree > 0) {        /* view-dependent colour of the patch's SH coefficients */
+            int K = sh_count(f->sc.sh_degree);
+            double C[3], dv[3], Y[15];
+            cam_centre(f->cam, C);
+            for (int c = 0; c < 3; ++c) dv[c] = S[c] - C[c];
+            double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            for (int c = 0; c < 3; ++c) dv[c] /= len;
+            sh_basis(f->sc.sh_degree, dv, Y, NULL);
+            for (int ch = 0; ch < 3; ++ch)
+                for (int k = 0; k < K; ++k) col[ch] += Y[k] * f->sc.sh[((size_t)ch * K + k) * P + p];
+        }
         cam_apply(f->cam, S, t);
         if (!(t[2] > f->cfg.z_near)) { f->is_b[pix] = 0; continue; }
         double tz = t[2];
@@ -425,9 +537,10 @@ static void gen_gaussians(orc_frame *f) {
         for (int a = 0; a < 2; ++a)
             for (int c = 0; c < 3; ++c)
                 Tm[3 * a + c] = J[3 * a] * Wc[c] + J[3 * a + 1] * Wc[3 + c] + J[3 * a + 2] * Wc[6 + c];
-        /* Eq. 5 with a resolution-1 map: constant rotation and scale */
-        double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9];
-        prim_attr(f, p, ls, qn, &qnorm);
+        /* Eq. 5: rotation and scale from the attribute maps at I_uv */
+        double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9], tw[3];
+        int ti[3], nt;
+        pixel_attr(f, p, u, v, ls, qn, &qnorm, ti, tw, &nt);
         quat_to_rot(qn, Rq);
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c) M[3 * a + c] = Rq[3 * a + c] * exp(ls[c]);
@@ -558,7 +671,8 @@ void orc_frame_free(orc_frame *f) {
 orc_frame *orc_frame_create(const orc_scene *sc, const float *cam, int W, int H,
                             const orc_config *cfg, const int32_t *I_tri_in, const double *I_uv_in) {
     if (!sc || !cam || !cfg || W <= 0 || H <= 0 || sc->degree < 1 || sc->degree > 5 ||
-        sc->num_prims <= 0 || cfg->L < 1 || cfg->tile <= 0 || sc->attr_res != 1)
+        sc->num_prims <= 0 || cfg->L < 1 || cfg->tile <= 0 || (sc->attr_res != 1 && sc->attr_res != 3) ||
+        sc->sh_degree < 0 || sc->sh_degree > 3 || (sc->sh_degree > 0 && !sc->sh))
         return NULL;
     orc_frame *f = (orc_frame *)calloc(1, sizeof(orc_frame));
     if (!f) return NULL;
@@ -755,10 +869,12 @@ static void atomic_add(double *p, double v) {
 /* gradient of the loss w.r.t. every parameter; grad_image is [H*W][3];
  * outputs (overwritten) use the scene layouts. */
 int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl, double *d_color,
-                   double *d_log_scale, double *d_quat, double *d_opacity, double *d_sharp) {
+                   double *d_log_scale, double *d_quat, double *d_opacity, double *d_sharp, double *d_sh) {
     if (!f || !grad_image) return ORC_EINVAL;
+    if (f->sc.sh_degree > 0 && !d_sh) return ORC_EINVAL;
     size_t npx = (size_t)f->W * f->H;
     int P = f->sc.num_prims, n = f->sc.degree, ncp = f->ncp;
+    int T = f->sc.attr_res * (f->sc.attr_res + 1) / 2, D = f->sc.sh_degree, K = sh_count(D);
     double *dg = (double *)calloc(npx * DG_N, sizeof(double));
     if (!dg) return ORC_ENOMEM;
     const double ln2 = log(2.0);
@@ -836,8 +952,9 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
     size_t nc3 = (size_t)3 * ncp * P;
     memset(d_ctrl, 0, nc3 * sizeof(double));
     memset(d_color, 0, nc3 * sizeof(double));
-    memset(d_log_scale, 0, (size_t)3 * P * sizeof(double));
-    memset(d_quat, 0, (size_t)4 * P * sizeof(double));
+    memset(d_log_scale, 0, (size_t)3 * T * P * sizeof(double));
+    memset(d_quat, 0, (size_t)4 * T * P * sizeof(double));
+    if (D > 0) memset(d_sh, 0, (size_t)3 * K * P * sizeof(double));
     memset(d_opacity, 0, (size_t)P * sizeof(double));
     memset(d_sharp, 0, (size_t)P * sizeof(double));
     const double *Wc = f->cam;
@@ -855,6 +972,25 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
             for (int ch = 0; ch < 3; ++ch)
                 d_color[((size_t)ch * ncp + c) * P + p] += B[c] * g[DG_CR + ch];
         d_opacity[p] += g[DG_O];
+        /* view-dependent colour: dl/dsh_k = Y_k dl/dc; the direction
+         * d = (S - C) / |S - C| also moves with S */
+        double dS_sh[3] = {0.0, 0.0, 0.0};
+        if (D > 0) {
+            double C[3], dv[3], Y[15], dY[15][3], gd[3] = {0.0, 0.0, 0.0};
+            cam_centre(f->cam, C);
+            for (int c = 0; c < 3; ++c) dv[c] = r[GR_SX + c] - C[c];
+            double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            for (int c = 0; c < 3; ++c) dv[c] /= len;
+            sh_basis(D, dv, Y, dY);
+            for (int ch = 0; ch < 3; ++ch)
+                for (int k = 0; k < K; ++k) {
+                    double coef = f->sc.sh[((size_t)ch * K + k) * P + p];
+                    d_sh[((size_t)ch * K + k) * P + p] += Y[k] * g[DG_CR + ch];
+                    for (int c = 0; c < 3; ++c) gd[c] += g[DG_CR + ch] * coef * dY[k][c];
+                }
+            double dot = dv[0] * gd[0] + dv[1] * gd[1] + dv[2] * gd[2];
+            for (int c = 0; c < 3; ++c) dS_sh[c] = (gd[c] - dv[c] * dot) / len;
+        }
         double tx = r[GR_TX], ty = r[GR_TY], tz = r[GR_TZ];
         double J[6] = {fx / tz, 0.0, -fx * tx / (tz * tz), 0.0, fy / tz, -fy * ty / (tz * tz)};
         double Tm[6];
@@ -869,8 +1005,9 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
         double dB = dQa * (2.0 * Bs * Cc / det2) + dQb * (-(A * Cc + Bs * Bs) / det2) + dQc * (2.0 * A * Bs / det2);
         double dC = dQa * (-Bs * Bs / det2) + dQb * (A * Bs / det2) + dQc * (-A * A / det2);
         /* Sigma2D = Tm Sigma3D Tm^T + low-pass, Tm = J W */
-        double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9], s[3];
-        prim_attr(f, p, ls, qn, &qnorm);
+        double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9], s[3], tw[3];
+        int ti[3], nt;
+        pixel_attr(f, p, u, v, ls, qn, &qnorm, ti, tw, &nt);
         quat_to_rot(qn, Rq);
         for (int c = 0; c < 3; ++c) s[c] = exp(ls[c]);
         for (int a = 0; a < 3; ++a)
@@ -903,7 +1040,7 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
         for (int c = 0; c < 3; ++c) {
             double ds = 0.0;
             for (int a = 0; a < 3; ++a) { ds += dM[3 * a + c] * Rq[3 * a + c]; dRq[3 * a + c] = dM[3 * a + c] * s[c]; }
-            d_log_scale[(size_t)c * P + p] += ds * s[c];
+            for (int e = 0; e < nt; ++e) d_log_scale[((size_t)c * T + ti[e]) * P + p] += tw[e] * ds * s[c];
         }
         {
             double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
@@ -913,7 +1050,9 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
             dq[2] = 2 * (-2 * y * dRq[0] + x * dRq[1] + w * dRq[2] + x * dRq[3] + z * dRq[5] - w * dRq[6] + z * dRq[7] - 2 * y * dRq[8]);
             dq[3] = 2 * (-2 * z * dRq[0] - w * dRq[1] + x * dRq[2] + w * dRq[3] - 2 * z * dRq[4] + y * dRq[5] + x * dRq[6] + y * dRq[7]);
             double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-            for (int c = 0; c < 4; ++c) d_quat[(size_t)c * P + p] += (dq[c] - qn[c] * dot) / qnorm;
+            for (int c = 0; c < 4; ++c)
+                for (int e = 0; e < nt; ++e)
+                    d_quat[((size_t)c * T + ti[e]) * P + p] += tw[e] * (dq[c] - qn[c] * dot) / qnorm;
         }
         double dJ[6];
         for (int a = 0; a < 2; ++a)
@@ -954,7 +1093,7 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
                 dJ[0] * (-fx / (tz * tz)) + dJ[2] * (2.0 * fx * tx / (tz * tz * tz)) +
                 dJ[4] * (-fy / (tz * tz)) + dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
         double dS[3];
-        for (int c = 0; c < 3; ++c) dS[c] = Wc[c] * dt[0] + Wc[3 + c] * dt[1] + Wc[6 + c] * dt[2];
+        for (int c = 0; c < 3; ++c) dS[c] = Wc[c] * dt[0] + Wc[3 + c] * dt[1] + Wc[6 + c] * dt[2] + dS_sh[c];
         /* dl/dp_ijk = dl/dS_q B^n_ijk(I_uv(q))  (Suppl. C) */
         for (int c = 0; c < ncp; ++c)
             for (int d = 0; d < 3; ++d) d_ctrl[((size_t)d * ncp + c) * P + p] += B[c] * dS[d];

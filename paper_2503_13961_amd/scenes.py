@@ -10,8 +10,11 @@ Layouts match the C ABI (structure-of-arrays, float32):
   ``i = 0..n`` outer, ``j = 0..n-i`` inner, ``k = n-i-j``; ``u`` pairs with
   ``i``, ``v`` with ``j`` and ``w`` with ``k``.
 * ``log_scale``: ``[3][T][P]``, ``quat``: ``[4][T][P]`` as ``(w, x, y, z)``,
-  with ``T = R(R+1)/2`` texels of the attribute map (``R = 1`` here).
+  with ``T = R(R+1)/2`` texels of the attribute map (``R`` 1 or 3; texel
+  ``t`` enumerates the nodes ``(a, b)``, ``a + b <= R - 1``, ``a`` outer).
 * ``opacity``, ``sharpness``: ``[P]``.
+* ``sh``: ``[3][K][P]``, the view-dependent colour's SH coefficients of bands
+  1..D (``K = (D+1)^2 - 1``, ``D = sh_degree``), absent when ``D = 0``.
 * cameras: ``cams`` float32 ``[V][16]`` = world-to-camera ``R`` (row-major
   3x3), ``t`` (3), ``fx, fy, cx, cy``; ``wh`` int32 ``[V][2]`` = width, height.
   Axes follow OpenCV (x right, y down, z forward); the vertical field of
@@ -50,21 +53,27 @@ class Scene:
     sharpness: np.ndarray     # [P] f32
     attr_res: int = 1
     name: str = ""
+    sh_degree: int = 0
+    sh: np.ndarray | None = None   # [3][K][P] f32 when sh_degree > 0
 
     @property
     def num_prims(self) -> int:
         return int(self.ctrl.shape[2])
 
     def arrays(self):
-        return dict(ctrl=self.ctrl, color_ctrl=self.color_ctrl,
-                    log_scale=self.log_scale, quat=self.quat,
-                    opacity=self.opacity, sharpness=self.sharpness)
+        d = dict(ctrl=self.ctrl, color_ctrl=self.color_ctrl,
+                 log_scale=self.log_scale, quat=self.quat,
+                 opacity=self.opacity, sharpness=self.sharpness)
+        if self.sh_degree > 0:
+            d["sh"] = self.sh
+        return d
 
     def copy(self) -> "Scene":
         return Scene(self.degree, self.ctrl.copy(), self.color_ctrl.copy(),
                      self.log_scale.copy(), self.quat.copy(),
                      self.opacity.copy(), self.sharpness.copy(),
-                     self.attr_res, self.name)
+                     self.attr_res, self.name, self.sh_degree,
+                     None if self.sh is None else self.sh.copy())
 
     def subset(self, idx) -> "Scene":
         idx = np.asarray(idx)
@@ -74,18 +83,20 @@ class Scene:
                      np.ascontiguousarray(self.quat[:, :, idx]),
                      np.ascontiguousarray(self.opacity[idx]),
                      np.ascontiguousarray(self.sharpness[idx]),
-                     self.attr_res, self.name + "[subset]")
+                     self.attr_res, self.name + "[subset]", self.sh_degree,
+                     None if self.sh is None else np.ascontiguousarray(self.sh[:, :, idx]))
 
     def save(self, path):
-        np.savez(path, degree=self.degree, attr_res=self.attr_res,
+        np.savez(path, degree=self.degree, attr_res=self.attr_res, sh_degree=self.sh_degree,
                  **self.arrays())
 
     @staticmethod
     def load(path) -> "Scene":
         z = np.load(path)  # allow_pickle stays False
+        shd = int(z["sh_degree"]) if "sh_degree" in z else 0
         return Scene(int(z["degree"]), z["ctrl"], z["color_ctrl"],
                      z["log_scale"], z["quat"], z["opacity"], z["sharpness"],
-                     int(z["attr_res"]))
+                     int(z["attr_res"]), "", shd, z["sh"] if shd > 0 else None)
 
 
 @dataclass
@@ -384,3 +395,38 @@ def workload(name: str, seed: int = 0):
 def l1_target(num_pixels: int, seed: int = 0) -> np.ndarray:
     """Random target image for the L1 cotangent, U[0,1] per pixel-channel."""
     return np.random.default_rng(1000 + seed).random((num_pixels, 3)).astype(np.float32)
+
+
+def num_sh(sh_degree: int) -> int:
+    """SH coefficients per colour channel in bands 1..D."""
+    return (sh_degree + 1) ** 2 - 1
+
+
+def with_attributes(scene: Scene, attr_res=3, sh_degree=3, seed=0, scale_jitter=0.2, quat_jitter=0.2,
+                    sh_std=0.1) -> Scene:
+    """The scene with resolution-`attr_res` rotation and scale maps and SH
+    colour of degree `sh_degree`.  Each texel takes its patch's log-scales
+    plus U(-scale_jitter, scale_jitter) and its quaternion plus
+    N(0, quat_jitter^2) per component; SH coefficients are N(0, sh_std^2)
+    divided by the band index.  Draw order: log-scales, quaternions, SH."""
+    rng = np.random.default_rng(seed)
+    P = scene.num_prims
+    T = attr_res * (attr_res + 1) // 2
+    out = scene.copy()
+    out.attr_res = attr_res
+    base_ls = scene.log_scale[:, 0, :].astype(np.float64)
+    base_q = scene.quat[:, 0, :].astype(np.float64)
+    ls = base_ls[:, None, :] + (rng.uniform(-scale_jitter, scale_jitter, size=(3, T, P)) if T > 1 else 0.0)
+    q = base_q[:, None, :] + (rng.normal(0.0, quat_jitter, size=(4, T, P)) if T > 1 else 0.0)
+    out.log_scale = np.ascontiguousarray(ls, dtype=np.float32)
+    out.quat = np.ascontiguousarray(q, dtype=np.float32)
+    out.sh_degree = sh_degree
+    if sh_degree > 0:
+        K = num_sh(sh_degree)
+        band = np.array([int(math.isqrt(k + 1)) for k in range(K)], np.float64)   # k + 1 = l^2 + (m + l)
+        out.sh = np.ascontiguousarray(rng.normal(0.0, sh_std, size=(3, K, P)) / band[None, :, None],
+                                      dtype=np.float32)
+    else:
+        out.sh = None
+    out.name = scene.name + f"_R{attr_res}_SH{sh_degree}"
+    return out

@@ -545,26 +545,31 @@ def test_degree_elevated_scene_renders_the_same(orc):
 
 # ---------------------------------------------------------------- backward
 
-def _fd_setup(orc, degree=2, no_boundary=False):
+def _fd_setup(orc, degree=2, no_boundary=False, attrs=False):
     sc = S.random_triangles(P=4, degree=degree, seed=7, opacity=0.8)
     sc.log_scale[:] += 1.2      # larger Gaussians: more overlap per pixel
     # wide boundary Gaussians (r_b = 1e-2 / s ~ 0.1) so the projected radius
     # depends on the off-axis Jacobian as much as on the low-pass
     sc.sharpness[:] = np.array([0.08, 0.1, 0.12, 0.15], np.float32)
+    if attrs:   # resolution-3 rotation and scale maps, SH colour of degree 3
+        sc = S.with_attributes(sc, attr_res=3, sh_degree=3, seed=3, sh_std=0.3)
     cams = S.make_cameras([(0.3, 0.2, 3.2)], [(26, 21)])
     cfg = orc.Config(tile=8, g_min=1e-300, t_min=0.0, no_boundary=no_boundary)
     return sc, cams.cams[0], 26, 21, cfg
 
 
-@pytest.mark.parametrize("degree,no_boundary", [(2, False), (1, False), (2, True)])
-def test_gradient_matches_finite_differences(orc, degree, no_boundary):
+@pytest.mark.parametrize("degree,no_boundary,attrs", [(2, False, False), (1, False, False), (2, True, False),
+                                                      (2, False, True)])
+def test_gradient_matches_finite_differences(orc, degree, no_boundary, attrs):
     """Backward (Suppl. C and the EWA chain) against FP64 central differences
     of the oracle's own forward with I_id, I_uv and B frozen.  Planar
     (degree-1) patches put every boundary point on its own pixel centre, the
     cone point of |q - b|, where the central difference is the 0 subgradient.
     Without blending coefficients (w = 1) there is no boundary term, and the
-    sharpness gradient is 0."""
-    sc, cam, W, Ht, cfg = _fd_setup(orc, degree, no_boundary)
+    sharpness gradient is 0.  With resolution-3 attribute maps the rotation
+    and scale gradients go to the texels of Eq. 5's interpolation, and the SH
+    colour adds its coefficients and the view direction's dependence on S_q."""
+    sc, cam, W, Ht, cfg = _fd_setup(orc, degree, no_boundary, attrs)
     fr0 = orc.Frame(sc, cam, W, Ht, cfg)
     it, iu, isb, _ = fr0.raster()
     assert (isb.sum() == 0) if no_boundary else (isb.sum() > 20)
@@ -579,7 +584,8 @@ def test_gradient_matches_finite_differences(orc, degree, no_boundary):
     checked = 0
     if no_boundary:
         assert not an["sharpness"].any()
-    for name in ("ctrl", "color_ctrl", "log_scale", "quat", "opacity") + (() if no_boundary else ("sharpness",)):
+    names = ("ctrl", "color_ctrl", "log_scale", "quat", "opacity") + (() if no_boundary else ("sharpness",))
+    for name in names + (("sh",) if attrs else ()):
         arr = getattr(sc, name)
         flat = np.argsort(-np.abs(an[name]).ravel())[:6]       # largest entries of each
         flat = np.concatenate([flat, rng.choice(arr.size, 3, replace=False)])
@@ -600,7 +606,7 @@ def test_gradient_matches_finite_differences(orc, degree, no_boundary):
                 continue   # a kink was crossed (gamma saturation / argmin switch)
             assert abs(fds[1] - a) <= 1e-5 * max(abs(a), 1e-2 * scale), (name, idx, fds, a)
             checked += 1
-    assert checked >= (38 if no_boundary else 45)
+    assert checked >= (38 if no_boundary else 45) + (8 if attrs else 0)
 
 
 def test_gradient_closed_forms_single_gaussian(orc):
