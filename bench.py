@@ -358,6 +358,17 @@ def main():
                                            "what": "w = 1 for every Gaussian (ablation w/o B)"}}
         log(f"[bench] variant without blending coefficients: {ms_v:.3f} ms/step")
         del vs, gv
+        # the paper's full model: resolution-3 rotation and scale maps, SH colour of degree 3
+        from paper_2503_13961_amd.render import scene_tensors
+        full = S.with_attributes(scene, attr_res=3, sh_degree=3)
+        vs = Step(Renderer(0, tile=tile, batch=batch), full.degree, scene_tensors(full, dev), camt, wh, target)
+        gv = capture(vs)
+        ms_v = time_replays(gv, args.steps, args.warmup)
+        out["variants"]["attr_maps_r3_sh3"] = {
+            "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+            "what": "resolution-3 rotation and scale maps and degree-3 SH colour (the paper's full model)"}
+        log(f"[bench] variant with resolution-3 maps and SH degree 3: {ms_v:.3f} ms/step")
+        del vs, gv
     if not args.no_train_step:
         # one optimisation iteration of Sec. 3.3 on the same views: forward,
         # Eq. 9 (L2 + D-SSIM) against the target images, backward, Adam

@@ -27,8 +27,11 @@
  *    double sum: i = 0..n outer, j = 0..n-i inner, k = n-i-j; u pairs with
  *    i, v with j, w with k.
  *  - ctrl, color_ctrl: [3][ncp][P]; log_scale: [3][T][P]; quat: [4][T][P]
- *    as (w,x,y,z), T = R(R+1)/2 texels of the attribute map (R = attr_res);
- *    opacity, sharpness: [P].
+ *    as (w,x,y,z), T = R(R+1)/2 texels of the attribute map (R = attr_res,
+ *    1 or 3; texel t enumerates the nodes (a, b), a + b <= R - 1, of the
+ *    barycentric lattice of level R - 1 at (u, v) = (a, b) / (R - 1), a
+ *    outer); opacity, sharpness: [P]; sh: [3][K][P], K = (D+1)^2 - 1 for
+ *    SH degree D = sh_degree (bands 1..D, m = -l..l within a band).
  *  - Camera v: 16 floats = world-to-camera rotation R (row-major 3x3),
  *    translation t (3), fx, fy, cx, cy.  Axes x right, y down, z forward;
  *    pixel (i, j) has its centre at (i + 0.5, j + 0.5).
@@ -68,18 +71,28 @@ typedef struct bgt_ctx bgt_ctx;
 
 /* BG-Triangle parameters (Sec. 3.1 control points p_ijk; Sec. 3.2 colour
  * control points p^c_ijk and attribute maps M_h; opacity o, Eq. 8).
- * `sharpness` s_g sets the boundary Gaussian scale r_b = r_ref / s_g. */
+ * `sharpness` s_g sets the boundary Gaussian scale r_b = r_ref / s_g.
+ * Eq. 5's attribute maps: a Gaussian's log-scales and raw quaternion are the
+ * linear interpolation, at its I_uv, of the three texels of the lattice
+ * triangle that contains it (R = 1: the single texel); the quaternion is then
+ * normalised.  SH colour (resolution-1 map): with D = sh_degree > 0 a
+ * Gaussian's colour is Eq. 4's diffuse colour plus sum_k Y_k(d) sh_k, Y_k
+ * the real spherical harmonics of bands 1..D (Condon-Shortley phase) and d
+ * the unit vector from the camera centre to S_q. */
 typedef struct {
     int32_t degree;      /* n, 1..BGT_MAX_DEGREE */
     int32_t num_prims;   /* P >= 1 */
-    int32_t attr_res;    /* R; this build implements R = 1 */
-    int32_t reserved;
+    int32_t attr_res;    /* R, 1 or 3 (the implementation details' rotation and scale maps) */
+    int32_t sh_degree;   /* D, 0..3 */
     const float *ctrl, *color_ctrl, *log_scale, *quat, *opacity, *sharpness;
+    const float *sh;     /* [3][K][P]; may be NULL when D = 0 */
 } bgt_prims;
 
-/* Gradients, same layouts as bgt_prims; every array is overwritten. */
+/* Gradients, same layouts as bgt_prims; every array is overwritten (`sh`
+ * only when the prims' sh_degree > 0; it may be NULL otherwise). */
 typedef struct {
     float *ctrl, *color_ctrl, *log_scale, *quat, *opacity, *sharpness;
+    float *sh;
 } bgt_grads;
 
 /* A batch of views rendered together in one call. */

@@ -21,7 +21,7 @@ import time
 import numpy as np
 import torch
 
-from .render import PARAM_NAMES, Renderer
+from .render import Renderer, param_names
 
 CANDIDATES = ((8, 32), (8, 64), (16, 32), (16, 64), (16, 128), (32, 32), (32, 64), (32, 128))
 
@@ -65,7 +65,7 @@ def time_candidate(degree, params, cams, wh, tile, batch, device=0, reps=5, warm
     g = torch.Generator(device="cpu").manual_seed(seed)
     # an L1-like cotangent: every pixel replays its whole list
     gi = (torch.randint(0, 2, images.shape, generator=g).float() * 2 - 1).div_(images.numel()).to(images.device)
-    grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+    grads = {k: torch.empty_like(params[k]) for k in param_names(params)}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * (reps + warmup))]
     for i in range(warmup + reps):
         ev[2 * i].record()

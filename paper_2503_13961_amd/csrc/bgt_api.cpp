@@ -67,6 +67,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     k.ncp = (pr->degree + 1) * (pr->degree + 2) / 2;
     k.P = pr->num_prims;
     k.T = pr->attr_res * (pr->attr_res + 1) / 2;
+    k.K = (pr->sh_degree + 1) * (pr->sh_degree + 1) - 1;
+    k.pdw = patch_dw(k.ncp, k.T, k.K);
     k.batch = c.batch;
     k.flags = c.flags;
     k.z_near = c.z_near;
@@ -125,7 +127,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
         sh.off[F_VERTS] = o;
         sh.wverts_off = align256(o + vbytes);
         sh.patch_off = align256(sh.wverts_off + wbytes);
-        o = align256(sh.patch_off + 4 * (int64_t)patch_dw(k.ncp) * k.P);
+        o = align256(sh.patch_off + 4 * (int64_t)k.pdw * k.P);
     }
     put(F_GCOUNT, 4 * NT);
     put(F_GSTART, 4 * NT);
@@ -188,6 +190,7 @@ PrimPtrs prim_ptrs(const bgt_prims *p) {
     r.quat = p->quat;
     r.opacity = p->opacity;
     r.sharp = p->sharpness;
+    r.sh = p->sh_degree > 0 ? p->sh : nullptr;
     return r;
 }
 
@@ -421,9 +424,12 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     gp.quat = grads->quat;
     gp.opacity = grads->opacity;
     gp.sharp = grads->sharpness;
+    gp.sh = grads->sh;
     const Consts &k = sh.k;
+    if (k.K > 0 && !gp.sh) return fail(ctx, BGT_E_INVALID, "null SH gradient array");
     hipError_t e = hipSuccess;
     const int64_t nc = 3LL * k.ncp * k.P;
+    if (k.K > 0 && (e = launch_fill_f32(gp.sh, 0.f, 3LL * k.K * k.P, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
     if ((e = launch_fill_f32(gp.ctrl, 0.f, nc, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.color, 0.f, nc, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.log_scale, 0.f, 3LL * k.T * k.P, st)) != hipSuccess ||
@@ -531,6 +537,8 @@ bgt_status bgt_densify_apply(bgt_ctx *ctx, const bgt_prims *prims, const int32_t
     k.ncp = (prims->degree + 1) * (prims->degree + 2) / 2;
     k.P = prims->num_prims;
     k.T = prims->attr_res * (prims->attr_res + 1) / 2;
+    k.K = (prims->sh_degree + 1) * (prims->sh_degree + 1) - 1;
+    if (k.K > 0 && !dst->sh) return fail(ctx, BGT_E_INVALID, "null SH output array");
     GradPtrs gp;
     gp.ctrl = dst->ctrl;
     gp.color = dst->color_ctrl;
@@ -538,6 +546,7 @@ bgt_status bgt_densify_apply(bgt_ctx *ctx, const bgt_prims *prims, const int32_t
     gp.quat = dst->quat;
     gp.opacity = dst->opacity;
     gp.sharp = dst->sharpness;
+    gp.sh = dst->sh;
     hipError_t e = launch_apply(k, prim_ptrs(prims), action, dst_index, dst_prims, gp, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "densify apply");
     return BGT_OK;

@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(1024) k_scan_slots(int P, int32_t *slots, int3
 // The rebuilt arrays: thread (p, c) writes the kept patch (c = 0) or child c
 // of a split patch at dst_index[p] + c.
 template <int DEG>
-__global__ void __launch_bounds__(kThreads) k_apply(int P, int T, PrimPtrs src, const int32_t *action,
+__global__ void __launch_bounds__(kThreads) k_apply(int P, int T, int K, PrimPtrs src, const int32_t *action,
                                                     const int32_t *dst_index, int Pd, GradPtrs dst) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
     const int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x;
@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(kThreads) k_apply(int P, int T, PrimPtrs src, 
         for (int k = 0; k < T; ++k) dst.quat[((int64_t)d * T + k) * Pd + slot] = src.quat[((int64_t)d * T + k) * P + p];
     dst.opacity[slot] = src.opacity[p];
     dst.sharp[slot] = src.sharp[p];
+    for (int j = 0; j < 3 * K; ++j) dst.sh[(int64_t)j * Pd + slot] = src.sh[(int64_t)j * P + p];
     // domain corners of the child: corner u, corner v, corner w, middle (half turn)
     const double corners[4][3][3] = {{{1, 0, 0}, {0.5, 0.5, 0}, {0.5, 0, 0.5}},
                                      {{0.5, 0.5, 0}, {0, 1, 0}, {0, 0.5, 0.5}},
@@ -298,7 +299,7 @@ static void apply_deg(const Consts &k, const PrimPtrs &src, const int32_t *actio
                       const GradPtrs &dst, hipStream_t s) {
     const int64_t n = 4 * (int64_t)k.P;
     hipLaunchKernelGGL(k_apply<DEG>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, k.P, k.T,
-                       src, action, dst_index, Pd, dst);
+                       k.K, src, action, dst_index, Pd, dst);
 }
 
 hipError_t launch_apply(const Consts &k, const PrimPtrs &src, const int32_t *action, const int32_t *dst_index,

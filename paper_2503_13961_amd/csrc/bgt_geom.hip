@@ -8,6 +8,7 @@
 // depth order, tile ranges) is computed in FP64.  The blending stages read
 // FP32 copies.
 #include "bgt_internal.h"
+#include "bgt_sh.h"
 
 namespace bgt {
 
@@ -165,7 +166,7 @@ __global__ void k_prim_setup(Consts k, PrimPtrs pr, float *patch) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= k.P) return;
     const int ncp = k.ncp;
-    float *o = patch + (int64_t)p * patch_dw(ncp);
+    float *o = patch + (int64_t)p * k.pdw;
     for (int c = 0; c < ncp; ++c)
         for (int d = 0; d < 3; ++d) {
             o[3 * c + d] = pr.ctrl[((int64_t)d * ncp + c) * k.P + p];
@@ -197,7 +198,20 @@ __global__ void k_prim_setup(Consts k, PrimPtrs pr, float *patch) {
     for (int d = 0; d < 4; ++d) raw[d] = pr.quat[(int64_t)d * k.T * k.P + p];
     for (int d = 0; d < 3; ++d) raw[4 + d] = pr.log_scale[(int64_t)d * k.T * k.P + p];
     raw[7] = pr.sharp[p];
-    for (int i = patch_q_off(ncp) + 8; i < patch_dw(ncp); ++i) o[i] = 0.f;
+    int end = patch_q_off(ncp) + 8;
+    if (k.T > 1 || k.K > 0) {
+        // every texel of the rotation and scale maps, then the SH coefficients
+        float *tx = o + patch_x_off(ncp);
+        for (int t = 0; t < k.T; ++t) {
+            for (int d = 0; d < 4; ++d) tx[7 * t + d] = pr.quat[((int64_t)d * k.T + t) * k.P + p];
+            for (int d = 0; d < 3; ++d) tx[7 * t + 4 + d] = pr.log_scale[((int64_t)d * k.T + t) * k.P + p];
+        }
+        float *shc = o + patch_sh_off(ncp, k.T);
+        for (int j = 0; j < k.K; ++j)
+            for (int c = 0; c < 3; ++c) shc[3 * j + c] = pr.sh[((int64_t)c * k.K + j) * k.P + p];
+        end = patch_sh_off(ncp, k.T) + 3 * k.K;
+    }
+    for (int i = end; i < k.pdw; ++i) o[i] = 0.f;
 }
 
 // ------------------------------------------------------------ projection
@@ -416,11 +430,12 @@ __device__ __forceinline__ void centre_range(double c, double r, int n, int &lo,
     hi = (int)b;
 }
 
-template <int DEG>
+template <int DEG, bool EXT>
 __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st,
                                              const float *__restrict__ patch) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
-    constexpr int PD = patch_dw(NCP), MO = patch_m_off(NCP);
+    constexpr int MO = patch_m_off(NCP);
+    const int PD = k.pdw;
     const int lane = threadIdx.x & 63;
     // the 8x8 block is wave-uniform, so its view is found with scalar loads
     const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -450,6 +465,8 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
     // Bernstein weights there (foreground lanes)
     double B[NCP];
     float2 uvo = make_float2(0.f, 0.f);
+    int ti[3] = {0, 0, 0};      // Eq. 5: texels of the pixel's lattice triangle and their weights
+    double tw[3] = {0.0, 0.0, 0.0};
     if (tri >= 0) {
         const int s = tri % k.L2;
         int m[3], ca[3], cb[3];
@@ -481,7 +498,19 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
         for (int c = 0; c < 3; ++c) { u += beta[c] * iws * lu[c]; vb += beta[c] * iws * lv[c]; }
         uvo = make_float2((float)u, (float)vb);
         bernstein<DEG>(u, vb, 1.0 - u - vb, B);
+        if constexpr (EXT) theta_weights<double>(k.T > 1 ? 3 : 1, u, vb, ti, tw);
     }
+    // camera centre -R^T t (for the SH view direction)
+    double Cc[3] = {0.0, 0.0, 0.0};
+    if constexpr (EXT) {
+        if (k.K > 0) {
+            const float *cm = cams + 16 * v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                Cc[c] = -((double)cm[c] * cm[9] + (double)cm[3 + c] * cm[10] + (double)cm[6 + c] * cm[11]);
+        }
+    }
+    double qi[4] = {0.0, 0.0, 0.0, 0.0}, lsi[3] = {0.0, 0.0, 0.0};  // interpolated raw quaternion, log-scales
     // Eq. 3 (position) and Eq. 4 (diffuse colour) with the patch records read
     // through the scalar unit: an 8x8 block sees a few patches, the wave walks
     // its distinct ids (wave-uniform), the lanes of each id sum their points
@@ -506,6 +535,29 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
 #pragma unroll
             for (int i = 0; i < 20; ++i) Rm[i] = src[MO + i];
             Rm[20] = src[6 * NCP];
+            if constexpr (EXT) {
+                // this pixel's texels of the rotation and scale maps
+                const float *tx = src + patch_x_off(NCP);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const float *tt = tx + 7 * ti[e];
+#pragma unroll
+                    for (int dd = 0; dd < 4; ++dd) qi[dd] += tw[e] * (double)tt[dd];
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) lsi[dd] += tw[e] * (double)tt[4 + dd];
+                }
+                if (k.K > 0) {
+                    // view-dependent colour: sum_j Y_j(d) sh_j, d from the camera centre to S_q
+                    double dv[3] = {S[0] - Cc[0], S[1] - Cc[1], S[2] - Cc[2]};
+                    const double il = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+                    double Y[15];
+                    sh_basis<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il, Y, nullptr);
+                    const float *shc = src + patch_sh_off(NCP, k.T);
+                    for (int j = 0; j < k.K; ++j)
+#pragma unroll
+                        for (int dd = 0; dd < 3; ++dd) col[dd] += Y[j] * (double)shc[3 * j + dd];
+                }
+            }
         }
     }
     if (act) {
@@ -515,6 +567,19 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             double Mv[10];
 #pragma unroll
             for (int i = 0; i < 10; ++i) Mv[i] = __hiloint2double(__float_as_int(Rm[2 * i + 1]), __float_as_int(Rm[2 * i]));
+            if constexpr (EXT) {
+                // Eq. 5 from the interpolated maps: M = R(q / |q|) diag(e^s) per pixel
+                const double qn = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+                const double w = qi[0] * qn, x = qi[1] * qn, y = qi[2] * qn, z = qi[3] * qn;
+                const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                                      2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                                      2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+                const double sc[3] = {exp(lsi[0]), exp(lsi[1]), exp(lsi[2])};
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) Mv[3 * r + cc] = Rq[3 * r + cc] * sc[cc];
+            }
             const float opa = Rm[20];
             const Cam c = load_cam(cams, v);
             double t[3];
@@ -617,14 +682,30 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s) {
     hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)((k.P + 255) / 256)), dim3(256), 0, s, k, pr, st.patch);
+    const bool ext = k.T > 1 || k.K > 0;  // resolution-3 maps or SH colour
     {
         dim3 grid((unsigned)((vt.total_b8 + 3) / 4)), block(256);  // one wave per 8x8 block
         switch (k.degree) {
-            case 1: hipLaunchKernelGGL(k_gen<1>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
-            case 2: hipLaunchKernelGGL(k_gen<2>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
-            case 3: hipLaunchKernelGGL(k_gen<3>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
-            case 4: hipLaunchKernelGGL(k_gen<4>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
-            case 5: hipLaunchKernelGGL(k_gen<5>, grid, block, 0, s, k, vt, pr, cams, st, st.patch); break;
+            case 1:
+                if (ext) hipLaunchKernelGGL((k_gen<1, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                else hipLaunchKernelGGL((k_gen<1, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                break;
+            case 2:
+                if (ext) hipLaunchKernelGGL((k_gen<2, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                else hipLaunchKernelGGL((k_gen<2, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                break;
+            case 3:
+                if (ext) hipLaunchKernelGGL((k_gen<3, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                else hipLaunchKernelGGL((k_gen<3, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                break;
+            case 4:
+                if (ext) hipLaunchKernelGGL((k_gen<4, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                else hipLaunchKernelGGL((k_gen<4, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                break;
+            case 5:
+                if (ext) hipLaunchKernelGGL((k_gen<5, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                else hipLaunchKernelGGL((k_gen<5, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
+                break;
             default: return hipErrorInvalidValue;
         }
     }

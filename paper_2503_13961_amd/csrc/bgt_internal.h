@@ -116,6 +116,7 @@ struct Consts {
     int32_t L, L2, VL, tile;
     int32_t degree, ncp, P, T;
     int32_t batch, flags;  // flags: BGT_FLAG_* of the configuration
+    int32_t K, pdw;        // SH coefficients per channel; dwords per patch record
     float z_near, g_min, t_min, alpha_max, dilation, r_ref;
     float bg[3];
     float kappa2;          // 2 ln(1/g_min), float
@@ -124,25 +125,32 @@ struct Consts {
 };
 
 struct PrimPtrs {
-    const float *ctrl, *color, *log_scale, *quat, *opacity, *sharp;
+    const float *ctrl, *color, *log_scale, *quat, *opacity, *sharp, *sh;
 };
 
 struct GradPtrs {
-    float *ctrl, *color, *log_scale, *quat, *opacity, *sharp;
+    float *ctrl, *color, *log_scale, *quat, *opacity, *sharp, *sh;
 };
 
-// per-view projected lattice vertex
 // Packed per-patch record in dwords, written by k_prim_setup so that the
 // generation pass reads a patch with a few scalar loads:
 //   [0, 3 NCP)      control points, [c][d]
 //   [3 NCP, 6 NCP)  colour control points, [c][d]
 //   6 NCP           opacity, then one pad dword
-//   6 NCP + 2 ...   ten doubles: R(q) diag(e^s) row-major, then r_b^2
-//   6 NCP + 22 ...  raw quaternion (4), log-scale (3), sharpness (1)
+//   6 NCP + 2 ...   ten doubles: R(q) diag(e^s) row-major of texel 0, then r_b^2
+//   6 NCP + 22 ...  raw quaternion (4), log-scale (3) of texel 0, sharpness (1)
+//   6 NCP + 30 ...  with resolution-3 maps or SH: every texel's raw quaternion
+//                   and log-scale ([t][7]), then the SH coefficients ([k][c])
 // rounded up to 16 dwords.
-__host__ __device__ constexpr int patch_dw(int ncp) { return (6 * ncp + 30 + 15) / 16 * 16; }
+__host__ __device__ constexpr int patch_dw(int ncp, int T = 1, int K = 0) {
+    return (6 * ncp + 30 + (T > 1 || K > 0 ? 7 * T + 3 * K : 0) + 15) / 16 * 16;
+}
 __host__ __device__ constexpr int patch_m_off(int ncp) { return 6 * ncp + 2; }
 __host__ __device__ constexpr int patch_q_off(int ncp) { return 6 * ncp + 22; }
+__host__ __device__ constexpr int patch_x_off(int ncp) { return 6 * ncp + 30; }
+__host__ __device__ constexpr int patch_sh_off(int ncp, int T) { return 6 * ncp + 30 + 7 * T; }
+
+// per-view projected lattice vertex
 
 struct VertRec {
     double x, y, iz;       // unsnapped projection and 1/z

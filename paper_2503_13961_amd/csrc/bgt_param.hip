@@ -7,6 +7,7 @@
 // pixel block; pixels of the same primitive are summed across the wave
 // (segmented by primitive id) before one atomic per parameter.
 #include "bgt_internal.h"
+#include "bgt_sh.h"
 #include "bgt_wave.h"
 
 namespace bgt {
@@ -39,17 +40,23 @@ __device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int
     for (int i = 0; i < N; ++i) v[i] = mine ? value(BASE + i) : 0.f;
     wave_reduce_scatter<N>(v, lane);
     const int j = BASE + scatter_index(lane);
-    if (j < BASE + N && v[0] != 0.f) unsafeAtomicAdd(target(j, gl), v[0]);
+    if (j < BASE + N && v[0] != 0.f) {
+        float *t = target(j, gl);
+        if (t) unsafeAtomicAdd(t, v[0]);
+    }
 }
 
-template <int DEG>
+template <int DEG, bool EXT>
 __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimPtrs pr, const float *cams,
                                                   StatePtrs st, GradPtrs gr, const float *__restrict__ patch) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
-    constexpr int PD = patch_dw(NCP), QO = patch_q_off(NCP);
-    // values per pixel: control points, colour control points, log-scale,
-    // quaternion, opacity, sharpness
-    constexpr int NV = 6 * NCP + 9;
+    constexpr int QO = patch_q_off(NCP);
+    const int PD = k.pdw;
+    // values per pixel: control points, colour control points, log-scales and
+    // quaternions of the map's texels (at most 6), opacity, sharpness, SH
+    // coefficients (at most 15 per channel)
+    constexpr int TM = EXT ? 6 : 1, KM = EXT ? 15 : 0;
+    constexpr int NV = 6 * NCP + 7 * TM + 2 + 3 * KM;
     const int lane = threadIdx.x & 63;
     // global 8x8 block (wave-uniform: its view is found with scalar loads)
     const int wblock = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -57,6 +64,12 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
     int pix = -1, prim = -1;
     float dS[3] = {0.f, 0.f, 0.f}, dcol[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dop = 0.f, dsh = 0.f;
+    float tw6[TM];  // this pixel's weight of each texel (Eq. 5)
+    float Yv[KM > 0 ? KM : 1];  // SH basis at its view direction
+#pragma unroll
+    for (int t = 0; t < TM; ++t) tw6[t] = 0.f;
+#pragma unroll
+    for (int j = 0; j < (KM > 0 ? KM : 1); ++j) Yv[j] = 0.f;
     float B[NCP];
 #pragma unroll
     for (int c = 0; c < NCP; ++c) B[c] = 0.f;
@@ -132,10 +145,35 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 float Tm[6];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { Tm[c] = J00 * W[c] + J02 * W[6 + c]; Tm[3 + c] = J11 * W[3 + c] + J12 * W[6 + c]; }
-                // rotation and scale of the patch (resolution-1 attribute map)
-                float q[4], qn = 0.f;
+                // rotation and scale: the patch's (resolution 1) or the
+                // interpolation of its maps at I_uv (Eq. 5)
+                const float *rec = patch + (int64_t)p * PD;
+                float q[4], qn = 0.f, lsv[3];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) { q[d] = raw[d]; qn += q[d] * q[d]; }
+                for (int d = 0; d < 4; ++d) q[d] = raw[d];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) lsv[d] = raw[4 + d];
+                if constexpr (EXT) {
+                    int ti[3];
+                    float tw[3];
+                    theta_weights<float>(k.T > 1 ? 3 : 1, uv.x, uv.y, ti, tw);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) q[d] = 0.f;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lsv[d] = 0.f;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        const float *tt = rec + patch_x_off(NCP) + 7 * ti[e];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) q[d] += tw[e] * tt[d];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) lsv[d] += tw[e] * tt[4 + d];
+#pragma unroll
+                        for (int t = 0; t < TM; ++t) tw6[t] += ti[e] == t ? tw[e] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) qn += q[d] * q[d];
                 qn = sqrtf(qn);
                 const float qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
                 const float R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
@@ -143,7 +181,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                                     2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
                 float s[3];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] = __expf(raw[4 + d]);
+                for (int d = 0; d < 3; ++d) s[d] = __expf(lsv[d]);
                 float M[9];  // R diag(s)
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
@@ -240,26 +278,66 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                         dJ11 * fy * iz2 + dJ12 * 2.f * fy * t[1] * iz3;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) dS[c] = W[c] * dt[0] + W[3 + c] * dt[1] + W[6 + c] * dt[2];
+                if constexpr (EXT) {
+                    if (k.K > 0) {
+                        // SH colour: dl/dsh_j = Y_j dl/dc; the view direction
+                        // d = (S - C) / |S - C| moves with S: dl/dS += (I - d d^T) g / |S - C|
+                        float C[3], dv[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) C[c] = -(W[c] * cm[9] + W[3 + c] * cm[10] + W[6 + c] * cm[11]);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) dv[c] = S[c] - C[c];
+                        const float len = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), il = 1.f / len;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) dv[c] *= il;
+                        float dY[15][3];
+                        sh_basis<float>(sh_degree_of(k.K), dv[0], dv[1], dv[2], Yv, dY);
+                        const float *shc = rec + patch_sh_off(NCP, k.T);
+                        float gd[3] = {0.f, 0.f, 0.f};
+                        for (int j = 0; j < k.K; ++j) {
+                            const float w = dcol[0] * shc[3 * j] + dcol[1] * shc[3 * j + 1] + dcol[2] * shc[3 * j + 2];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) gd[c] += w * dY[j][c];
+                        }
+                        const float dot = dv[0] * gd[0] + dv[1] * gd[1] + dv[2] * gd[2];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) dS[c] += (gd[c] - dv[c] * dot) * il;
+                    }
+                }
             }
         }
     }
     // per primitive present in the wave: a reduce-scatter of its NV sums over
     // the wave, then one multi-lane atomic add per 64 values
+    // value order: ctrl [d][c], colour [d][c], log-scale [d][t], quaternion
+    // [d][t], opacity, sharpness, SH [c][j]
     auto value = [&](int j) -> float {  // j is a compile-time constant after unrolling
         if (j < 3 * NCP) return B[j % NCP] * dS[j / NCP];
         if (j < 6 * NCP) return B[(j - 3 * NCP) % NCP] * dcol[(j - 3 * NCP) / NCP];
         const int r = j - 6 * NCP;
-        if (r < 3) return dls[r];
-        if (r < 7) return dq[r - 3];
-        return r == 7 ? dop : dsh;
+        if (r < 3 * TM) return EXT ? dls[r / TM] * tw6[r % TM] : dls[r];
+        if (r < 7 * TM) return EXT ? dq[(r - 3 * TM) / TM] * tw6[(r - 3 * TM) % TM] : dq[r - 3];
+        if (r == 7 * TM) return dop;
+        if (r == 7 * TM + 1) return dsh;
+        const int h = r - 7 * TM - 2;
+        return KM > 0 ? Yv[h % (KM > 0 ? KM : 1)] * dcol[h / (KM > 0 ? KM : 1)] : 0.f;
     };
     auto target = [&](int j, int gl) -> float * {
         if (j < 3 * NCP) return gr.ctrl + (int64_t)j * k.P + gl;  // [d][c] with j = d NCP + c
         if (j < 6 * NCP) return gr.color + (int64_t)(j - 3 * NCP) * k.P + gl;
         const int r = j - 6 * NCP;
-        if (r < 3) return gr.log_scale + (int64_t)r * k.T * k.P + gl;
-        if (r < 7) return gr.quat + (int64_t)(r - 3) * k.T * k.P + gl;
-        return r == 7 ? gr.opacity + gl : gr.sharp + gl;
+        if (r < 3 * TM) {
+            const int d = r / TM, t = r % TM;
+            return t < k.T ? gr.log_scale + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
+        }
+        if (r < 7 * TM) {
+            const int d = (r - 3 * TM) / TM, t = (r - 3 * TM) % TM;
+            return t < k.T ? gr.quat + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
+        }
+        if (r == 7 * TM) return gr.opacity + gl;
+        if (r == 7 * TM + 1) return gr.sharp + gl;
+        const int h = r - 7 * TM - 2, c = h / (KM > 0 ? KM : 1), jj = h % (KM > 0 ? KM : 1);
+        return jj < k.K ? gr.sh + ((int64_t)c * k.K + jj) * k.P + gl : nullptr;
     };
     for (unsigned long long pending = __ballot(act); pending;) {
         const int gl = __builtin_amdgcn_readlane(prim, __ffsll((long long)pending) - 1);
@@ -268,6 +346,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
         reduce_chunk<0, NV>(value, target, mine, gl, lane);
         if constexpr (NV > 64) reduce_chunk<64, NV>(value, target, mine, gl, lane);
         if constexpr (NV > 128) reduce_chunk<128, NV>(value, target, mine, gl, lane);
+        if constexpr (NV > 192) reduce_chunk<192, NV>(value, target, mine, gl, lane);
     }
 }
 
@@ -275,12 +354,28 @@ hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs
                             const StatePtrs &st, const GradPtrs &gr, hipStream_t s) {
     const int nblk = vt.total_b8;
     dim3 grid((unsigned)((nblk + 3) / 4)), block(256);
+    const bool ext = k.T > 1 || k.K > 0;  // resolution-3 maps or SH colour
     switch (k.degree) {
-        case 1: hipLaunchKernelGGL(k_param_bwd<1>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
-        case 2: hipLaunchKernelGGL(k_param_bwd<2>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
-        case 3: hipLaunchKernelGGL(k_param_bwd<3>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
-        case 4: hipLaunchKernelGGL(k_param_bwd<4>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
-        case 5: hipLaunchKernelGGL(k_param_bwd<5>, grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch); break;
+        case 1:
+            if (ext) hipLaunchKernelGGL((k_param_bwd<1, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            else hipLaunchKernelGGL((k_param_bwd<1, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            break;
+        case 2:
+            if (ext) hipLaunchKernelGGL((k_param_bwd<2, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            else hipLaunchKernelGGL((k_param_bwd<2, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            break;
+        case 3:
+            if (ext) hipLaunchKernelGGL((k_param_bwd<3, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            else hipLaunchKernelGGL((k_param_bwd<3, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            break;
+        case 4:
+            if (ext) hipLaunchKernelGGL((k_param_bwd<4, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            else hipLaunchKernelGGL((k_param_bwd<4, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            break;
+        case 5:
+            if (ext) hipLaunchKernelGGL((k_param_bwd<5, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            else hipLaunchKernelGGL((k_param_bwd<5, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

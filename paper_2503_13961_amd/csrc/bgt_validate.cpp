@@ -59,7 +59,10 @@ bgt_status bgt_validate_prims(const bgt_prims *p, const bgt_config *c) {
     if (p->degree < 1 || p->degree > BGT_MAX_DEGREE) return BGT_E_INVALID;
     if (p->num_prims < 1) return BGT_E_INVALID;
     if (p->attr_res < 1) return BGT_E_INVALID;
-    if (p->attr_res != 1) return BGT_E_UNSUPPORTED;
+    if (p->attr_res != 1 && p->attr_res != 3) return BGT_E_UNSUPPORTED;
+    if (p->sh_degree < 0) return BGT_E_INVALID;
+    if (p->sh_degree > 3) return BGT_E_UNSUPPORTED;
+    if (p->sh_degree > 0 && !p->sh) return BGT_E_INVALID;
     // per-view sub-triangle ids live in 24 bits of the z-buffer word
     const int64_t L2 = (int64_t)c->tess_level * c->tess_level;
     if ((int64_t)p->num_prims * L2 >= (int64_t)1 << 24) return BGT_E_INVALID;

@@ -6,7 +6,7 @@ from __future__ import annotations
 import torch
 
 from . import native as N
-from .render import PARAM_NAMES, Renderer, _ptr, _stream
+from .render import Renderer, _grad_ptrs, _ptr, _stream, param_names
 
 
 class PrimStats:
@@ -31,7 +31,7 @@ class PrimStats:
         """One rendered batch: `state` from renderer.forward of the same
         params and views, `targets` the training images, `grads` the
         backward pass's output (dict), either may be None."""
-        g = None if grads is None else N.make_grads(*(_ptr(grads[k]) for k in PARAM_NAMES))
+        g = None if grads is None else _grad_ptrs(grads)
         N.bgt_stats_accumulate(renderer.ctx, renderer.prims_struct(degree, params), renderer.views_struct(cams, wh),
                                _ptr(state), state.numel(), None if targets is None else _ptr(targets), g,
                                self.struct(), _stream())
@@ -51,12 +51,12 @@ def plan(renderer: Renderer, degree, params, stats: PrimStats, **thresholds):
 def apply(renderer: Renderer, degree, params, action, dst_index, count) -> dict:
     """The rebuilt parameter tensors (count patches)."""
     out = {}
-    for k in PARAM_NAMES:
+    for k in param_names(params):
         shape = list(params[k].shape)
         shape[-1] = count
         out[k] = torch.empty(shape, dtype=torch.float32, device=renderer.device)
     N.bgt_densify_apply(renderer.ctx, renderer.prims_struct(degree, params), _ptr(action), _ptr(dst_index), count,
-                        N.make_grads(*(_ptr(out[k]) for k in PARAM_NAMES)), _stream())
+                        _grad_ptrs(out), _stream())
     return out
 
 

@@ -36,14 +36,15 @@ class BgtError(RuntimeError):
 
 class bgt_prims(C.Structure):
     _fields_ = [("degree", C.c_int32), ("num_prims", C.c_int32), ("attr_res", C.c_int32),
-                ("reserved", C.c_int32), ("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p),
+                ("sh_degree", C.c_int32), ("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p),
                 ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
-                ("sharpness", C.c_void_p)]
+                ("sharpness", C.c_void_p), ("sh", C.c_void_p)]
 
 
 class bgt_grads(C.Structure):
     _fields_ = [("ctrl", C.c_void_p), ("color_ctrl", C.c_void_p), ("log_scale", C.c_void_p),
-                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sharpness", C.c_void_p)]
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sharpness", C.c_void_p),
+                ("sh", C.c_void_p)]
 
 
 class bgt_views(C.Structure):
@@ -269,9 +270,11 @@ def bgt_stage_times(ctx) -> dict:
 
 # ------------------------------------------------------------ struct builders
 
-def make_prims(degree, num_prims, ctrl, color_ctrl, log_scale, quat, opacity, sharpness, attr_res=1):
+def make_prims(degree, num_prims, ctrl, color_ctrl, log_scale, quat, opacity, sharpness, attr_res=1, sh_degree=0,
+               sh=None):
     """Pointers are integers (device addresses)."""
-    return bgt_prims(degree, num_prims, attr_res, 0, ctrl, color_ctrl, log_scale, quat, opacity, sharpness)
+    return bgt_prims(degree, num_prims, attr_res, sh_degree, ctrl, color_ctrl, log_scale, quat, opacity, sharpness,
+                     sh)
 
 
 def make_views(wh_int32_array, cams_ptr):
@@ -281,5 +284,5 @@ def make_views(wh_int32_array, cams_ptr):
     return bgt_views(n, 0, p, cams_ptr)
 
 
-def make_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness):
-    return bgt_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness)
+def make_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness, sh=None):
+    return bgt_grads(ctrl, color_ctrl, log_scale, quat, opacity, sharpness, sh)

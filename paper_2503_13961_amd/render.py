@@ -13,6 +13,16 @@ from . import native as N
 PARAM_NAMES = ("ctrl", "color_ctrl", "log_scale", "quat", "opacity", "sharpness")
 
 
+def param_names(params) -> tuple:
+    """The parameter arrays present: the six of every scene, plus the SH
+    coefficients ("sh", [3][K][P]) of a scene with view-dependent colour."""
+    return PARAM_NAMES + (("sh",) if params.get("sh") is not None and params["sh"].numel() > 0 else ())
+
+
+def _grad_ptrs(grads) -> N.bgt_grads:
+    return N.make_grads(*(_ptr(grads[k]) for k in PARAM_NAMES), sh=_ptr(grads["sh"]) if "sh" in grads else None)
+
+
 def _ptr(t: torch.Tensor) -> int:
     assert t.is_contiguous(), "tensor must be contiguous"
     return t.data_ptr()
@@ -42,7 +52,14 @@ class Renderer:
     @staticmethod
     def prims_struct(degree, params) -> N.bgt_prims:
         P = int(params["opacity"].shape[0])
-        return N.make_prims(degree, P, *(_ptr(params[k]) for k in PARAM_NAMES))
+        T = int(params["log_scale"].shape[1]) if params["log_scale"].dim() == 3 else 1
+        R = {1: 1, 6: 3}.get(T, 0)  # attribute-map texels T = R(R+1)/2
+        sh = params.get("sh")
+        shd = 0
+        if sh is not None and sh.numel() > 0:
+            shd = {3: 1, 8: 2, 15: 3}.get(int(sh.shape[1]), -1)
+        return N.make_prims(degree, P, *(_ptr(params[k]) for k in PARAM_NAMES), attr_res=R, sh_degree=shd,
+                            sh=_ptr(sh) if shd > 0 else None)
 
     @staticmethod
     def views_struct(cams: torch.Tensor, wh: np.ndarray) -> N.bgt_views:
@@ -87,8 +104,8 @@ class Renderer:
     def backward(self, degree, params, cams, wh, images, grad_images, state, grads=None):
         wh = np.ascontiguousarray(wh, dtype=np.int32).reshape(-1, 2)
         if grads is None:
-            grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
-        g = N.make_grads(*(_ptr(grads[k]) for k in PARAM_NAMES))
+            grads = {k: torch.empty_like(params[k]) for k in param_names(params)}
+        g = _grad_ptrs(grads)
         N.bgt_render_bwd(self.ctx, self.prims_struct(degree, params), self.views_struct(cams, wh), _ptr(images),
                          _ptr(grad_images), _ptr(state), state.numel(), g, _stream())
         return grads
@@ -109,24 +126,27 @@ class RenderFunction(torch.autograd.Function):
     """images = render(BG-Triangle parameters); backward = bgt_render_bwd."""
 
     @staticmethod
-    def forward(ctx, renderer, degree, cams, wh, ctrl, color_ctrl, log_scale, quat, opacity, sharpness):
+    def forward(ctx, renderer, degree, cams, wh, ctrl, color_ctrl, log_scale, quat, opacity, sharpness, sh=None):
         params = dict(zip(PARAM_NAMES, (ctrl, color_ctrl, log_scale, quat, opacity, sharpness)))
+        if sh is not None:
+            params["sh"] = sh
         params = {k: v.detach().contiguous() for k, v in params.items()}
         images, state = renderer.forward(degree, params, cams, wh)
         ctx.renderer, ctx.degree, ctx.wh, ctx.state = renderer, degree, wh, state
-        ctx.save_for_backward(*(params[k] for k in PARAM_NAMES), cams, images)
+        ctx.names = param_names(params)
+        ctx.save_for_backward(*(params[k] for k in ctx.names), cams, images)
         return images
 
     @staticmethod
     def backward(ctx, grad_images):
         *ps, cams, images = ctx.saved_tensors
-        params = dict(zip(PARAM_NAMES, ps))
+        params = dict(zip(ctx.names, ps))
         grads = ctx.renderer.backward(ctx.degree, params, cams, ctx.wh, images, grad_images.contiguous(), ctx.state)
-        return (None, None, None, None) + tuple(grads[k] for k in PARAM_NAMES)
+        return (None, None, None, None) + tuple(grads[k] for k in PARAM_NAMES) + (grads.get("sh"),)
 
 
 def render(renderer: Renderer, degree: int, params: dict, cams: torch.Tensor, wh) -> torch.Tensor:
-    return RenderFunction.apply(renderer, degree, cams, wh, *(params[k] for k in PARAM_NAMES))
+    return RenderFunction.apply(renderer, degree, cams, wh, *(params[k] for k in PARAM_NAMES), params.get("sh"))
 
 
 def scene_tensors(scene, device) -> dict:

@@ -7,16 +7,17 @@ import numpy as np
 import torch
 
 from . import native as N
-from .render import PARAM_NAMES, Renderer, _ptr, _stream
+from .render import Renderer, _ptr, _stream, param_names
 
 LAMBDA = 0.2  # weight of the D-SSIM term in Eq. 9
 
 # The paper gives no learning rates.  Defaults: the 3DGS framework's own for
 # positions, colour, log-scales and rotations; opacity here is the value
 # itself rather than a logit, so it takes the colour rate, and the boundary
-# sharpness the rotation rate.
+# sharpness the rotation rate; SH coefficients take the colour rate over 20,
+# the 3DGS ratio between its higher SH bands and their DC term.
 DEFAULT_LR = {"ctrl": 1.6e-4, "color_ctrl": 2.5e-3, "log_scale": 5e-3, "quat": 1e-3, "opacity": 2.5e-3,
-              "sharpness": 1e-3}
+              "sharpness": 1e-3, "sh": 2.5e-3 / 20}
 
 
 class PhotometricLoss:
@@ -69,13 +70,14 @@ class Adam:
         self.lr = dict(DEFAULT_LR if lr is None else lr)
         self.betas = (float(betas[0]), float(betas[1]))
         self.eps = float(eps)
-        self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
-        self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.names = param_names(params)
+        self.m = {k: torch.zeros_like(params[k]) for k in self.names}
+        self.v = {k: torch.zeros_like(params[k]) for k in self.names}
         self.step_count = torch.zeros(1, dtype=torch.int32, device=renderer.device)
 
     def step(self, grads: dict):
         groups = [N.bgt_adam_group(_ptr(self.params[k]), _ptr(grads[k]), _ptr(self.m[k]), _ptr(self.v[k]),
-                                   self.params[k].numel(), self.lr[k], 0) for k in PARAM_NAMES]
+                                   self.params[k].numel(), self.lr[k], 0) for k in self.names]
         N.bgt_adam_step(self.renderer.ctx, groups, self.betas[0], self.betas[1], self.eps, _ptr(self.step_count),
                         _stream())
 
@@ -94,7 +96,7 @@ class TrainStep:
         self.opt = Adam(renderer, params, lr)
         self.images, self.state = renderer.forward(degree, params, cams, self.wh)
         self.grad_images = torch.empty_like(self.images)
-        self.grads = {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+        self.grads = {k: torch.empty_like(params[k]) for k in param_names(params)}
 
     def __call__(self):
         self.r.forward(self.degree, self.params, self.cams, self.wh, state=self.state, images=self.images,

@@ -52,7 +52,13 @@ def test_prims_and_views_validation():
     assert N.bgt_validate_prims(N.make_prims(6, 10, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
     assert N.bgt_validate_prims(N.make_prims(2, 0, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
     assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 0, 1, 1), c) == N.BGT_E_INVALID
-    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, attr_res=3), c) == N.BGT_E_UNSUPPORTED
+    # attribute maps of resolution 1 or 3; SH colour of degree 0..3 with its array
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, attr_res=3), c) == N.BGT_OK
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, attr_res=2), c) == N.BGT_E_UNSUPPORTED
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, sh_degree=3, sh=1), c) == N.BGT_OK
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, sh_degree=3), c) == N.BGT_E_INVALID
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, sh_degree=4, sh=1), c) == N.BGT_E_UNSUPPORTED
+    assert N.bgt_validate_prims(N.make_prims(2, 10, 1, 1, 1, 1, 1, 1, sh_degree=-1, sh=1), c) == N.BGT_E_INVALID
     # sub-triangle ids must fit 24 bits
     assert N.bgt_validate_prims(N.make_prims(2, 1 << 20, 1, 1, 1, 1, 1, 1), c) == N.BGT_E_INVALID
     wh = np.array([[800, 800], [37, 1]], np.int32)

@@ -19,6 +19,11 @@ GRAD_TOL = 1e-3
 
 
 def _workload(name):
+    if "_r" in name and "_sh" in name:  # resolution-R attribute maps and SH colour of degree D
+        base, rest = name.split("_r")
+        R, D = (int(x) for x in rest.split("_sh"))
+        sc, cams = _workload(base)
+        return S.with_attributes(sc, attr_res=R, sh_degree=D, seed=R + D, sh_std=0.2), cams
     if name.startswith("degree"):  # small random scenes of every Bezier degree
         n = int(name[len("degree"):])
         sc = S.random_triangles(P=24, degree=n, seed=10 + n)
@@ -33,7 +38,8 @@ def _workload(name):
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
-@pytest.mark.parametrize("name", ["tiny", "random64", "sphere_small", "ragged", "degree1", "degree5"])
+@pytest.mark.parametrize("name", ["tiny", "random64", "sphere_small", "ragged", "degree1", "degree5",
+                                  "random64_r3_sh3", "sphere_small_r3_sh3"])
 def test_stage_parity(name, tile):
     """Index map, boundary set, Gaussians, tile lists and images per view."""
     G.log(f"[stage_parity] workload={name} tile={tile}")
@@ -105,7 +111,9 @@ def test_full_size_sphere_image():
     assert err <= IMG_TOL
 
 
-@pytest.mark.parametrize("name", ["random64", "sphere_small", "ragged", "degree1", "degree4", "degree5"])
+@pytest.mark.parametrize("name", ["random64", "sphere_small", "ragged", "degree1", "degree4", "degree5",
+                                  "random64_r3_sh3", "sphere_small_r3_sh3", "random64_r3_sh0", "random64_r1_sh2",
+                                  "degree5_r3_sh3", "degree1_r3_sh1"])
 def test_gradient_parity(name):
     """Backward against the oracle's analytic FP64 gradient (itself pinned by
     finite differences) for an L1 loss to a random target."""
