@@ -66,7 +66,8 @@ class Step:
 
     def __init__(self, renderer, degree, params, camt, wh, target):
         import torch
-        self.torch = torch
+        from paper_2503_13961_amd import native as N
+        self.torch, self.N = torch, N
         self.r, self.degree, self.params, self.camt, self.wh = renderer, degree, params, camt, wh
         self.npx = int((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
         dev = camt.device
@@ -81,9 +82,8 @@ class Step:
         torch = self.torch
         self.r.forward(self.degree, self.params, self.camt, self.wh, state=self.state, images=self.images,
                        check=False)
-        torch.sub(self.images, self.target, out=self.gimg)
-        torch.sign(self.gimg, out=self.gimg)
-        self.gimg.mul_(1.0 / self.gimg.numel())
+        self.N.bgt_l1_cotangent(self.r.ctx, self.gimg.numel(), self.images.data_ptr(), self.target.data_ptr(),
+                                1.0 / self.gimg.numel(), self.gimg.data_ptr(), torch.cuda.current_stream().cuda_stream)
         self.r.backward(self.degree, self.params, self.camt, self.wh, self.images, self.gimg, self.state,
                         grads=self.grads)
 
@@ -105,9 +105,8 @@ class PerViewStep:
         for s in self.steps:
             s.r.forward(s.degree, s.params, s.camt, s.wh, state=s.state, images=s.images, check=False)
         for s in self.steps:
-            torch.sub(s.images, s.target, out=s.gimg)
-            torch.sign(s.gimg, out=s.gimg)
-            s.gimg.mul_(1.0 / (3 * self.npx))
+            s.N.bgt_l1_cotangent(s.r.ctx, s.gimg.numel(), s.images.data_ptr(), s.target.data_ptr(),
+                                 1.0 / (3 * self.npx), s.gimg.data_ptr(), torch.cuda.current_stream().cuda_stream)
         for g in self.grads.values():
             g.zero_()
         for s in self.steps:

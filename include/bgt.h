@@ -196,6 +196,13 @@ bgt_status bgt_loss(bgt_ctx *ctx, const bgt_views *views, const float *images, c
                     float lambda, float *loss, float *grad_images, void *workspace, size_t workspace_bytes,
                     void *stream);
 
+/* Cotangent of an L1 loss scale * sum |C - target| over n values (images
+ * and targets device arrays of n floats): grad = scale * sign(C - target),
+ * 0 where they are equal.  The L1 loss of the benchmark workload, mean over
+ * the 3 sum W H values, takes scale = 1 / n. */
+bgt_status bgt_l1_cotangent(bgt_ctx *ctx, int64_t n, const float *images, const float *targets, float scale,
+                            float *grad_images, void *stream);
+
 /* One Adam update (Kingma and Ba 2015, Algorithm 1, with bias correction)
  * of up to BGT_MAX_ADAM_GROUPS parameter arrays, each with its own learning
  * rate: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,

@@ -580,6 +580,18 @@ bgt_status bgt_loss(bgt_ctx *ctx, const bgt_views *views, const float *images, c
     return BGT_OK;
 }
 
+bgt_status bgt_l1_cotangent(bgt_ctx *ctx, int64_t n, const float *images, const float *targets, float scale,
+                            float *grad_images, void *stream) {
+    if (!ctx) return BGT_E_INVALID;
+    if (n < 0 || (n > 0 && (!images || !targets || !grad_images)) || !isfinite(scale))
+        return fail(ctx, BGT_E_INVALID, "bad size, null buffer or non-finite scale");
+    bgt_status s;
+    if ((s = use_device(ctx)) != BGT_OK) return s;
+    hipError_t e = launch_l1(n, images, targets, scale, grad_images, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "l1 cotangent");
+    return BGT_OK;
+}
+
 bgt_status bgt_adam_step(bgt_ctx *ctx, const bgt_adam_group *groups, int32_t n_groups, float beta1,
                          float beta2, float eps, int32_t *step, void *stream) {
     if (!ctx) return BGT_E_INVALID;

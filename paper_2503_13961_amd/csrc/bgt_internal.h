@@ -258,6 +258,7 @@ hipError_t launch_plan(const Consts &k, const float *ctrl, const StatsPtrs &sp, 
                        int32_t *action, int32_t *dst_index, int32_t *count, hipStream_t s);
 hipError_t launch_apply(const Consts &k, const PrimPtrs &src, const int32_t *action, const int32_t *dst_index,
                         int Pd, const GradPtrs &dst, hipStream_t s);
+hipError_t launch_l1(int64_t n, const float *x, const float *y, float scale, float *g, hipStream_t s);
 hipError_t launch_adam(const AdamTable &at, double b1, double b2, double eps, int32_t *step, hipStream_t s);
 
 }  // namespace bgt

@@ -232,6 +232,24 @@ void loss_tiles(int W, int H, int *tiles_x, int *tiles) {
     *tiles = *tiles_x * ((H + kTH - 1) / kTH);
 }
 
+// ------------------------------------------------------------------- L1
+
+__global__ void __launch_bounds__(kThreads) k_l1_cotangent(int64_t n, const float *x, const float *y, float scale,
+                                                           float *g) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const float d = x[i] - y[i];
+        g[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    }
+}
+
+hipError_t launch_l1(int64_t n, const float *x, const float *y, float scale, float *g, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + kThreads - 1) / kThreads;
+    blocks = blocks > 8192 ? 8192 : blocks;
+    hipLaunchKernelGGL(k_l1_cotangent, dim3((unsigned)blocks), dim3(kThreads), 0, s, n, x, y, scale, g);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------- Adam
 
 // One Adam update (Kingma and Ba, Algorithm 1) over every group, at step

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "bgt.h")).read()
-    return sorted(set(re.findall(r"\b(bgt_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(bgt_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -153,3 +153,26 @@ def test_train_step_in_a_graph_matches_eager_and_lowers_the_loss():
     for a, b in zip(ref, got):
         assert abs(a - b) <= 1e-3 * a, (ref, got)
     assert ref[-1] < 0.8 * ref[0]
+
+
+def test_l1_cotangent_is_exact():
+    """sign(C - target) * scale, 0 on ties, over a length that is not a
+    multiple of 4 and from an offset slice: bit-exact."""
+    import torch
+    from paper_2503_13961_amd import native as N
+    from paper_2503_13961_amd.render import Renderer
+    rng = np.random.default_rng(9)
+    n = 3 * 1001
+    x = rng.random(n + 5).astype(np.float32)
+    y = rng.random(n + 5).astype(np.float32)
+    y[::7] = x[::7]                                      # exact ties
+    dev = torch.device("cuda", 0)
+    xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    g = torch.full((n + 5,), 7.0, device=dev)
+    r = Renderer(0)
+    scale = np.float32(1.0 / n)
+    N.bgt_l1_cotangent(r.ctx, n, xt[3:].data_ptr(), yt[3:].data_ptr(), float(scale), g[3:].data_ptr(), 0)
+    got = g.cpu().numpy()
+    want = np.sign(x[3:3 + n] - y[3:3 + n]).astype(np.float32) * scale
+    np.testing.assert_array_equal(got[3:3 + n], want)
+    assert (got[:3] == 7.0).all() and (got[3 + n:] == 7.0).all()
