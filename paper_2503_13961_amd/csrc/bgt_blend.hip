@@ -389,6 +389,13 @@ __device__ __forceinline__ float cross_row_sum(float x) {
     return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
+// The same sum over the four rows through the LDS crossbar (ds_bpermute),
+// which keeps the two exchanges off the vector ALU.
+__device__ __forceinline__ float cross_row_sum_bp(float x, int lane) {
+    x += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(x)));
+    return x + __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 16) << 2, __float_as_int(x)));
+}
+
 // ------------------------------------------------------------ forward
 
 template <int TS, int K>
@@ -669,8 +676,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 // instructions
                 float vals[9] = {gx, gy, gx * dx, gx * dy, gy * dy, d_c0, d_c1, d_c2, d_o};
                 row_reduce_scatter9(vals, lane);
-                vals[0] = cross_row_sum(vals[0]);
-                vals[8] = cross_row_sum(vals[8]);
+                vals[0] = cross_row_sum_bp(vals[0], lane);
+                vals[8] = cross_row_sum_bp(vals[8], lane);
                 if (lane < 16 && (lane & 4)) {
                     float *dst = acc + kk * 9;
                     atomicAdd(&dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)], vals[0]);
