@@ -378,19 +378,8 @@ __device__ __forceinline__ void row_reduce_scatter9(float *v, int lane) {
     v[8] = s8;
 }
 
-// Sum over the four rows, in every row: swapping a value with itself across
-// the wave halves (v_permlane32_swap) and then across neighbouring rows
-// (v_permlane16_swap) hands each lane the partner's value in one of the two
-// results, so their sum plus nothing else is the pair total.
-__device__ __forceinline__ float cross_row_sum(float x) {
-    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
-    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
-}
-
-// The same sum over the four rows through the LDS crossbar (ds_bpermute),
-// which keeps the two exchanges off the vector ALU.
+// Sum over the four 16-lane rows, in every row: exchanges with lane xor 32
+// and xor 16 through the LDS crossbar (ds_bpermute), off the vector ALU.
 __device__ __forceinline__ float cross_row_sum_bp(float x, int lane) {
     x += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(x)));
     return x + __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 16) << 2, __float_as_int(x)));
