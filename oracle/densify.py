@@ -8,7 +8,8 @@ Readings where the paper is silent:
     parent's domain triangle turned by a half turn (its u corner is the
     midpoint opposite u).  Their control nets are the parent's blossom at the
     sub-domain corners, so each child reproduces its part of the parent
-    surface (and colour) exactly.  Per-patch attributes are copied.
+    surface (and colour) exactly.  Per-patch attributes (attribute-map
+    texels, opacity, sharpness, SH coefficients) are copied.
   - Position gradient: the mean over a patch's control points of |dL/dp|,
     accumulated over the calls in which the patch is visible, and averaged.
   - Edge prior: the Sobel gradient magnitude of the training image's grey
@@ -202,7 +203,8 @@ def apply(scene, act, dst):
     kept patches copied, split patches replaced by their four children, in
     patch order."""
     n = scene.degree
-    out = {k: [] for k in ("ctrl", "color_ctrl", "log_scale", "quat", "opacity", "sharpness")}
+    has_sh = getattr(scene, "sh_degree", 0) > 0
+    out = {k: [] for k in ("ctrl", "color_ctrl", "log_scale", "quat", "opacity", "sharpness", "sh")}
     for p in range(scene.num_prims):
         if act[p] == PRUNE:
             continue
@@ -216,6 +218,11 @@ def apply(scene, act, dst):
             out["quat"].append(scene.quat[:, :, p])
             out["opacity"].append(scene.opacity[p])
             out["sharpness"].append(scene.sharpness[p])
-    return {"ctrl": np.stack(out["ctrl"], axis=-1), "color_ctrl": np.stack(out["color_ctrl"], axis=-1),
-            "log_scale": np.stack(out["log_scale"], axis=-1), "quat": np.stack(out["quat"], axis=-1),
-            "opacity": np.array(out["opacity"]), "sharpness": np.array(out["sharpness"])}
+            if has_sh:
+                out["sh"].append(scene.sh[:, :, p])
+    res = {"ctrl": np.stack(out["ctrl"], axis=-1), "color_ctrl": np.stack(out["color_ctrl"], axis=-1),
+           "log_scale": np.stack(out["log_scale"], axis=-1), "quat": np.stack(out["quat"], axis=-1),
+           "opacity": np.array(out["opacity"]), "sharpness": np.array(out["sharpness"])}
+    if has_sh:
+        res["sh"] = np.stack(out["sh"], axis=-1)
+    return res

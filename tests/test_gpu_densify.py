@@ -59,8 +59,8 @@ def test_statistics_match_oracle(name):
     assert e <= 1e-5 and gsum <= 1e-3
 
 
-@pytest.mark.parametrize("degree", [1, 2, 3, 5])
-def test_plan_and_apply_match_oracle(degree):
+@pytest.mark.parametrize("degree,attrs", [(1, False), (2, False), (3, False), (5, False), (2, True)])
+def test_plan_and_apply_match_oracle(degree, attrs):
     """Statistics set so that every rule fires on some patch; the decision,
     slots and count are exact and the rebuilt arrays match."""
     import torch
@@ -69,6 +69,8 @@ def test_plan_and_apply_match_oracle(degree):
     from paper_2503_13961_amd.render import Renderer, scene_tensors
     G.log(f"[densify] plan and apply, degree {degree}")
     sc = S.random_triangles(P=300, degree=degree, seed=20 + degree)
+    if attrs:   # resolution-3 maps and SH colour travel with each child
+        sc = S.with_attributes(sc, attr_res=3, sh_degree=3, seed=degree)
     P = sc.num_prims
     rng = np.random.default_rng(degree)
     ref = D.Stats(P)
@@ -104,7 +106,7 @@ def test_plan_and_apply_match_oracle(degree):
         got = new[k].cpu().numpy().astype(np.float64)
         ulp = np.spacing(np.abs(want[k]).astype(np.float32)).astype(np.float64)
         assert (np.abs(got - want[k]) <= 2 * ulp + 1e-30).all(), k
-    for k in ("log_scale", "quat", "opacity", "sharpness"):
+    for k in ("log_scale", "quat", "opacity", "sharpness") + (("sh",) if attrs else ()):
         np.testing.assert_array_equal(new[k].cpu().numpy(), want[k])
 
 

@@ -153,7 +153,7 @@ def test_boundary_lists_over_the_lds_stage(W, tile):
         assert e <= GRAD_TOL, k
 
 
-@pytest.mark.parametrize("name", ["random64", "sphere_small", "degree3"])
+@pytest.mark.parametrize("name", ["random64", "sphere_small", "degree3", "random64_r3_sh3"])
 def test_without_coefficients_parity(name):
     """The ablation variant without blending coefficients (w = 1 for every
     Gaussian): no boundary points, index map bit-exact, image 1e-4 and
