@@ -133,3 +133,12 @@ def test_training_step_entry_points_validate_on_the_host():
         assert "host-only" in N.bgt_last_error(ctx)
     finally:
         N.bgt_destroy(ctx)
+
+
+def test_bench_measures_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits with a message instead of timing."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout
