@@ -211,6 +211,24 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st) 
         return;
     }
     const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
+    if (cnt <= 64) {
+        // short lists (most boundary lists, border tiles): one wave, one key
+        // per lane, the bitonic network through lane exchanges, no barriers
+        if (threadIdx.x >= 64) return;
+        const int lane = threadIdx.x;
+        unsigned long long x = lane < cnt ? src[start + lane] : ~0ull;
+        for (int kk = 2; kk <= 64; kk <<= 1)
+            for (int j = kk >> 1; j >= 1; j >>= 1) {
+                const unsigned long long y = __shfl_xor(x, j, 64);
+                // the lower lane of a pair keeps the smaller key in ascending runs
+                const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
+                x = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+            }
+        const int off = vt.v[view_of_tile(vt, t)].px_off;
+        uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+        if (lane < cnt) dst[start + lane] = (uint32_t)(off + (int)(x & 0xFFFFFFull));
+        return;
+    }
     int n2 = 1;
     while (n2 < cnt) n2 <<= 1;
     for (int i = threadIdx.x; i < n2; i += blockDim.x) keys[i] = i < cnt ? src[start + i] : ~0ull;

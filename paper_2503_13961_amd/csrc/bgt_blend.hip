@@ -586,114 +586,92 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             const int j = c0 + lane, jj = j < K ? j : K - 1;
             unsigned long long mask = __ballot(j < nkw && !(hi16(S.xr[jj]) < wx0 || lo16(S.xr[jj]) > wx0 + 7 ||
                                                              hi16(S.yr[jj]) < wy0 || lo16(S.yr[jj]) > wy0 + 7));
-            if (mask) {
-                // the next entry's record index and gamma* map value are read
-                // while the current entry is replayed, so the two dependent
-                // LDS reads of an entry leave the critical path
-                int kk = c0 + __ffsll((long long)mask) - 1;  // wave-uniform
+            while (mask) {
+                const int kk = c0 + __ffsll((long long)mask) - 1;  // wave-uniform
                 mask &= mask - 1;
-                int2 prk = S.pr[kk];
-                int r = __builtin_amdgcn_readfirstlane(prk.y);
-                float gmap = __uint_as_float(B.map[min(max(r, 0), RM - 1)][tid]);
-                while (true) {
-                    const bool more = mask != 0;  // wave-uniform
-                    int kn = kk;
-                    int2 prn = prk;
-                    if (more) {
-                        kn = c0 + __ffsll((long long)mask) - 1;
-                        mask &= mask - 1;
-                        prn = S.pr[kn];
-                    }
-                    const int g = prk.x;
-                    const float2 m = S.m[wave][kk];
-                    const float4 ex = S.e[kk];
-                    const float4 c = S.c[kk];
-                    const bool own = g == h || nob;  // w = 1 for all without coefficients
-                    const float dx = qx - m.x, dy = qy - m.y;
-                    const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
-                    bool live = base + kk < mylast && (own || r != -1) && e >= e_min;
-                    const bool mapped = r >= 0 && r < RM;
-                    float gam = 1.0f;
-                    int arg = -1;
+                const int2 prk = S.pr[kk];
+                const int g = prk.x;
+                const int r = __builtin_amdgcn_readfirstlane(prk.y);
+                const float2 m = S.m[wave][kk];
+                const float4 ex = S.e[kk];
+                const float4 c = S.c[kk];
+                const bool own = g == h || nob;  // w = 1 for all without coefficients
+                const float dx = qx - m.x, dy = qy - m.y;
+                const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
+                bool live = base + kk < mylast && (own || r != -1) && e >= e_min;
+                const bool mapped = r >= 0 && r < RM;
+                float gam = 1.0f;
+                int arg = -1;
+                if (mapped) {
+                    gam = __uint_as_float(B.map[r][tid]);
+                } else if (r >= 0) {
+                    if (live) gam = gamma_lds(B, r, lx, ly, &arg);
+                } else if (r == -2) {
+                    if (live) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                }
+                const float w = own ? gam : 1.0f - gam;
+                live = live && w > 0.0f;
+                if (!__any(live)) continue;
+                const float o = ex.w;
+                const float Gv = support_exp2(e);
+                const float raw = o * w * Gv;
+                const bool clamped = raw > amax;
+                float a = clamped ? amax : raw;
+                a = live ? a : 0.0f;
+                const float ta = T * a;
+                const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
+                P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+                const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
+                                     g2 * (T * c.z - (im2 - P2) * inv);
+                T = T * (1.0f - a);
+                const bool smooth = live && !clamped;
+                const float d_o = smooth ? dalpha * w * Gv : 0.0f;
+                const float dG = d_o * o;  // dl/dG * G
+                // dl/dmu = Q sum dG d and dl/dQ = -1/2 sum dG d d^T over the
+                // pixels (d = q - mu): the sums are taken of the moments, and
+                // the Gaussian's conic is applied once per Gaussian after them
+                const float gx = dG * dx, gy = dG * dy;
+                if (r != -1) {
+                    const float dgm = (smooth && gam < 1.0f) ? (own ? 1.0f : -1.0f) * dalpha * o * Gv : 0.0f;
                     if (mapped) {
-                        gam = gmap;
-                    } else if (r >= 0) {
-                        if (live) gam = gamma_lds(B, r, lx, ly, &arg);
-                    } else if (r == -2) {
-                        if (live) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                        if (__any(dgm != 0.0f)) dgr[r] += dgm;  // only near the run's boundary points
+                    } else if (dgm != 0.0f && arg >= 0) {
+                        float ddx, ddy, sg;
+                        const int bpix = (int)st.b_list[bs0 + arg];
+                        if (r >= 0) {
+                            ddx = (float)(lx - lo16(B.bxy[arg])) - B.bdx[arg];
+                            ddy = (float)(ly - hi16(B.bxy[arg])) - B.bdy[arg];
+                            sg = B.bs[arg];
+                        } else {
+                            const float4 r0 = st.rec[(int64_t)bpix * 4];
+                            const int lp = bpix - vi.px_off;
+                            ddx = (float)(px - lp % vi.W) - r0.x;
+                            ddy = (float)(py - lp / vi.W) - r0.y;
+                            sg = st.rec[(int64_t)bpix * 4 + 2].z;
+                        }
+                        const float d = sqrtf(ddx * ddx + ddy * ddy);
+                        const float dd = dgm * LN2 / sg * gam;
+                        float *dst = st.dgauss + (int64_t)bpix * 12;
+                        if (d > kDKink) {
+                            unsafeAtomicAdd(&dst[10], -dd * ddx / d);
+                            unsafeAtomicAdd(&dst[11], -dd * ddy / d);
+                        }
+                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
                     }
-                    const float w = own ? gam : 1.0f - gam;
-                    live = live && w > 0.0f;
-                    const int rn = __builtin_amdgcn_readfirstlane(prn.y);
-                    const float gmap_n = __uint_as_float(B.map[min(max(rn, 0), RM - 1)][tid]);
-                    if (__any(live)) {
-                        const float o = ex.w;
-                        const float Gv = support_exp2(e);
-                        const float raw = o * w * Gv;
-                        const bool clamped = raw > amax;
-                        float a = clamped ? amax : raw;
-                        a = live ? a : 0.0f;
-                        const float ta = T * a;
-                        const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
-                        P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
-                        const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-                        const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
-                                             g2 * (T * c.z - (im2 - P2) * inv);
-                        T = T * (1.0f - a);
-                        const bool smooth = live && !clamped;
-                        const float d_o = smooth ? dalpha * w * Gv : 0.0f;
-                        const float dG = d_o * o;  // dl/dG * G
-                        // dl/dmu = Q sum dG d and dl/dQ = -1/2 sum dG d d^T over the
-                        // pixels (d = q - mu): the sums are taken of the moments, and
-                        // the Gaussian's conic is applied once per Gaussian after them
-                        const float gx = dG * dx, gy = dG * dy;
-                        if (r != -1) {
-                            const float dgm = (smooth && gam < 1.0f) ? (own ? 1.0f : -1.0f) * dalpha * o * Gv : 0.0f;
-                            if (mapped) {
-                                if (__any(dgm != 0.0f)) dgr[r] += dgm;  // only near the run's boundary points
-                            } else if (dgm != 0.0f && arg >= 0) {
-                                float ddx, ddy, sg;
-                                const int bpix = (int)st.b_list[bs0 + arg];
-                                if (r >= 0) {
-                                    ddx = (float)(lx - lo16(B.bxy[arg])) - B.bdx[arg];
-                                    ddy = (float)(ly - hi16(B.bxy[arg])) - B.bdy[arg];
-                                    sg = B.bs[arg];
-                                } else {
-                                    const float4 r0 = st.rec[(int64_t)bpix * 4];
-                                    const int lp = bpix - vi.px_off;
-                                    ddx = (float)(px - lp % vi.W) - r0.x;
-                                    ddy = (float)(py - lp / vi.W) - r0.y;
-                                    sg = st.rec[(int64_t)bpix * 4 + 2].z;
-                                }
-                                const float d = sqrtf(ddx * ddx + ddy * ddy);
-                                const float dd = dgm * LN2 / sg * gam;
-                                float *dst = st.dgauss + (int64_t)bpix * 12;
-                                if (d > kDKink) {
-                                    unsafeAtomicAdd(&dst[10], -dd * ddx / d);
-                                    unsafeAtomicAdd(&dst[11], -dd * ddy / d);
-                                }
-                                unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
-                            }
-                        }
-                        // wave totals, scattered over the lanes of row 0 with bit 2 set,
-                        // go to the entry's LDS sums: nine single-lane adds in two
-                        // instructions
-                        float vals[9] = {gx, gy, gx * dx, gx * dy, gy * dy, d_c0, d_c1, d_c2, d_o};
-                        row_reduce_scatter9(vals, lane);
-                        vals[0] = cross_row_sum_bp(vals[0], lane);
-                        vals[8] = cross_row_sum_bp(vals[8], lane);
-                        if (lane < 16 && (lane & 4)) {
-                            float *dst = acc + kk * 9;
-                            atomicAdd(&dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)], vals[0]);
-                            if (lane == 4) atomicAdd(&dst[8], vals[8]);
-                        }
-                    }  // any live lane
-                    if (!more) break;
-                    kk = kn;
-                    prk = prn;
-                    r = rn;
-                    gmap = gmap_n;
-                }  // entries of the mask
+                }
+                // wave totals, scattered over the lanes of row 0 with bit 2 set,
+                // go to the entry's LDS sums: nine single-lane adds in two
+                // instructions
+                float vals[9] = {gx, gy, gx * dx, gx * dy, gy * dy, d_c0, d_c1, d_c2, d_o};
+                row_reduce_scatter9(vals, lane);
+                vals[0] = cross_row_sum_bp(vals[0], lane);
+                vals[8] = cross_row_sum_bp(vals[8], lane);
+                if (lane < 16 && (lane & 4)) {
+                    float *dst = acc + kk * 9;
+                    atomicAdd(&dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)], vals[0]);
+                    if (lane == 4) atomicAdd(&dst[8], vals[8]);
+                }
             }
         }
         __syncthreads();
