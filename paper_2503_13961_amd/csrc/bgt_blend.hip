@@ -68,17 +68,17 @@ struct BoundaryLds {
     static constexpr int NMAP = RM;
     float bdx[CAP], bdy[CAP], bs[CAP];
     int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
-    int bp[CAP], brun[CAP];
+    int brun[CAP];
     int run_prim[CAP], run_start[CAP + 1];
     int wsum[33];
     int n_runs, nbl;
-    unsigned map[RM][TS * TS];  // gamma* bits per (run, pixel in thread order)
+    union {
+        int bp[CAP];                // each point's primitive, while the runs are found
+        unsigned map[RM][TS * TS];  // then gamma* bits per (run, pixel in thread order)
+    };
+    static_assert(RM * TS * TS >= CAP, "the maps hold the staging ids");
 };
 
-// A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
-// the Gaussian's own pixel, w0 the origin of the wave's 8x8 block and delta
-// the mean's offset from g's centre: one rounding that does not depend on
-// the tile size.
 // A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
 // the Gaussian's own pixel, w0 the origin of the wave's 8x8 block and delta
 // the mean's offset from g's centre: one rounding that does not depend on
@@ -568,7 +568,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 
     const int gs0 = st.g_start[t];
     const int nlast = max_last;
-    float T = 1.0f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
+    // R = C - prefix: the colour still to come after the current entry
+    float T = 1.0f, P0 = im0, P1 = im1, P2 = im2;
     const float amax = k.alpha_max;
     const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
     const float e_min = kE * k.kappa2;
@@ -620,10 +621,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 a = live ? a : 0.0f;
                 const float ta = T * a;
                 const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
-                P0 += ta * c.x; P1 += ta * c.y; P2 += ta * c.z;
+                P0 -= ta * c.x; P1 -= ta * c.y; P2 -= ta * c.z;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-                const float dalpha = g0 * (T * c.x - (im0 - P0) * inv) + g1 * (T * c.y - (im1 - P1) * inv) +
-                                     g2 * (T * c.z - (im2 - P2) * inv);
+                const float dalpha = g0 * (T * c.x - P0 * inv) + g1 * (T * c.y - P1 * inv) + g2 * (T * c.z - P2 * inv);
                 T = T * (1.0f - a);
                 const bool smooth = live && !clamped;
                 const float d_o = smooth ? dalpha * w * Gv : 0.0f;
