@@ -54,7 +54,7 @@ typedef enum {
     BGT_E_NOMEM = 2,       /* state buffer too small or host allocation failed */
     BGT_E_OVERFLOW = 3,    /* a pair capacity was exceeded (see bgt_query) */
     BGT_E_HIP = 4,         /* a HIP runtime call failed */
-    BGT_E_UNSUPPORTED = 5  /* valid request outside what this build implements */
+    BGT_E_UNSUPPORTED = 5  /* valid request outside what this library implements */
 } bgt_status;
 
 #define BGT_MAX_VIEWS 64
