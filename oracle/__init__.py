@@ -51,7 +51,7 @@ def lib():
         L.orc_frame_free.argtypes = [C.c_void_p]
         L.orc_frame_dims.argtypes = [C.c_void_p, ip]
         L.orc_frame_raster.argtypes = [C.c_void_p, ip, dp, C.c_void_p, C.c_void_p]
-        L.orc_frame_records.argtypes = [C.c_void_p, dp]
+        L.orc_frame_records.argtypes = [C.c_void_p, dp, C.c_void_p]
         L.orc_frame_lists.argtypes = [C.c_void_p, C.c_int, ip, ip]
         L.orc_frame_render.argtypes = [C.c_void_p, ip, C.c_int, dp, dp, ip, ip]
         L.orc_frame_render.restype = C.c_int
@@ -78,7 +78,8 @@ class _Scene(C.Structure):
 class _Config(C.Structure):
     _fields_ = [("L", C.c_int), ("tile", C.c_int), ("z_near", C.c_double), ("g_min", C.c_double),
                 ("t_min", C.c_double), ("alpha_max", C.c_double), ("dilation", C.c_double),
-                ("r_ref", C.c_double), ("bg", C.c_double * 3), ("no_boundary", C.c_int)]
+                ("r_ref", C.c_double), ("bg", C.c_double * 3), ("no_boundary", C.c_int),
+                ("lattice", C.c_int)]
 
 
 @dataclass
@@ -94,10 +95,12 @@ class Config:
     r_ref: float = 1e-2
     bg: tuple = (0.0, 0.0, 0.0)
     no_boundary: bool = False  # the ablation variant without blending coefficients (w = 1)
+    lattice: int = 0           # m >= 2: m Gaussians per flat sub-triangle edge instead of one per pixel
 
     def c(self) -> _Config:
         return _Config(self.L, self.tile, self.z_near, self.g_min, self.t_min, self.alpha_max,
-                       self.dilation, self.r_ref, (C.c_double * 3)(*self.bg), int(self.no_boundary))
+                       self.dilation, self.r_ref, (C.c_double * 3)(*self.bg), int(self.no_boundary),
+                       int(self.lattice))
 
     @property
     def kappa2(self) -> float:
@@ -193,6 +196,7 @@ class Frame:
         lib().orc_frame_dims(h, _ip(d))
         self.tiles_x, self.tiles_y = int(d[2]), int(d[3])
         self.n_gpairs, self.n_bpairs = int(d[4]), int(d[5])
+        self.nlat = int(d[7])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -212,10 +216,14 @@ class Frame:
         lib().orc_frame_raster(self._h, _ip(it), _dp(iu), isb.ctypes.data, val.ctypes.data)
         return it, iu, isb.astype(bool), val.astype(bool)
 
-    def records(self):
-        r = np.zeros((self.npx, len(GR)))
-        lib().orc_frame_records(self._h, _dp(r))
-        return r
+    def records(self, rendered=False):
+        """Records [H*W + nlat][GR]: one per pixel (the pixel's Gaussian, or
+        in the lattice variant its boundary point only), then the lattice
+        Gaussians; with `rendered`, also which records are rendered."""
+        r = np.zeros((self.npx + self.nlat, len(GR)))
+        ren = np.zeros(self.npx + self.nlat, np.uint8)
+        lib().orc_frame_records(self._h, _dp(r), ren.ctypes.data)
+        return (r, ren.astype(bool)) if rendered else r
 
     def lists(self, which=0):
         nt = self.tiles_x * self.tiles_y

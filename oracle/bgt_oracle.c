@@ -76,6 +76,8 @@ typedef struct {
     double z_near, g_min, t_min, alpha_max, dilation, r_ref;
     double bg[3];
     int no_boundary;     /* the ablation variant without blending coefficients */
+    int lattice;         /* 0: one Gaussian per foreground pixel (Sec. 3.2); m >= 2: instead a
+                            lattice of m Gaussians per flat sub-triangle edge on every patch */
 } orc_config;
 
 /* per-pixel Gaussian record (doubles) */
@@ -95,8 +97,10 @@ typedef struct {
     int32_t *I_tri;      /* [H*W] sub-triangle id, -1 background */
     double *I_uv;        /* [H*W][2] */
     uint8_t *is_b;       /* [H*W] boundary flag (and Gaussian valid) */
-    uint8_t *valid;      /* [H*W] Gaussian exists */
-    double *rec;         /* [H*W][GR_N] */
+    uint8_t *valid;      /* [H*W + nlat] record is a rendered Gaussian */
+    uint8_t *has_rec;    /* [H*W] the pixel's record exists (S_q in front of z_near) */
+    int nlat, lat_level; /* lattice Gaussians per frame (P NL) and the lattice level */
+    double *rec;         /* [H*W + nlat][GR_N]: pixel records, then lattice records */
     int32_t *g_start;    /* [ntiles+1] */
     int32_t *g_list;     /* pixel index of each Gaussian pair, sorted per tile */
     int32_t *b_start;    /* [ntiles+1] */
@@ -499,87 +503,123 @@ static void cam_centre(const double *cam, double *C) {
     for (int c = 0; c < 3; ++c) C[c] = -(cam[c] * cam[9] + cam[3 + c] * cam[10] + cam[6 + c] * cam[11]);
 }
 
-static void gen_gaussians(orc_frame *f) {
+/* The Gaussian of patch p at (u, v) into record r: Eq. 3 (position), Eq. 4
+ * plus the SH colour, Eq. 5 (rotation and scale from the attribute maps) and
+ * the EWA projection; with `boundary` also the radius of the boundary
+ * Gaussian there.  Returns 0 when S lies behind z_near. */
+static int make_record(const orc_frame *f, int p, double u, double v, int boundary, double *r) {
     int P = f->sc.num_prims, n = f->sc.degree, ncp = f->ncp;
-    size_t npx = (size_t)f->W * f->H;
     const double *Wc = f->cam;
     double fx = f->cam[12], fy = f->cam[13], cx = f->cam[14], cy = f->cam[15];
+    double w = 1.0 - u - v;
+    double cp[64 * 3], cc[64 * 3], S[3], col[3], t[3];
+    prim_points(f->sc.ctrl, ncp, P, p, cp);
+    prim_points(f->sc.color_ctrl, ncp, P, p, cc);
+    orc_surface(n, cp, u, v, w, S);   /* Eq. 3 */
+    orc_surface(n, cc, u, v, w, col); /* Eq. 4 */
+    if (f->sc.sh_degree > 0) {        /* view-dependent colour of the patch's SH coefficients */
+        int K = sh_count(f->sc.sh_degree);
+        double C[3], dv[3], Y[15];
+        cam_centre(f->cam, C);
+        for (int c = 0; c < 3; ++c) dv[c] = S[c] - C[c];
+        double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        for (int c = 0; c < 3; ++c) dv[c] /= len;
+        sh_basis(f->sc.sh_degree, dv, Y, NULL);
+        for (int ch = 0; ch < 3; ++ch)
+            for (int k = 0; k < K; ++k) col[ch] += Y[k] * f->sc.sh[((size_t)ch * K + k) * P + p];
+    }
+    cam_apply(f->cam, S, t);
+    if (!(t[2] > f->cfg.z_near)) return 0;
+    double tz = t[2];
+    double J[6] = {fx / tz, 0.0, -fx * t[0] / (tz * tz), 0.0, fy / tz, -fy * t[1] / (tz * tz)};
+    double Tm[6];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c)
+            Tm[3 * a + c] = J[3 * a] * Wc[c] + J[3 * a + 1] * Wc[3 + c] + J[3 * a + 2] * Wc[6 + c];
+    /* Eq. 5: rotation and scale from the attribute maps at (u, v) */
+    double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9], tw[3];
+    int ti[3], nt;
+    pixel_attr(f, p, u, v, ls, qn, &qnorm, ti, tw, &nt);
+    quat_to_rot(qn, Rq);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) M[3 * a + c] = Rq[3 * a + c] * exp(ls[c]);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            S3[3 * a + c] = M[3 * a] * M[3 * c] + M[3 * a + 1] * M[3 * c + 1] + M[3 * a + 2] * M[3 * c + 2];
+    double TS[6];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c)
+            TS[3 * a + c] = Tm[3 * a] * S3[c] + Tm[3 * a + 1] * S3[3 + c] + Tm[3 * a + 2] * S3[6 + c];
+    double SA = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + f->cfg.dilation;
+    double SB = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
+    double SC = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + f->cfg.dilation;
+    double det = SA * SC - SB * SB;
+    r[GR_MUX] = fx * t[0] / tz + cx;
+    r[GR_MUY] = fy * t[1] / tz + cy;
+    r[GR_QA] = SC / det;
+    r[GR_QB] = -SB / det;
+    r[GR_QC] = SA / det;
+    r[GR_CR] = col[0]; r[GR_CG] = col[1]; r[GR_CB] = col[2];
+    r[GR_DEPTH] = tz;
+    r[GR_SA] = SA; r[GR_SB] = SB; r[GR_SC] = SC;
+    r[GR_PRIM] = p;
+    double kappa = sqrt(f->kappa2);
+    r[GR_RX] = kappa * sqrt(SA);
+    r[GR_RY] = kappa * sqrt(SC);
+    for (int d = 0; d < 3; ++d) { r[GR_SX + d] = S[d]; r[GR_TX + d] = t[d]; }
+    r[GR_SIGMA] = 0.0;
+    if (boundary) {
+        /* isotropic boundary Gaussian of scale r_b projected to the image:
+         * r_b^2 J J^T + low-pass; its radius is 3 sqrt(lambda_max) */
+        double rb = f->cfg.r_ref / (double)f->sc.sharpness[p];
+        double ma = rb * rb * (J[0] * J[0] + J[2] * J[2]) + f->cfg.dilation;
+        double mb = rb * rb * (J[2] * J[5]);
+        double mc = rb * rb * (J[4] * J[4] + J[5] * J[5]) + f->cfg.dilation;
+        double lam = 0.5 * (ma + mc) + sqrt(0.25 * (ma - mc) * (ma - mc) + mb * mb);
+        r[GR_SIGMA] = 3.0 * sqrt(lam);
+    }
+    return 1;
+}
+
+/* (u, v) of lattice Gaussian `node` (nodes (a, b), a + b <= level, in the
+ * lattice order, a outer) */
+static void lattice_uv(int level, int node, double *u, double *v) {
+    int a = 0;
+    while (node > level - a) { node -= level - a + 1; ++a; }
+    *u = (double)a / level;
+    *v = (double)node / level;
+}
+
+/* Gaussian records: one per foreground pixel at I_uv (Sec. 3.2, Sub-Primitive
+ * Generation).  In the lattice variant the pixel records only serve the
+ * boundary points, and the rendered Gaussians sit on a lattice of each
+ * patch's (u, v) domain, view by view. */
+static void gen_gaussians(orc_frame *f) {
+    size_t npx = (size_t)f->W * f->H;
     #pragma omp parallel for schedule(static)
     for (long long pi = 0; pi < (long long)npx; ++pi) {
         size_t pix = (size_t)pi;
         double *r = &f->rec[pix * GR_N];
         f->valid[pix] = 0;
+        f->has_rec[pix] = 0;
         int tri = f->I_tri[pix];
         if (tri < 0) { f->is_b[pix] = 0; continue; }
         int p = tri / f->L2;
-        double u = f->I_uv[2 * pix], v = f->I_uv[2 * pix + 1], w = 1.0 - u - v;
-        double cp[64 * 3], cc[64 * 3], S[3], col[3], t[3];
-        prim_points(f->sc.ctrl, ncp, P, p, cp);
-        prim_points(f->sc.color_ctrl, ncp, P, p, cc);
-        orc_surface(n, cp, u, v, w, S);   /* Eq. 3 */
-        orc_surface(n, cc, u, v, w, col); /* Eq. 4 */
-        if (f->sc.sh_degree > 0) {        /* view-dependent colour of the patch's SH coefficients */
-            int K = sh_count(f->sc.sh_degree);
-            double C[3], dv[3], Y[15];
-            cam_centre(f->cam, C);
-            for (int c = 0; c < 3; ++c) dv[c] = S[c] - C[c];
-            double len = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-            for (int c = 0; c < 3; ++c) dv[c] /= len;
-            sh_basis(f->sc.sh_degree, dv, Y, NULL);
-            for (int ch = 0; ch < 3; ++ch)
-                for (int k = 0; k < K; ++k) col[ch] += Y[k] * f->sc.sh[((size_t)ch * K + k) * P + p];
+        if (!make_record(f, p, f->I_uv[2 * pix], f->I_uv[2 * pix + 1], f->is_b[pix], r)) {
+            f->is_b[pix] = 0;
+            continue;
         }
-        cam_apply(f->cam, S, t);
-        if (!(t[2] > f->cfg.z_near)) { f->is_b[pix] = 0; continue; }
-        double tz = t[2];
-        double J[6] = {fx / tz, 0.0, -fx * t[0] / (tz * tz), 0.0, fy / tz, -fy * t[1] / (tz * tz)};
-        double Tm[6];
-        for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < 3; ++c)
-                Tm[3 * a + c] = J[3 * a] * Wc[c] + J[3 * a + 1] * Wc[3 + c] + J[3 * a + 2] * Wc[6 + c];
-        /* Eq. 5: rotation and scale from the attribute maps at I_uv */
-        double ls[3], qn[4], qnorm, Rq[9], M[9], S3[9], tw[3];
-        int ti[3], nt;
-        pixel_attr(f, p, u, v, ls, qn, &qnorm, ti, tw, &nt);
-        quat_to_rot(qn, Rq);
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c) M[3 * a + c] = Rq[3 * a + c] * exp(ls[c]);
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c)
-                S3[3 * a + c] = M[3 * a] * M[3 * c] + M[3 * a + 1] * M[3 * c + 1] + M[3 * a + 2] * M[3 * c + 2];
-        double TS[6];
-        for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < 3; ++c)
-                TS[3 * a + c] = Tm[3 * a] * S3[c] + Tm[3 * a + 1] * S3[3 + c] + Tm[3 * a + 2] * S3[6 + c];
-        double SA = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + f->cfg.dilation;
-        double SB = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
-        double SC = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + f->cfg.dilation;
-        double det = SA * SC - SB * SB;
-        r[GR_MUX] = fx * t[0] / tz + cx;
-        r[GR_MUY] = fy * t[1] / tz + cy;
-        r[GR_QA] = SC / det;
-        r[GR_QB] = -SB / det;
-        r[GR_QC] = SA / det;
-        r[GR_CR] = col[0]; r[GR_CG] = col[1]; r[GR_CB] = col[2];
-        r[GR_DEPTH] = tz;
-        r[GR_SA] = SA; r[GR_SB] = SB; r[GR_SC] = SC;
-        r[GR_PRIM] = p;
-        double kappa = sqrt(f->kappa2);
-        r[GR_RX] = kappa * sqrt(SA);
-        r[GR_RY] = kappa * sqrt(SC);
-        for (int d = 0; d < 3; ++d) { r[GR_SX + d] = S[d]; r[GR_TX + d] = t[d]; }
-        r[GR_SIGMA] = 0.0;
-        if (f->is_b[pix]) {
-            /* isotropic boundary Gaussian of scale r_b projected to the image:
-             * r_b^2 J J^T + low-pass; its radius is 3 sqrt(lambda_max) */
-            double rb = f->cfg.r_ref / (double)f->sc.sharpness[p];
-            double ma = rb * rb * (J[0] * J[0] + J[2] * J[2]) + f->cfg.dilation;
-            double mb = rb * rb * (J[2] * J[5]);
-            double mc = rb * rb * (J[4] * J[4] + J[5] * J[5]) + f->cfg.dilation;
-            double lam = 0.5 * (ma + mc) + sqrt(0.25 * (ma - mc) * (ma - mc) + mb * mb);
-            r[GR_SIGMA] = 3.0 * sqrt(lam);
+        f->has_rec[pix] = 1;
+        f->valid[pix] = f->nlat == 0;
+    }
+    if (f->nlat) {
+        int NL = f->nlat / f->sc.num_prims;
+        #pragma omp parallel for schedule(static)
+        for (long long i = 0; i < (long long)f->nlat; ++i) {
+            double u, v;
+            lattice_uv(f->lat_level, (int)(i % NL), &u, &v);
+            f->valid[npx + i] = (uint8_t)make_record(f, (int)(i / NL), u, v, 0, &f->rec[(npx + i) * GR_N]);
         }
-        f->valid[pix] = 1;
     }
 }
 
@@ -611,9 +651,10 @@ static int build_lists(orc_frame *f, int which) {
     int TS = f->cfg.tile;
     size_t cap = 0, cnt = 0;
     pair_t *pairs = NULL;
-    for (size_t pix = 0; pix < npx; ++pix) {
-        if (!f->valid[pix]) continue;
-        if (which == 1 && !f->is_b[pix]) continue;
+    size_t nrec = which == 0 ? npx + (size_t)f->nlat : npx;
+    for (size_t pix = 0; pix < nrec; ++pix) {
+        if (which == 0 && !f->valid[pix]) continue;                        /* rendered Gaussians */
+        if (which == 1 && !(f->has_rec[pix] && f->is_b[pix])) continue;   /* boundary points */
         const double *r = &f->rec[pix * GR_N];
         int i0, i1, j0, j1;
         if (which == 0) {
@@ -663,7 +704,7 @@ static int build_lists(orc_frame *f, int which) {
 
 void orc_frame_free(orc_frame *f) {
     if (!f) return;
-    free(f->I_tri); free(f->I_uv); free(f->is_b); free(f->valid); free(f->rec);
+    free(f->I_tri); free(f->I_uv); free(f->is_b); free(f->valid); free(f->has_rec); free(f->rec);
     free(f->g_start); free(f->g_list); free(f->b_start); free(f->b_list);
     free(f);
 }
@@ -672,7 +713,8 @@ orc_frame *orc_frame_create(const orc_scene *sc, const float *cam, int W, int H,
                             const orc_config *cfg, const int32_t *I_tri_in, const double *I_uv_in) {
     if (!sc || !cam || !cfg || W <= 0 || H <= 0 || sc->degree < 1 || sc->degree > 5 ||
         sc->num_prims <= 0 || cfg->L < 1 || cfg->tile <= 0 || (sc->attr_res != 1 && sc->attr_res != 3) ||
-        sc->sh_degree < 0 || sc->sh_degree > 3 || (sc->sh_degree > 0 && !sc->sh))
+        sc->sh_degree < 0 || sc->sh_degree > 3 || (sc->sh_degree > 0 && !sc->sh) ||
+        cfg->lattice == 1 || cfg->lattice < 0 || cfg->lattice > 64)
         return NULL;
     orc_frame *f = (orc_frame *)calloc(1, sizeof(orc_frame));
     if (!f) return NULL;
@@ -687,12 +729,20 @@ orc_frame *orc_frame_create(const orc_scene *sc, const float *cam, int W, int H,
     f->ntiles = f->tiles_x * f->tiles_y;
     f->kappa2 = 2.0 * log(1.0 / cfg->g_min);
     size_t npx = (size_t)W * H;
+    if (cfg->lattice >= 2) {
+        /* m nodes per flat sub-triangle edge: the patch's lattice of level
+         * L (m - 1), nodes on shared sub-triangle edges counted once */
+        f->lat_level = cfg->L * (cfg->lattice - 1);
+        f->nlat = sc->num_prims * ((f->lat_level + 1) * (f->lat_level + 2) / 2);
+    }
+    size_t nrec = npx + (size_t)f->nlat;
     f->I_tri = (int32_t *)malloc(npx * sizeof(int32_t));
     f->I_uv = (double *)calloc(2 * npx, sizeof(double));
     f->is_b = (uint8_t *)calloc(npx, 1);
-    f->valid = (uint8_t *)calloc(npx, 1);
-    f->rec = (double *)calloc(npx * GR_N, sizeof(double));
-    if (!f->I_tri || !f->I_uv || !f->is_b || !f->valid || !f->rec) { orc_frame_free(f); return NULL; }
+    f->valid = (uint8_t *)calloc(nrec, 1);
+    f->has_rec = (uint8_t *)calloc(npx, 1);
+    f->rec = (double *)calloc(nrec * GR_N, sizeof(double));
+    if (!f->I_tri || !f->I_uv || !f->is_b || !f->valid || !f->has_rec || !f->rec) { orc_frame_free(f); return NULL; }
     if (I_tri_in) {
         memcpy(f->I_tri, I_tri_in, npx * sizeof(int32_t));
         if (I_uv_in) memcpy(f->I_uv, I_uv_in, 2 * npx * sizeof(double));
@@ -711,7 +761,7 @@ orc_frame *orc_frame_create(const orc_scene *sc, const float *cam, int W, int H,
 
 void orc_frame_dims(const orc_frame *f, int32_t *out) {
     out[0] = f->W; out[1] = f->H; out[2] = f->tiles_x; out[3] = f->tiles_y;
-    out[4] = f->g_start[f->ntiles]; out[5] = f->b_start[f->ntiles]; out[6] = GR_N;
+    out[4] = f->g_start[f->ntiles]; out[5] = f->b_start[f->ntiles]; out[6] = GR_N; out[7] = f->nlat;
 }
 
 void orc_frame_raster(const orc_frame *f, int32_t *I_tri, double *I_uv, uint8_t *is_b, uint8_t *valid) {
@@ -719,11 +769,14 @@ void orc_frame_raster(const orc_frame *f, int32_t *I_tri, double *I_uv, uint8_t 
     if (I_tri) memcpy(I_tri, f->I_tri, npx * sizeof(int32_t));
     if (I_uv) memcpy(I_uv, f->I_uv, 2 * npx * sizeof(double));
     if (is_b) memcpy(is_b, f->is_b, npx);
-    if (valid) memcpy(valid, f->valid, npx);
+    if (valid) memcpy(valid, f->has_rec, npx);   /* the pixel's Gaussian record exists */
 }
 
-void orc_frame_records(const orc_frame *f, double *rec) {
-    memcpy(rec, f->rec, (size_t)f->W * f->H * GR_N * sizeof(double));
+/* records [H*W + nlat][GR_N] and which of them are rendered Gaussians */
+void orc_frame_records(const orc_frame *f, double *rec, uint8_t *rendered) {
+    size_t nrec = (size_t)f->W * f->H + f->nlat;
+    if (rec) memcpy(rec, f->rec, nrec * GR_N * sizeof(double));
+    if (rendered) memcpy(rendered, f->valid, nrec);
 }
 
 void orc_frame_lists(const orc_frame *f, int which, int32_t *start, int32_t *list) {
@@ -872,10 +925,10 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
                    double *d_log_scale, double *d_quat, double *d_opacity, double *d_sharp, double *d_sh) {
     if (!f || !grad_image) return ORC_EINVAL;
     if (f->sc.sh_degree > 0 && !d_sh) return ORC_EINVAL;
-    size_t npx = (size_t)f->W * f->H;
+    size_t npx = (size_t)f->W * f->H, nrec = npx + (size_t)f->nlat;
     int P = f->sc.num_prims, n = f->sc.degree, ncp = f->ncp;
     int T = f->sc.attr_res * (f->sc.attr_res + 1) / 2, D = f->sc.sh_degree, K = sh_count(D);
-    double *dg = (double *)calloc(npx * DG_N, sizeof(double));
+    double *dg = (double *)calloc(nrec * DG_N, sizeof(double));
     if (!dg) return ORC_ENOMEM;
     const double ln2 = log(2.0);
 
@@ -959,12 +1012,16 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
     memset(d_sharp, 0, (size_t)P * sizeof(double));
     const double *Wc = f->cam;
     double fx = f->cam[12], fy = f->cam[13];
-    for (size_t pix = 0; pix < npx; ++pix) {
-        if (!f->valid[pix]) continue;
-        const double *r = &f->rec[pix * GR_N];
-        const double *g = &dg[pix * DG_N];
+    int NL = f->nlat ? f->nlat / P : 0;
+    for (size_t ri = 0; ri < nrec; ++ri) {
+        /* rendered Gaussians, and pixel records that only serve as boundary points */
+        if (!(f->valid[ri] || (ri < npx && f->has_rec[ri]))) continue;
+        const double *r = &f->rec[ri * GR_N];
+        const double *g = &dg[ri * DG_N];
         int p = (int)r[GR_PRIM];
-        double u = f->I_uv[2 * pix], v = f->I_uv[2 * pix + 1];
+        double u, v;
+        if (ri < npx) { u = f->I_uv[2 * ri]; v = f->I_uv[2 * ri + 1]; }
+        else lattice_uv(f->lat_level, (int)((ri - npx) % NL), &u, &v);
         double B[64];
         orc_bernstein(n, u, v, 1.0 - u - v, B);
         /* colour, Eq. 4 */
@@ -1059,7 +1116,7 @@ int orc_frame_grad(const orc_frame *f, const double *grad_image, double *d_ctrl,
             for (int c = 0; c < 3; ++c)
                 dJ[3 * a + c] = dTm[3 * a] * Wc[3 * c] + dTm[3 * a + 1] * Wc[3 * c + 1] + dTm[3 * a + 2] * Wc[3 * c + 2];
         /* boundary radius sigma = 3 sqrt(lambda_max(r_b^2 J J^T + low-pass)) */
-        if (f->is_b[pix] && g[DG_SIGMA] != 0.0) {
+        if (ri < npx && f->is_b[ri] && g[DG_SIGMA] != 0.0) {
             double rb = f->cfg.r_ref / (double)f->sc.sharpness[p], r2 = rb * rb;
             double ma = r2 * (J[0] * J[0] + J[2] * J[2]) + f->cfg.dilation;
             double mb = r2 * (J[2] * J[5]);

@@ -545,7 +545,7 @@ def test_degree_elevated_scene_renders_the_same(orc):
 
 # ---------------------------------------------------------------- backward
 
-def _fd_setup(orc, degree=2, no_boundary=False, attrs=False):
+def _fd_setup(orc, degree=2, no_boundary=False, attrs=False, lattice=0):
     sc = S.random_triangles(P=4, degree=degree, seed=7, opacity=0.8)
     sc.log_scale[:] += 1.2      # larger Gaussians: more overlap per pixel
     # wide boundary Gaussians (r_b = 1e-2 / s ~ 0.1) so the projected radius
@@ -554,13 +554,14 @@ def _fd_setup(orc, degree=2, no_boundary=False, attrs=False):
     if attrs:   # resolution-3 rotation and scale maps, SH colour of degree 3
         sc = S.with_attributes(sc, attr_res=3, sh_degree=3, seed=3, sh_std=0.3)
     cams = S.make_cameras([(0.3, 0.2, 3.2)], [(26, 21)])
-    cfg = orc.Config(tile=8, g_min=1e-300, t_min=0.0, no_boundary=no_boundary)
+    cfg = orc.Config(tile=8, g_min=1e-300, t_min=0.0, no_boundary=no_boundary, lattice=lattice)
     return sc, cams.cams[0], 26, 21, cfg
 
 
-@pytest.mark.parametrize("degree,no_boundary,attrs", [(2, False, False), (1, False, False), (2, True, False),
-                                                      (2, False, True)])
-def test_gradient_matches_finite_differences(orc, degree, no_boundary, attrs):
+@pytest.mark.parametrize("degree,no_boundary,attrs,lattice", [(2, False, False, 0), (1, False, False, 0),
+                                                              (2, True, False, 0), (2, False, True, 0),
+                                                              (2, False, False, 3), (3, False, True, 4)])
+def test_gradient_matches_finite_differences(orc, degree, no_boundary, attrs, lattice):
     """Backward (Suppl. C and the EWA chain) against FP64 central differences
     of the oracle's own forward with I_id, I_uv and B frozen.  Planar
     (degree-1) patches put every boundary point on its own pixel centre, the
@@ -568,8 +569,10 @@ def test_gradient_matches_finite_differences(orc, degree, no_boundary, attrs):
     Without blending coefficients (w = 1) there is no boundary term, and the
     sharpness gradient is 0.  With resolution-3 attribute maps the rotation
     and scale gradients go to the texels of Eq. 5's interpolation, and the SH
-    colour adds its coefficients and the view direction's dependence on S_q."""
-    sc, cam, W, Ht, cfg = _fd_setup(orc, degree, no_boundary, attrs)
+    colour adds its coefficients and the view direction's dependence on S_q.
+    In the lattice variant the rendered Gaussians sit at fixed (u, v) nodes
+    and the pixel records carry only the boundary points' gradients."""
+    sc, cam, W, Ht, cfg = _fd_setup(orc, degree, no_boundary, attrs, lattice)
     fr0 = orc.Frame(sc, cam, W, Ht, cfg)
     it, iu, isb, _ = fr0.raster()
     assert (isb.sum() == 0) if no_boundary else (isb.sum() > 20)
