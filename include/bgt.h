@@ -117,9 +117,24 @@ typedef struct {
     float dilation;        /* 2-D low-pass added to projected covariances (0.3) */
     float r_ref;           /* r_b = r_ref / sharpness (1e-2) */
     float bg[3];           /* background colour (0, 0, 0) */
-    float pair_factor;     /* Gaussian-tile pair capacity per pixel (4) */
+    float pair_factor;     /* Gaussian-tile pair capacity per Gaussian record (4) */
     float bpair_factor;    /* boundary-tile pair capacity per pixel (2) */
+    int32_t lattice;       /* 0: one Gaussian per foreground pixel (Sec. 3.2; default); m in
+                              2..16: the lattice variant, m Gaussians per flat sub-triangle edge */
 } bgt_config;
+
+/* The lattice variant.  Sec. 3.2 places one Gaussian at every foreground
+ * pixel, at I_uv(q).  With lattice = m the rendered Gaussians are instead
+ * the nodes (a, b), a + b <= M, M = L (m - 1), of each patch's (u, v)
+ * domain at (u, v) = (a/M, b/M): m per edge of every flat sub-triangle,
+ * nodes on edges shared by two sub-triangles counted once, so a patch
+ * carries NL = (M+1)(M+2)/2 Gaussians in every view, evaluated with Eq. 3-5
+ * and the EWA projection like a pixel's.  The boundary points, and so the
+ * blending coefficients of Eq. 6-7, stay those of the foreground pixels.
+ * Records: the state's record array holds the N pixel records (boundary
+ * points only, in this variant) followed by the lattice records, view v,
+ * patch p, node k (a outer, b inner) at N + (v P + p) NL + k.  Each view
+ * needs W H + P NL < 2^24 and all views N + V P NL < 2^31. */
 
 void bgt_default_config(bgt_config *cfg);
 

@@ -34,6 +34,7 @@ struct Shape {
     ViewTable vt;
     Consts k;
     int64_t N, NT;
+    int64_t NR;  // Gaussian records: the N pixel records, then the lattice Gaussians of every view
     int64_t off[BGT_STATE_FIELDS];
     int64_t wverts_off, patch_off, bigsort_off;
 };
@@ -69,6 +70,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     k.T = pr->attr_res * (pr->attr_res + 1) / 2;
     k.K = (pr->sh_degree + 1) * (pr->sh_degree + 1) - 1;
     k.pdw = patch_dw(k.ncp, k.T, k.K);
+    k.lat_level = c.lattice >= 2 ? k.L * (c.lattice - 1) : 0;
+    k.NL = c.lattice >= 2 ? (k.lat_level + 1) * (k.lat_level + 2) / 2 : 0;
     k.batch = c.batch;
     k.flags = c.flags;
     k.z_near = c.z_near;
@@ -103,8 +106,14 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     vt.total_b8 = (int32_t)b8;
     sh.N = px;
     sh.NT = tiles;
-    const int64_t N = px, NT = tiles;
-    k.cap_g = (int64_t)ceil((double)c.pair_factor * (double)N) + 1024;
+    const int64_t lat_view = (int64_t)k.P * k.NL;
+    for (int v = 0; v < vw->n_views; ++v)  // record ids within a view are the low 24 bits of the list keys
+        if ((int64_t)vt.v[v].W * vt.v[v].H + lat_view >= ((int64_t)1 << 24))
+            return fail(ctx, BGT_E_INVALID, "pixels plus lattice Gaussians of a view exceed 2^24");
+    sh.NR = px + (int64_t)vw->n_views * lat_view;
+    if (sh.NR >= ((int64_t)1 << 31)) return fail(ctx, BGT_E_INVALID, "Gaussian records exceed 2^31");
+    const int64_t N = px, NT = tiles, NR = sh.NR;
+    k.cap_g = (int64_t)ceil((double)c.pair_factor * (double)NR) + 1024;
     k.cap_b = (int64_t)ceil((double)c.bpair_factor * (double)N) + 1024;
     if (k.cap_g >= ((int64_t)1 << 31) || k.cap_b >= ((int64_t)1 << 31))
         return fail(ctx, BGT_E_INVALID, "pair capacity exceeds 2^31");
@@ -117,8 +126,8 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_ITRI, 4 * N);
     put(F_IUV, 8 * N);
     put(F_PFLAGS, N);
-    put(F_REC, 64 * N);
-    put(F_GKEY, 8 * N);
+    put(F_REC, 64 * NR);
+    put(F_GKEY, 8 * NR);
     put(F_TFINAL, 4 * N);
     put(F_LAST, 4 * N);
     {
@@ -139,7 +148,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_GLIST, 4 * k.cap_g);
     put(F_BKEYS, 8 * k.cap_b);
     put(F_BLIST, 4 * k.cap_b);
-    put(F_DGAUSS, 48 * N);
+    put(F_DGAUSS, 48 * NR);
     put(F_BIGTRI, 4 * k.cap_big);
     {
         sh.off[F_SCAN] = o;
@@ -436,7 +445,7 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         (e = launch_fill_f32(gp.quat, 0.f, 4LL * k.T * k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.opacity, 0.f, k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(sp.dgauss, 0.f, 12 * sh.N, st)) != hipSuccess)
+        (e = launch_fill_f32(sp.dgauss, 0.f, 12 * sh.NR, st)) != hipSuccess)
         return hip_fail(ctx, e, "fill");
     {
         StageTimer tm(ctx, 4, st);

@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
         if (fl & PF_VALID) {
             const float4 r3 = st.rec[(int64_t)pix * 4 + 3];
             const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
-            if (lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
+            // (in the lattice variant a pixel record is a boundary point only)
+            if (k.NL == 0 && lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
                 gt0 = lo16(gx) / TS; gt1 = hi16(gx) / TS; gu0 = lo16(gy) / TS; gu1 = hi16(gy) / TS;
             }
             gkey = (st.gkey[pix] << 24) | (unsigned long long)lp;
@@ -169,6 +170,41 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
     });
 }
 
+// Lattice variant: the pairs of the lattice Gaussians, one lane per record;
+// a record's key digit is its index within its view, after the view's pixels.
+__global__ void __launch_bounds__(256) k_scatter_lattice(Consts k, ViewTable vt, StatePtrs st) {
+    const int lane = threadIdx.x & 63;
+    const int64_t per_view = (int64_t)k.P * k.NL;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool act = i < (int64_t)vt.n * per_view;
+    const int v = act ? (int)(i / per_view) : 0;
+    const ViewInfo vi = vt.v[v];
+    const int TS = k.tile;
+    int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0;
+    unsigned long long gkey = 0ull;
+    if (act) {
+        const int64_t rid = vt.total_px + i;
+        const float4 r3 = st.rec[rid * 4 + 3];
+        const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
+        if (lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
+            gt0 = lo16(gx) / TS; gt1 = hi16(gx) / TS; gu0 = lo16(gy) / TS; gu1 = hi16(gy) / TS;
+        }
+        const int lr = vi.W * vi.H + (int)(i - v * per_view);
+        gkey = (st.gkey[rid] << 24) | (unsigned long long)lr;
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off,
+                      [&](int t, unsigned long long gm, bool in, int leader) {
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&st.g_cursor[t], __popcll(gm));
+        base = __shfl(base, leader, 64);
+        if (in) {
+            const int slot = base + __popcll(gm & below);
+            if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = gkey;
+        }
+    });
+}
+
 // ------------------------------------------------------------ segment sort
 
 // Ascending bitonic network whose first step of every merge compares mirrored
@@ -196,7 +232,7 @@ __device__ __forceinline__ void bitonic_steps(int n2, CmpX cmpx) {
 
 struct NoGet {};
 
-__global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st) {
+__global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, int lat_per_view) {
     __shared__ unsigned long long keys[kSortLds];
     const int t = blockIdx.x, which = blockIdx.y;
     const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
@@ -224,9 +260,9 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st) 
                 const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
                 x = keep_min ? (y < x ? y : x) : (y < x ? x : y);
             }
-        const int off = vt.v[view_of_tile(vt, t)].px_off;
+        const int v = view_of_tile(vt, t);
         uint32_t *dst = which == 0 ? st.g_list : st.b_list;
-        if (lane < cnt) dst[start + lane] = (uint32_t)(off + (int)(x & 0xFFFFFFull));
+        if (lane < cnt) dst[start + lane] = (uint32_t)record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
         return;
     }
     int n2 = 1;
@@ -237,14 +273,15 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st) 
         const unsigned long long x = keys[a], y = keys[b];
         if (y < x) { keys[a] = y; keys[b] = x; }
     });
-    const int off = vt.v[view_of_tile(vt, t)].px_off;
+    const int v = view_of_tile(vt, t);
     uint32_t *dst = which == 0 ? st.g_list : st.b_list;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) dst[start + i] = (uint32_t)(off + (int)(keys[i] & 0xFFFFFFull));
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
 }
 
 // Segments longer than the LDS buffer: same network on global memory, one
 // block per segment (rare; correctness path).
-__global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st) {
+__global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st, int lat_per_view) {
     const int which = blockIdx.y;
     const int64_t nq = st.counters[C_BIGSORT_Q + which];
     for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
@@ -259,9 +296,10 @@ __global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st) {
             const unsigned long long x = keys[a], y = keys[b];
             if (y < x) { keys[a] = y; keys[b] = x; }
         });
-        const int off = vt.v[view_of_tile(vt, t)].px_off;
+        const int v = view_of_tile(vt, t);
         uint32_t *dst = which == 0 ? st.g_list : st.b_list;
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) dst[start + i] = (uint32_t)(off + (int)(keys[i] & 0xFFFFFFull));
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+            dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
         __syncthreads();
     }
 }
@@ -277,8 +315,13 @@ hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs 
                        st.b_count, st.b_start, st.b_cursor, (const int64_t *)sums, n, nb, k.cap_g, k.cap_b,
                        st.counters);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((vt.total_b8 + 3) / 4)), dim3(256), 0, s, k, vt, st);
-    hipLaunchKernelGGL(k_sort_tiles, dim3(n, 2), dim3(256), 0, s, vt, st);
-    hipLaunchKernelGGL(k_sort_big, dim3(64, 2), dim3(256), 0, s, vt, st);
+    const int lat_per_view = k.P * k.NL;
+    if (lat_per_view > 0) {
+        const int64_t nl = (int64_t)vt.n * lat_per_view;
+        hipLaunchKernelGGL(k_scatter_lattice, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, k, vt, st);
+    }
+    hipLaunchKernelGGL(k_sort_tiles, dim3(n, 2), dim3(256), 0, s, vt, st, lat_per_view);
+    hipLaunchKernelGGL(k_sort_big, dim3(64, 2), dim3(256), 0, s, vt, st, lat_per_view);
     return hipGetLastError();
 }
 

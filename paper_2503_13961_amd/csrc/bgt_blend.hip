@@ -290,12 +290,23 @@ struct SlotPrefetch {
 };
 
 template <int TS, int K>
-__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, const ViewInfo &vi, int kk,
-                                           int ox, int oy, const int *run_prim, int n_runs, bool slow_b) {
+__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, const ViewInfo &vi,
+                                           int total_px, int kk, int ox, int oy, const int *run_prim, int n_runs,
+                                           bool slow_b) {
     using G = TileGeom<TS>;
     const int gp = P.gp;
-    const int lp = gp - vi.px_off;
-    const int x = lp % vi.W - ox, y = lp / vi.W - oy;  // tile-relative pixel of the Gaussian
+    // tile-relative pixel the Gaussian's mean is stored against: its own
+    // pixel, or for a lattice Gaussian the pixel kept in r3.z
+    int x, y;
+    if (gp < total_px) {
+        const int lp = gp - vi.px_off;
+        x = lp % vi.W - ox;
+        y = lp / vi.W - oy;
+    } else {
+        const int a = __float_as_int(P.r3.z);
+        x = lo16(a) - ox;
+        y = hi16(a) - oy;
+    }
 #pragma unroll
     for (int w = 0; w < G::NT / 64; ++w)
         S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
@@ -430,7 +441,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, gc, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
         pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
@@ -482,7 +493,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();  // everyone is done with this batch
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     if (inside) {
         image[3 * (int64_t)pix + 0] = C0 + T * k.bg[0];
@@ -577,7 +588,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, nlast, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
         const int cur_gp = pf.gp;
@@ -686,7 +697,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 }
             }
         }
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (first, i.e. lowest raster

@@ -430,6 +430,57 @@ __device__ __forceinline__ void centre_range(double c, double r, int n, int &lo,
     hi = (int)b;
 }
 
+// EWA projection of a Gaussian at world point S with M = R diag(s) (Eq. 5):
+// mean, J, and Sigma2D = (J W M)(J W M)^T + low-pass.  False when S lies
+// behind z_near.
+struct Ewa {
+    double tz, J00, J02, J11, J12, SA, SB, SC, mux, muy;
+};
+
+__device__ __forceinline__ bool ewa_project(const Consts &k, const Cam &c, const double *S, const double *Mv, Ewa &e) {
+    double t[3];
+    cam_apply(c, S, t);
+    if (!(t[2] > (double)k.z_near)) return false;
+    const double tz = t[2], iz = 1.0 / tz;
+    e.tz = tz;
+    e.J00 = c.fx * iz;
+    e.J02 = -c.fx * t[0] * iz * iz;
+    e.J11 = c.fy * iz;
+    e.J12 = -c.fy * t[1] * iz * iz;
+    double Tm[6];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        Tm[cc] = e.J00 * c.R[cc] + e.J02 * c.R[6 + cc];
+        Tm[3 + cc] = e.J11 * c.R[3 + cc] + e.J12 * c.R[6 + cc];
+    }
+    double V0[3], V1[3];  // V = Tm M, Sigma2D = V V^T + low-pass
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        V0[cc] = Tm[0] * Mv[cc] + Tm[1] * Mv[3 + cc] + Tm[2] * Mv[6 + cc];
+        V1[cc] = Tm[3] * Mv[cc] + Tm[4] * Mv[3 + cc] + Tm[5] * Mv[6 + cc];
+    }
+    e.SA = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + k.dilation;
+    e.SB = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
+    e.SC = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + k.dilation;
+    e.mux = c.fx * t[0] * iz + c.cx;
+    e.muy = c.fy * t[1] * iz + c.cy;
+    return true;
+}
+
+// rotation-scale M = R(q / |q|) diag(e^s) of Eq. 5 from a raw quaternion and log-scales
+__device__ __forceinline__ void rot_scale(const double *qi, const double *lsi, double *Mv) {
+    const double qn = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+    const double w = qi[0] * qn, x = qi[1] * qn, y = qi[2] * qn, z = qi[3] * qn;
+    const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                          2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    const double sc[3] = {exp(lsi[0]), exp(lsi[1]), exp(lsi[2])};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) Mv[3 * r + cc] = Rq[3 * r + cc] * sc[cc];
+}
+
 template <int DEG, bool EXT>
 __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr, const float *cams, StatePtrs st,
                                              const float *__restrict__ patch) {
@@ -567,46 +618,15 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             double Mv[10];
 #pragma unroll
             for (int i = 0; i < 10; ++i) Mv[i] = __hiloint2double(__float_as_int(Rm[2 * i + 1]), __float_as_int(Rm[2 * i]));
-            if constexpr (EXT) {
-                // Eq. 5 from the interpolated maps: M = R(q / |q|) diag(e^s) per pixel
-                const double qn = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
-                const double w = qi[0] * qn, x = qi[1] * qn, y = qi[2] * qn, z = qi[3] * qn;
-                const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                                      2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                                      2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-                const double sc[3] = {exp(lsi[0]), exp(lsi[1]), exp(lsi[2])};
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) Mv[3 * r + cc] = Rq[3 * r + cc] * sc[cc];
-            }
+            // Eq. 5 from the interpolated maps (M per pixel), else the patch's M
+            if constexpr (EXT) rot_scale(qi, lsi, Mv);
             const float opa = Rm[20];
             const Cam c = load_cam(cams, v);
-            double t[3];
-            cam_apply(c, S, t);
-            if (t[2] > (double)k.z_near) {
-                const double tz = t[2], iz = 1.0 / tz;
-                const double J00 = c.fx * iz, J02 = -c.fx * t[0] * iz * iz;
-                const double J11 = c.fy * iz, J12 = -c.fy * t[1] * iz * iz;
-                double Tm[6];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    Tm[cc] = J00 * c.R[cc] + J02 * c.R[6 + cc];
-                    Tm[3 + cc] = J11 * c.R[3 + cc] + J12 * c.R[6 + cc];
-                }
-                // Eq. 5 with a resolution-1 attribute map: M = Rq diag(s) of the patch;
-                // V = Tm M, Sigma2D = V V^T + low-pass
-                double V0[3], V1[3];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    V0[cc] = Tm[0] * Mv[cc] + Tm[1] * Mv[3 + cc] + Tm[2] * Mv[6 + cc];
-                    V1[cc] = Tm[3] * Mv[cc] + Tm[4] * Mv[3 + cc] + Tm[5] * Mv[6 + cc];
-                }
-                const double SA = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + k.dilation;
-                const double SB = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
-                const double SC = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + k.dilation;
+            Ewa e;
+            if (ewa_project(k, c, S, Mv, e)) {
+                const double tz = e.tz, J00 = e.J00, J02 = e.J02, J11 = e.J11, J12 = e.J12;
+                const double SA = e.SA, SB = e.SB, SC = e.SC, mux = e.mux, muy = e.muy;
                 const double idet = 1.0 / (SA * SC - SB * SB);
-                const double mux = c.fx * t[0] * iz + c.cx, muy = c.fy * t[1] * iz + c.cy;
                 int gi0, gi1, gj0, gj1;
                 centre_range(mux, k.kappa * sqrt(SA), vi.W, gi0, gi1);
                 centre_range(muy, k.kappa * sqrt(SC), vi.H, gj0, gj1);
@@ -636,7 +656,10 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;
                 // tiles reached by the Gaussian's support and by the boundary disc
                 const int TS = k.tile;
-                if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS; }
+                // (in the lattice variant the pixel records are boundary points only)
+                if (gi0 <= gi1 && gj0 <= gj1 && k.NL == 0) {
+                    gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS;
+                }
                 if (bi0 <= bi1 && bj0 <= bj1) { bt0 = bi0 / TS; bt1 = bi1 / TS; bu0 = bj0 / TS; bu1 = bj1 / TS; }
             }
             fg = true;
@@ -658,6 +681,110 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
         if (mf) atomicAdd(&slot[0], (unsigned long long)__popcll(mf));
         if (mb) atomicAdd(&slot[1], (unsigned long long)__popcll(mb));
     }
+}
+
+// Lattice variant: the Gaussian of view v, patch p at node (a, b) of the
+// level-M lattice of the patch's domain, (u, v) = (a, b) / M, M = L (m - 1);
+// one lane per record, consecutive lanes walk one patch's nodes.  Eq. 3-5,
+// the SH colour and the EWA projection as for a pixel's Gaussian; the mean
+// is stored relative to the pixel (floor(mu_x), floor(mu_y)), kept in r3.z.
+template <int DEG, bool EXT>
+__global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, const float *cams, StatePtrs st,
+                                                     const float *__restrict__ patch) {
+    constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
+    constexpr int MO = patch_m_off(NCP);
+    const int lane = threadIdx.x & 63;
+    const int64_t per_view = (int64_t)k.P * k.NL;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool act = i < (int64_t)vt.n * per_view;
+    int v = 0, p = 0, node = 0;
+    if (act) {
+        v = (int)(i / per_view);
+        const int64_t r = i - v * per_view;
+        p = (int)(r / k.NL);
+        node = (int)(r - (int64_t)p * k.NL);
+    }
+    const ViewInfo vi = vt.v[v];
+    int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0;
+    if (act) {
+        int a, b;
+        lattice_node(k.lat_level, node, a, b);
+        const double u = (double)a / k.lat_level, vb = (double)b / k.lat_level;
+        double B[NCP];
+        bernstein<DEG>(u, vb, 1.0 - u - vb, B);
+        const float *src = patch + (int64_t)p * k.pdw;
+        double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NCP; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                S[d] += B[c] * (double)src[3 * c + d];
+                col[d] += B[c] * (double)src[3 * NCP + 3 * c + d];
+            }
+        double Mv[10];
+        const double *md = (const double *)(src + MO);  // 8-byte aligned: pdw is a multiple of 16
+#pragma unroll
+        for (int j = 0; j < 9; ++j) Mv[j] = md[j];
+        if constexpr (EXT) {
+            int ti[3];
+            double tw[3], qi[4] = {0.0, 0.0, 0.0, 0.0}, lsi[3] = {0.0, 0.0, 0.0};
+            theta_weights<double>(k.T > 1 ? 3 : 1, u, vb, ti, tw);
+            const float *tx = src + patch_x_off(NCP);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const float *tt = tx + 7 * ti[e];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) qi[d] += tw[e] * (double)tt[d];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) lsi[d] += tw[e] * (double)tt[4 + d];
+            }
+            rot_scale(qi, lsi, Mv);
+            if (k.K > 0) {
+                const float *cm = cams + 16 * v;
+                double dv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    dv[c] = S[c] + ((double)cm[c] * cm[9] + (double)cm[3 + c] * cm[10] + (double)cm[6 + c] * cm[11]);
+                const double il = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+                double Y[15];
+                sh_basis<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il, Y, nullptr);
+                const float *shc = src + patch_sh_off(NCP, k.T);
+                for (int j = 0; j < k.K; ++j)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) col[d] += Y[j] * (double)shc[3 * j + d];
+            }
+        }
+        const Cam c = load_cam(cams, v);
+        Ewa e;
+        float4 *rec = st.rec + ((int64_t)vt.total_px + i) * 4;
+        if (ewa_project(k, c, S, Mv, e)) {
+            const double idet = 1.0 / (e.SA * e.SC - e.SB * e.SB);
+            int gi0, gi1, gj0, gj1;
+            centre_range(e.mux, k.kappa * sqrt(e.SA), vi.W, gi0, gi1);
+            centre_range(e.muy, k.kappa * sqrt(e.SC), vi.H, gj0, gj1);
+            const double fx = floor(e.mux), fy = floor(e.muy);
+            const int ax = (int)fmin(fmax(fx, -30000.0), 30000.0), ay = (int)fmin(fmax(fy, -30000.0), 30000.0);
+            rec[0] = make_float4((float)(e.mux - (ax + 0.5)), (float)(e.muy - (ay + 0.5)), (float)(e.SC * idet),
+                                 (float)(-e.SB * idet));
+            rec[1] = make_float4((float)(e.SA * idet), (float)col[0], (float)col[1], (float)col[2]);
+            rec[2] = make_float4(src[6 * NCP], __int_as_float(p), 0.f, (float)e.tz);
+            rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
+                                 __int_as_float(pack16(ax, ay)), 0.f);
+            st.gkey[vt.total_px + i] = ((unsigned long long)__double_as_longlong(e.tz)) >> 24;
+            const int TS = k.tile;
+            if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS; }
+        } else {
+            // behind z_near: empty ranges, never listed
+            rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[2] = make_float4(0.f, __int_as_float(p), 0.f, 0.f);
+            rec[3] = make_float4(__int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)), 0.f, 0.f);
+            st.gkey[vt.total_px + i] = 0ull;
+        }
+    }
+    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off, [&](int t, unsigned long long gm, bool, int leader) {
+        if (lane == leader) atomicAdd(&st.g_count[t], __popcll(gm));
+    });
 }
 
 hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
@@ -706,6 +833,20 @@ hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, 
                 if (ext) hipLaunchKernelGGL((k_gen<5, true>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
                 else hipLaunchKernelGGL((k_gen<5, false>), grid, block, 0, s, k, vt, pr, cams, st, st.patch);
                 break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (k.NL > 0) {
+        const int64_t n = (int64_t)vt.n * k.P * k.NL;
+        dim3 grid((unsigned)((n + 255) / 256)), block(256);
+        switch (k.degree) {
+#define BGT_LAT(D)                                                                                               \
+    case D:                                                                                                      \
+        if (ext) hipLaunchKernelGGL((k_gen_lattice<D, true>), grid, block, 0, s, k, vt, cams, st, st.patch);    \
+        else hipLaunchKernelGGL((k_gen_lattice<D, false>), grid, block, 0, s, k, vt, cams, st, st.patch);       \
+        break;
+            BGT_LAT(1) BGT_LAT(2) BGT_LAT(3) BGT_LAT(4) BGT_LAT(5)
+#undef BGT_LAT
             default: return hipErrorInvalidValue;
         }
     }

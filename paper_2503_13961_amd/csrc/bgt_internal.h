@@ -117,6 +117,7 @@ struct Consts {
     int32_t degree, ncp, P, T;
     int32_t batch, flags;  // flags: BGT_FLAG_* of the configuration
     int32_t K, pdw;        // SH coefficients per channel; dwords per patch record
+    int32_t lat_level, NL; // lattice variant: level L (m - 1) and Gaussians per patch; NL = 0 otherwise
     float z_near, g_min, t_min, alpha_max, dilation, r_ref;
     float bg[3];
     float kappa2;          // 2 ln(1/g_min), float
@@ -164,6 +165,8 @@ struct VertRec {
 //  r1 = (Q_c, c_r, c_g, c_b)
 //  r2 = (opacity, prim (int bits), sigma_b, depth)
 //  r3 = (g x-range, g y-range, b x-range, b y-range) as int16 pairs (lo | hi << 16)
+// A lattice Gaussian has no pixel of its own: its mean is relative to the
+// pixel (x, y) stored in r3.z as an int16 pair (x | y << 16), r3.w unused.
 struct StatePtrs {
     int64_t *counters;
     unsigned long long *zbuf;
@@ -181,13 +184,22 @@ struct StatePtrs {
     int32_t *b_count, *b_start, *b_cursor;
     unsigned long long *g_keys, *b_keys;
     uint32_t *g_list, *b_list;
-    float *dgauss;         // [N_px][12]
+    float *dgauss;         // [records][12]
     int32_t *big_tris;     // [cap_big] queue of raster items
     int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
     int32_t *scan_tmp;     // block sums
 };
 
 __device__ __forceinline__ int pack16(int lo, int hi) { return (lo & 0xFFFF) | (hi << 16); }
+
+// Record index of a tile-list key's low digits `lr`, the record's index
+// within its view v: the view's pixels first, then its lattice Gaussians
+// (lat_per_view = P NL of them, stored after all views' pixels).
+__device__ __forceinline__ int record_of(const ViewTable &vt, int v, int lr, int lat_per_view) {
+    const ViewInfo &vi = vt.v[v];
+    const int npx = vi.W * vi.H;
+    return lr < npx ? vi.px_off + lr : vt.total_px + v * lat_per_view + (lr - npx);
+}
 __device__ __forceinline__ int lo16(int v) { return (int)(int16_t)(v & 0xFFFF); }
 __device__ __forceinline__ int hi16(int v) { return v >> 16; }
 

@@ -5,7 +5,9 @@
 //   dl/dp^c_ijk = sum_q B^n_ijk(I_uv(q)) dl/dc_q     (Eq. 4)
 // plus log-scale, rotation, opacity and sharpness.  One wave covers an 8x8
 // pixel block; pixels of the same primitive are summed across the wave
-// (segmented by primitive id) before one atomic per parameter.
+// (segmented by primitive id) before one atomic per parameter.  In the
+// lattice variant a second launch walks the lattice Gaussians, 64
+// consecutive records (one or two patches) per wave, at their nodes' (u, v).
 #include "bgt_internal.h"
 #include "bgt_sh.h"
 #include "bgt_wave.h"
@@ -46,7 +48,7 @@ __device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int
     }
 }
 
-template <int DEG, bool EXT>
+template <int DEG, bool EXT, bool LAT>
 __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimPtrs pr, const float *cams,
                                                   StatePtrs st, GradPtrs gr, const float *__restrict__ patch) {
     constexpr int NCP = (DEG + 1) * (DEG + 2) / 2;
@@ -78,10 +80,27 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
 #pragma unroll
     for (int i = 0; i < 12; ++i) g[i] = 0.f;
     int v0 = 0;
-    {
+    float2 uv = make_float2(0.f, 0.f);
+    if constexpr (LAT) {
+        // record total_px + i: view i / (P NL), patch, node (a, b) at (a, b) / M
+        const int64_t per_view = (int64_t)k.P * k.NL;
+        const int64_t i = (int64_t)wblock * 64 + lane;
+        if (i < (int64_t)vt.n * per_view) {
+            v0 = (int)(i / per_view);
+            const int64_t r = i - v0 * per_view;
+            const int p = (int)(r / k.NL);
+            int node = (int)(r - (int64_t)p * k.NL), a = 0;
+            while (node > k.lat_level - a) { node -= k.lat_level - a + 1; ++a; }
+            uv = make_float2((float)a / (float)k.lat_level, (float)node / (float)k.lat_level);
+            pix = vt.total_px + (int)i;
+            prim = p;
+        }
+    } else {
         int x0, y0;
         if (block8_pixel(vt, wblock, lane, v0, x0, y0)) pix = vt.v[v0].px_off + y0 * vt.v[v0].W + x0;
-        if (pix >= 0 && (st.pflags[pix] & PF_VALID)) {
+    }
+    {
+        if (pix >= 0 && (LAT || (st.pflags[pix] & PF_VALID))) {
             // the blend sums: moments m0..m4 = sum dG (dx, dy, dx dx, dx dy, dy dy)
             // of dl/dG G, colour, opacity, boundary radius and position
             const float4 *gp = (const float4 *)(st.dgauss + (int64_t)pix * 12);
@@ -93,7 +112,10 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             for (int i = 0; i < 12; ++i) nz = nz || g[i] != 0.f;
             if (nz) {
                 act = true;
-                prim = st.I_tri[pix] / k.L2;
+                if constexpr (!LAT) {
+                    prim = st.I_tri[pix] / k.L2;
+                    uv = st.I_uv[pix];
+                }
             }
         }
     }
@@ -125,7 +147,6 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             const float dsig = g[9], dbx = g[10], dby = g[11];
             {
                 const int p = prim;
-                const float2 uv = st.I_uv[pix];
                 bern_f<DEG>(uv.x, uv.y, 1.f - uv.x - uv.y, B);
                 float S[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -352,31 +373,28 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
 
 hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                             const StatePtrs &st, const GradPtrs &gr, hipStream_t s) {
-    const int nblk = vt.total_b8;
-    dim3 grid((unsigned)((nblk + 3) / 4)), block(256);
     const bool ext = k.T > 1 || k.K > 0;  // resolution-3 maps or SH colour
-    switch (k.degree) {
-        case 1:
-            if (ext) hipLaunchKernelGGL((k_param_bwd<1, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            else hipLaunchKernelGGL((k_param_bwd<1, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            break;
-        case 2:
-            if (ext) hipLaunchKernelGGL((k_param_bwd<2, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            else hipLaunchKernelGGL((k_param_bwd<2, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            break;
-        case 3:
-            if (ext) hipLaunchKernelGGL((k_param_bwd<3, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            else hipLaunchKernelGGL((k_param_bwd<3, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            break;
-        case 4:
-            if (ext) hipLaunchKernelGGL((k_param_bwd<4, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            else hipLaunchKernelGGL((k_param_bwd<4, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            break;
-        case 5:
-            if (ext) hipLaunchKernelGGL((k_param_bwd<5, true>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            else hipLaunchKernelGGL((k_param_bwd<5, false>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch);
-            break;
-        default: return hipErrorInvalidValue;
+    // pixel records (in the lattice variant: boundary points only), then the lattice Gaussians
+    for (int lat = 0; lat < (k.NL > 0 ? 2 : 1); ++lat) {
+        const int64_t waves = lat ? ((int64_t)vt.n * k.P * k.NL + 63) / 64 : vt.total_b8;
+        dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define BGT_PB(D, E, LT) hipLaunchKernelGGL((k_param_bwd<D, E, LT>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch)
+#define BGT_PB_CASE(D)                                  \
+    case D:                                             \
+        if (lat) {                                      \
+            if (ext) BGT_PB(D, true, true);             \
+            else BGT_PB(D, false, true);                \
+        } else {                                        \
+            if (ext) BGT_PB(D, true, false);            \
+            else BGT_PB(D, false, false);               \
+        }                                               \
+        break;
+        switch (k.degree) {
+            BGT_PB_CASE(1) BGT_PB_CASE(2) BGT_PB_CASE(3) BGT_PB_CASE(4) BGT_PB_CASE(5)
+            default: return hipErrorInvalidValue;
+        }
+#undef BGT_PB_CASE
+#undef BGT_PB
     }
     return hipGetLastError();
 }

@@ -22,6 +22,7 @@ void bgt_default_config(bgt_config *c) {
     c->bg[0] = c->bg[1] = c->bg[2] = 0.0f;
     c->pair_factor = 4.0f;
     c->bpair_factor = 2.0f;
+    c->lattice = 0;
 }
 
 void bgt_default_densify_config(bgt_densify_config *c) {
@@ -51,6 +52,7 @@ bgt_status bgt_validate_config(const bgt_config *c) {
         if (!isfinite(c->bg[i])) return BGT_E_INVALID;
     if (!(c->pair_factor > 0.0f && c->pair_factor <= 1024.0f)) return BGT_E_INVALID;
     if (!(c->bpair_factor > 0.0f && c->bpair_factor <= 1024.0f)) return BGT_E_INVALID;
+    if (c->lattice != 0 && (c->lattice < 2 || c->lattice > 16)) return BGT_E_INVALID;
     return BGT_OK;
 }
 

@@ -57,7 +57,7 @@ class bgt_config(C.Structure):
                 ("flags", C.c_int32), ("z_near", C.c_float), ("g_min", C.c_float),
                 ("t_min", C.c_float), ("alpha_max", C.c_float), ("dilation", C.c_float),
                 ("r_ref", C.c_float), ("bg", C.c_float * 3), ("pair_factor", C.c_float),
-                ("bpair_factor", C.c_float)]
+                ("bpair_factor", C.c_float), ("lattice", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -91,6 +91,37 @@ def test_host_only_context_sizes_state_and_refuses_work():
         N.bgt_destroy(ctx)
 
 
+def test_lattice_option_validation_and_state_size():
+    """The lattice variant: m in 2..16 (0 = pixel Gaussians); the record
+    arrays grow by V P NL, NL = (M+1)(M+2)/2, M = L (m - 1); a view whose
+    pixels plus lattice Gaussians exceed 24-bit ids is refused."""
+    assert N.bgt_default_config().lattice == 0
+    for m, want in ((0, N.BGT_OK), (2, N.BGT_OK), (16, N.BGT_OK), (1, N.BGT_E_INVALID), (17, N.BGT_E_INVALID),
+                    (-2, N.BGT_E_INVALID)):
+        assert N.bgt_validate_config(N.bgt_default_config(lattice=m)) == want, m
+    sc, cams, _ = S.workload("sphere2k_16v_800")
+    pr = N.make_prims(2, sc.num_prims, 1, 1, 1, 1, 1, 1)
+    vw = N.make_views(cams.wh, 1)
+    lays = {}
+    for m in (0, 4):
+        ctx = N.bgt_create(N.bgt_default_config(lattice=m), -1)
+        try:
+            lays[m] = N.bgt_state_layout(ctx, pr, vw)
+        finally:
+            N.bgt_destroy(ctx)
+    NR = cams.num_pixels + cams.n_views * sc.num_prims * 91
+    assert lays[4]["gkey"] - lays[4]["rec"] >= 64 * NR and lays[4]["T_final"] - lays[4]["gkey"] >= 8 * NR
+    assert lays[4]["end"] > lays[0]["end"]
+    ctx = N.bgt_create(N.bgt_default_config(lattice=16), -1)
+    try:
+        big = N.make_views(np.array([[4000, 4000]], np.int32), 1)
+        with pytest.raises(N.BgtError) as e:
+            N.bgt_state_size(ctx, N.make_prims(2, 3000, 1, 1, 1, 1, 1, 1), big)
+        assert e.value.status == N.BGT_E_INVALID and "2^24" in N.bgt_last_error(ctx)
+    finally:
+        N.bgt_destroy(ctx)
+
+
 def test_create_rejects_bad_device_and_config():
     with pytest.raises(N.BgtError):
         N.bgt_create(N.bgt_default_config(tile=7), -1)

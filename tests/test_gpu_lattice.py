@@ -1,0 +1,101 @@
+"""Parity of the lattice variant (m Gaussians per flat sub-triangle edge,
+rendered in place of the per-pixel Gaussians) against the oracle run in the
+same mode.  The same bars as the pixel variant: integer outputs bit-exact,
+images within 1e-4, gradients within 1e-3 of each tensor's largest entry.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_13961_amd import scenes as S
+from tests import gpu_common as G
+from tests.test_gpu_parity import GRAD_TOL, IMG_TOL, _workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_record_index(cams, P, NL, v, r):
+    """GPU record of the oracle's record r of view v (pixels, then lattice)."""
+    po = G.view_offsets(cams)
+    npx = int(po[v + 1] - po[v])
+    r = np.asarray(r, np.int64)
+    return np.where(r < npx, po[v] + r, po[-1] + (v * P) * NL + (r - npx))
+
+
+@pytest.mark.parametrize("m,tile", [(4, 16), (2, 8), (3, 32)])
+@pytest.mark.parametrize("name", ["tiny", "sphere_small", "ragged", "degree1", "degree5", "random64_r3_sh3"])
+def test_lattice_stage_parity(name, m, tile):
+    """Index map and boundary set as in the pixel variant; lattice records
+    (mean, conic, colour, depth) against the oracle's; tile lists bit-exact
+    after mapping record ids; images 1e-4."""
+    G.log(f"[lattice_stage] workload={name} m={m} tile={tile}")
+    sc, cams = _workload(name)
+    g = G.run_gpu(sc, cams, tile=tile, lattice=m)
+    assert g["status"] == 0, g["counters"]
+    cfg = G.oracle_config(tile=tile, lattice=m)
+    po, to = G.view_offsets(cams), G.tile_offsets(cams, tile)
+    P = sc.num_prims
+    R = oracle.GR
+    for v, fr in enumerate(G.oracle_frames(sc, cams, cfg)):
+        NL = fr.nlat // P
+        sl = slice(po[v], po[v + 1])
+        it, iu, isb, has = fr.raster()
+        np.testing.assert_array_equal(g["I_tri"][sl], it)
+        np.testing.assert_array_equal((g["pflags"][sl] & 1) != 0, has)
+        np.testing.assert_array_equal((g["pflags"][sl] & 2) != 0, isb)
+        rec, ren = fr.records(rendered=True)
+        lat = np.nonzero(ren)[0]
+        assert len(lat) and (lat >= fr.npx).all()
+        gr = g["rec"][_gpu_record_index(cams, P, NL, v, lat)]
+        anchor = gr[:, 14].view(np.int32)
+        ax = (anchor << 16 >> 16).astype(np.float64)
+        ay = (anchor >> 16).astype(np.float64)
+        assert np.abs(ax + 0.5 + gr[:, 0] - rec[lat, R["MUX"]]).max() < 2e-5 * max(1.0, np.abs(rec[lat, R["MUX"]]).max() / 100)
+        assert np.abs(ay + 0.5 + gr[:, 1] - rec[lat, R["MUY"]]).max() < 2e-5 * max(1.0, np.abs(rec[lat, R["MUY"]]).max() / 100)
+        for j, key in ((2, "QA"), (3, "QB"), (4, "QC")):
+            assert np.abs(gr[:, j] - rec[lat, R[key]]).max() <= 1e-6 * np.abs(rec[lat, R["QA"]]).max()
+        for j, key in ((5, "CR"), (6, "CG"), (7, "CB")):
+            assert np.abs(gr[:, j] - rec[lat, R[key]]).max() < 1e-6
+        np.testing.assert_array_equal(gr[:, 9].view(np.int32), rec[lat, R["PRIM"]].astype(np.int32))
+        assert np.abs(gr[:, 11] - rec[lat, R["DEPTH"]]).max() <= 1e-6 * np.abs(rec[lat, R["DEPTH"]]).max()
+        for which, (cnt, start, lst) in enumerate(((g["g_count"], g["g_start"], g["g_list"]),
+                                                   (g["b_count"], g["b_start"], g["b_list"]))):
+            os_, ol = fr.lists(which)
+            c = cnt[to[v]:to[v + 1]]
+            np.testing.assert_array_equal(c, np.diff(os_))
+            for t in range(len(c)):
+                s0 = start[to[v] + t]
+                want = _gpu_record_index(cams, P, NL, v, ol[os_[t]:os_[t + 1]])
+                np.testing.assert_array_equal(lst[s0:s0 + c[t]], want)
+        img = fr.render()[0]
+        err = np.abs(g["images"][sl] - img).max()
+        G.log(f"    view {v}: {len(lat)} lattice Gaussians, image max abs err {err:.3e}")
+        assert err <= IMG_TOL
+
+
+@pytest.mark.parametrize("name,m,no_b", [("random64", 4, False), ("sphere_small", 4, False), ("degree1", 2, False),
+                                         ("degree5", 3, False), ("random64_r3_sh3", 4, False),
+                                         ("sphere_small", 4, True), ("ragged", 3, False)])
+def test_lattice_gradient_parity(name, m, no_b):
+    """Backward of the lattice variant against the oracle's FP64 gradient
+    (pinned by finite differences in the same mode)."""
+    from paper_2503_13961_amd import native as N
+    G.log(f"[lattice_grad] workload={name} m={m} no_boundary={no_b}")
+    sc, cams = _workload(name)
+    cfg = G.oracle_config(tile=16, lattice=m, no_boundary=no_b)
+    img_ref, frames = oracle.render_views(sc, cams, cfg)
+    gi = G.l1_cotangent(img_ref, S.l1_target(cams.num_pixels))
+    g = G.run_gpu(sc, cams, tile=16, grad_images=gi, lean=True, lattice=m,
+                  flags=N.BGT_FLAG_NO_BOUNDARY if no_b else 0)
+    assert g["status"] == 0, g["counters"]
+    err = np.abs(g["images"] - img_ref).max()
+    G.log(f"    image max abs err {err:.3e}")
+    assert err <= IMG_TOL
+    ref = oracle.grad_views(frames, gi)
+    for k in ref:
+        if no_b and k == "sharpness":
+            assert not g["grads"][k].any()
+            continue
+        e = G.grad_error(g["grads"][k], ref[k])
+        G.log(f"    {k}: {e:.3e}")
+        assert e <= GRAD_TOL, k
