@@ -215,15 +215,16 @@ def profiled_traffic(workload, kernel):
     return b["fetch"] + b["write"]
 
 
-def parity_check(scene, cams, images, samples=6000, seed=0):
-    """Image parity of the timed replay's output on sampled pixels of every view."""
+def parity_check(scene, cams, images, samples=6000, seed=0, views=None, **mode):
+    """Image parity of the timed replay's output on sampled pixels of every
+    view (or of `views`); `mode` sets the oracle's variant (e.g. lattice=4)."""
     import oracle
     cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
-                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
+                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)), **mode)
     rng = np.random.default_rng(seed)
     off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
     worst = 0.0
-    for v in range(cams.n_views):
+    for v in (range(cams.n_views) if views is None else views):
         W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
         fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
         pix = rng.choice(W * H, size=min(samples // cams.n_views, W * H), replace=False).astype(np.int32)
@@ -367,6 +368,28 @@ def main():
             "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
             "what": "resolution-3 rotation and scale maps and degree-3 SH colour (the paper's full model)"}
         log(f"[bench] variant with resolution-3 maps and SH degree 3: {ms_v:.3f} ms/step")
+        del vs, gv
+        # the lattice variant: m = 4 Gaussians per flat sub-triangle edge
+        # (91 per patch and view) in place of the per-pixel Gaussians, sized
+        # to the lattice spacing; the image of the last replay is checked on
+        # sampled pixels of four views
+        lat = S.lattice_scaled(scene, m=4, L=4)
+        vs = Step(Renderer(0, tile=tile, batch=batch, lattice=4), lat.degree, scene_tensors(lat, dev), camt, wh,
+                  target)
+        gv = capture(vs)
+        ms_v = time_replays(gv, args.steps, args.warmup)
+        _, lc = vs.r.query(vs.state)
+        lerr = None
+        if not args.no_parity:
+            lerr = parity_check(lat, cams, vs.images.detach().cpu().numpy(), samples=4000,
+                                views=range(0, cams.n_views, max(1, cams.n_views // 4)), lattice=4)
+        out["variants"]["lattice_m4"] = {
+            "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+            "gaussians": int(cams.n_views * scene.num_prims * 91), "gauss_pairs": int(lc[1]),
+            "image_max_abs_err_sampled": lerr,
+            "what": "4 Gaussians per flat sub-triangle edge (91 per patch and view) instead of one per pixel, "
+                    "log-scales set to 0.6 x the lattice spacing"}
+        log(f"[bench] lattice variant: {ms_v:.3f} ms/step, {lc[1]} pairs, sampled image err {lerr}")
         del vs, gv
     if not args.no_train_step:
         # one optimisation iteration of Sec. 3.3 on the same views: forward,

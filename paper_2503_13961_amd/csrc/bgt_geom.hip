@@ -430,16 +430,14 @@ __device__ __forceinline__ void centre_range(double c, double r, int n, int &lo,
     hi = (int)b;
 }
 
-// EWA projection of a Gaussian at world point S with M = R diag(s) (Eq. 5):
-// mean, J, and Sigma2D = (J W M)(J W M)^T + low-pass.  False when S lies
-// behind z_near.
+// EWA projection of a Gaussian at camera-space point t with M = R diag(s)
+// (Eq. 5): mean, J, and Sigma2D = (J W M)(J W M)^T + low-pass.  False when
+// t lies behind z_near.
 struct Ewa {
     double tz, J00, J02, J11, J12, SA, SB, SC, mux, muy;
 };
 
-__device__ __forceinline__ bool ewa_project(const Consts &k, const Cam &c, const double *S, const double *Mv, Ewa &e) {
-    double t[3];
-    cam_apply(c, S, t);
+__device__ __forceinline__ bool ewa_project(const Consts &k, const Cam &c, const double *t, const double *Mv, Ewa &e) {
     if (!(t[2] > (double)k.z_near)) return false;
     const double tz = t[2], iz = 1.0 / tz;
     e.tz = tz;
@@ -622,8 +620,10 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
             if constexpr (EXT) rot_scale(qi, lsi, Mv);
             const float opa = Rm[20];
             const Cam c = load_cam(cams, v);
+            double t[3];
+            cam_apply(c, S, t);
             Ewa e;
-            if (ewa_project(k, c, S, Mv, e)) {
+            if (ewa_project(k, c, t, Mv, e)) {
                 const double tz = e.tz, J00 = e.J00, J02 = e.J02, J11 = e.J11, J12 = e.J12;
                 const double SA = e.SA, SB = e.SB, SC = e.SC, mux = e.mux, muy = e.muy;
                 const double idet = 1.0 / (SA * SC - SB * SB);
@@ -713,14 +713,29 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
         double B[NCP];
         bernstein<DEG>(u, vb, 1.0 - u - vb, B);
         const float *src = patch + (int64_t)p * k.pdw;
-        double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0};
+        const Cam c = load_cam(cams, v);
+        // S (Eq. 1 summed in control-point order) and its camera coordinates
+        // with each product rounded before its sum (no FMA contraction).  The
+        // depth key decides the list order; a node that two patches share
+        // (on their common edge) has equal depths in exact arithmetic, and
+        // with an axis-aligned camera such depths often fall exactly on a key
+        // boundary, where a one-ulp difference in rounding swaps the two
+        // copies.  Evaluated as plain IEEE sums and products in this order,
+        // the depth is reproducible by any evaluation in the same order.
+        double S[3] = {0.0, 0.0, 0.0}, col[3] = {0.0, 0.0, 0.0}, t[3];
+        {
+#pragma clang fp contract(off)
 #pragma unroll
-        for (int c = 0; c < NCP; ++c)
+            for (int cc = 0; cc < NCP; ++cc)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                S[d] += B[c] * (double)src[3 * c + d];
-                col[d] += B[c] * (double)src[3 * NCP + 3 * c + d];
-            }
+                for (int d = 0; d < 3; ++d) S[d] += B[cc] * (double)src[3 * cc + d];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) t[r] = c.R[3 * r] * S[0] + c.R[3 * r + 1] * S[1] + c.R[3 * r + 2] * S[2] + c.t[r];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NCP; ++cc)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) col[d] += B[cc] * (double)src[3 * NCP + 3 * cc + d];
         double Mv[10];
         const double *md = (const double *)(src + MO);  // 8-byte aligned: pdw is a multiple of 16
 #pragma unroll
@@ -754,10 +769,9 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
                     for (int d = 0; d < 3; ++d) col[d] += Y[j] * (double)shc[3 * j + d];
             }
         }
-        const Cam c = load_cam(cams, v);
         Ewa e;
         float4 *rec = st.rec + ((int64_t)vt.total_px + i) * 4;
-        if (ewa_project(k, c, S, Mv, e)) {
+        if (ewa_project(k, c, t, Mv, e)) {
             const double idet = 1.0 / (e.SA * e.SC - e.SB * e.SB);
             int gi0, gi1, gj0, gj1;
             centre_range(e.mux, k.kappa * sqrt(e.SA), vi.W, gi0, gi1);

@@ -392,6 +392,27 @@ def workload(name: str, seed: int = 0):
     raise KeyError(name)
 
 
+def lattice_scaled(scene: Scene, m: int = 4, L: int = 4, c: float = 0.6) -> Scene:
+    """The scene with Gaussians sized for the lattice variant (m Gaussians
+    per flat sub-triangle edge at tessellation level L): the log-scales of
+    patch p shifted so that their mean is log(c h_p), h_p = the mean length
+    of its three corner edges over L (m - 1), the lattice spacing, so that
+    neighbouring lattice Gaussians overlap and cover the patch.  The
+    per-axis offsets (the anisotropy) and the rotations are kept."""
+    n = scene.degree
+    ids = cp_indices(n)
+    corner = [ids.index((n, 0, 0)), ids.index((0, n, 0)), ids.index((0, 0, n))]
+    X = scene.ctrl[:, corner, :].astype(np.float64)            # [3][3 corners][P]
+    edges = [np.linalg.norm(X[:, a] - X[:, b], axis=0) for a, b in ((0, 1), (1, 2), (2, 0))]
+    h = (edges[0] + edges[1] + edges[2]) / 3.0 / (L * (m - 1))
+    out = scene.copy()
+    ls = scene.log_scale.astype(np.float64)
+    ls = ls - ls.mean(axis=(0, 1), keepdims=True) + np.log(c * h)[None, None, :]
+    out.log_scale = np.ascontiguousarray(ls, dtype=np.float32)
+    out.name = scene.name + f"_lattice{m}"
+    return out
+
+
 def l1_target(num_pixels: int, seed: int = 0) -> np.ndarray:
     """Random target image for the L1 cotangent, U[0,1] per pixel-channel."""
     return np.random.default_rng(1000 + seed).random((num_pixels, 3)).astype(np.float32)
