@@ -146,8 +146,8 @@ __device__ __forceinline__ void stage_boundary(BL &B, const StatePtrs &st, int b
         const int bpix = (int)st.b_list[bs0 + e];
         const float4 r0 = st.rec[(int64_t)bpix * 4];
         const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
-        const int lp = bpix - vi.px_off;
-        B.bxy[e] = pack16(lp % vi.W - ox, lp / vi.W - oy);  // relative to the tile origin
+        const int a = __float_as_int(r2.w);                  // the record's pixel
+        B.bxy[e] = pack16(lo16(a) - ox, hi16(a) - oy);       // relative to the tile origin
         B.bdx[e] = r0.x;
         B.bdy[e] = r0.y;
         B.bs[e] = r2.z;
@@ -231,8 +231,8 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
         const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
         if (__float_as_int(r2.y) != g) break;
         const float4 r0 = st.rec[(int64_t)bpix * 4];
-        const int lp = bpix - vi.px_off;
-        const float dx = (float)(px - lp % vi.W) - r0.x, dy = (float)(py - lp / vi.W) - r0.y;
+        const int a = __float_as_int(r2.w);
+        const float dx = (float)(px - lo16(a)) - r0.x, dy = (float)(py - hi16(a)) - r0.y;
         const float d = bdist(dx, dy), q = __fdiv_rn(d, r2.z);
         const float gm = gamma_fn(d, r2.z);
         if (gm < best) best = gm;
@@ -290,23 +290,12 @@ struct SlotPrefetch {
 };
 
 template <int TS, int K>
-__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, const ViewInfo &vi,
-                                           int total_px, int kk, int ox, int oy, const int *run_prim, int n_runs,
-                                           bool slow_b) {
+__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, int kk, int ox, int oy,
+                                           const int *run_prim, int n_runs, bool slow_b) {
     using G = TileGeom<TS>;
-    const int gp = P.gp;
-    // tile-relative pixel the Gaussian's mean is stored against: its own
-    // pixel, or for a lattice Gaussian the pixel kept in r3.z
-    int x, y;
-    if (gp < total_px) {
-        const int lp = gp - vi.px_off;
-        x = lp % vi.W - ox;
-        y = lp / vi.W - oy;
-    } else {
-        const int a = __float_as_int(P.r3.z);
-        x = lo16(a) - ox;
-        y = hi16(a) - oy;
-    }
+    // tile-relative pixel the Gaussian's mean is stored against
+    const int a = __float_as_int(P.r2.w);
+    const int x = lo16(a) - ox, y = hi16(a) - oy;
 #pragma unroll
     for (int w = 0; w < G::NT / 64; ++w)
         S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
@@ -441,7 +430,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, gc, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
         pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
@@ -493,7 +482,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();  // everyone is done with this batch
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     if (inside) {
         image[3 * (int64_t)pix + 0] = C0 + T * k.bg[0];
@@ -588,7 +577,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, nlast, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
         const int cur_gp = pf.gp;
@@ -656,10 +645,11 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                             sg = B.bs[arg];
                         } else {
                             const float4 r0 = st.rec[(int64_t)bpix * 4];
-                            const int lp = bpix - vi.px_off;
-                            ddx = (float)(px - lp % vi.W) - r0.x;
-                            ddy = (float)(py - lp / vi.W) - r0.y;
-                            sg = st.rec[(int64_t)bpix * 4 + 2].z;
+                            const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
+                            const int a = __float_as_int(r2.w);
+                            ddx = (float)(px - lo16(a)) - r0.x;
+                            ddy = (float)(py - hi16(a)) - r0.y;
+                            sg = r2.z;
                         }
                         const float d = sqrtf(ddx * ddx + ddy * ddy);
                         const float dd = dgm * LN2 / sg * gam;
@@ -697,7 +687,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 }
             }
         }
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, vi, vt.total_px, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (first, i.e. lowest raster

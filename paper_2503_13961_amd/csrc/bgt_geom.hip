@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 rec[0] = make_float4((float)(mux - (x + 0.5)), (float)(muy - (y + 0.5)), (float)(SC * idet),
                                      (float)(-SB * idet));
                 rec[1] = make_float4((float)(SA * idet), (float)col[0], (float)col[1], (float)col[2]);
-                rec[2] = make_float4(opa, __int_as_float(p), sigma, (float)tz);
+                rec[2] = make_float4(opa, __int_as_float(p), sigma, __int_as_float(pack16(x, y)));
                 rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
                                      __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
                 st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;
@@ -687,7 +687,7 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
 // level-M lattice of the patch's domain, (u, v) = (a, b) / M, M = L (m - 1);
 // one lane per record, consecutive lanes walk one patch's nodes.  Eq. 3-5,
 // the SH colour and the EWA projection as for a pixel's Gaussian; the mean
-// is stored relative to the pixel (floor(mu_x), floor(mu_y)), kept in r3.z.
+// is stored relative to the pixel (floor(mu_x), floor(mu_y)), kept in r2.w.
 template <int DEG, bool EXT>
 __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, const float *cams, StatePtrs st,
                                                      const float *__restrict__ patch) {
@@ -781,9 +781,9 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
             rec[0] = make_float4((float)(e.mux - (ax + 0.5)), (float)(e.muy - (ay + 0.5)), (float)(e.SC * idet),
                                  (float)(-e.SB * idet));
             rec[1] = make_float4((float)(e.SA * idet), (float)col[0], (float)col[1], (float)col[2]);
-            rec[2] = make_float4(src[6 * NCP], __int_as_float(p), 0.f, (float)e.tz);
+            rec[2] = make_float4(src[6 * NCP], __int_as_float(p), 0.f, __int_as_float(pack16(ax, ay)));
             rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
-                                 __int_as_float(pack16(ax, ay)), 0.f);
+                                 __int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)));
             st.gkey[vt.total_px + i] = ((unsigned long long)__double_as_longlong(e.tz)) >> 24;
             const int TS = k.tile;
             if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS; }
@@ -792,7 +792,8 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
             rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[2] = make_float4(0.f, __int_as_float(p), 0.f, 0.f);
-            rec[3] = make_float4(__int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)), 0.f, 0.f);
+            rec[3] = make_float4(__int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)),
+                                 __int_as_float(pack16(1, 0)));
             st.gkey[vt.total_px + i] = 0ull;
         }
     }

@@ -158,15 +158,16 @@ struct VertRec {
     int32_t X, Y;          // 1/256-px fixed point; X == INT32_MIN marks a culled vertex
 };
 
-// Gaussian record, 4 x float4 per pixel:
+// Gaussian record, 4 x float4 per pixel (and per lattice Gaussian):
 //  r0 = (mu_x - x - 1/2, mu_y - y - 1/2, Q_a, Q_b): the mean relative to the
-//       centre of the Gaussian's own pixel (x, y) keeps FP32 offsets small;
+//       centre of the record's pixel (x, y) keeps FP32 offsets small;
 //       conic Q = [[a, b], [b, c]]
 //  r1 = (Q_c, c_r, c_g, c_b)
-//  r2 = (opacity, prim (int bits), sigma_b, depth)
+//  r2 = (opacity, prim (int bits), sigma_b, (x, y) as an int16 pair x | y << 16)
 //  r3 = (g x-range, g y-range, b x-range, b y-range) as int16 pairs (lo | hi << 16)
-// A lattice Gaussian has no pixel of its own: its mean is relative to the
-// pixel (x, y) stored in r3.z as an int16 pair (x | y << 16), r3.w unused.
+// A pixel's record is at its own pixel; a lattice Gaussian's at the pixel
+// (floor(mu_x), floor(mu_y)), clamped to +-30000.  The depth is kept in
+// the sort key array (gkey) only.
 struct StatePtrs {
     int64_t *counters;
     unsigned long long *zbuf;

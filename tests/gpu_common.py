@@ -49,7 +49,7 @@ def run_gpu(scene, cams, tile=16, L=4, bg=(0.0, 0.0, 0.0), grad_images=None, ren
     out = dict(images=images.cpu().numpy().astype(np.float64), I_tri=sec("I_tri", np.int32, N),
                pflags=sec("pflags", np.uint8, N))
     if not lean:
-        out.update(I_uv=sec("I_uv", np.float32, 2 * N).reshape(N, 2), rec=sec("rec", np.float32, 16 * NR).reshape(NR, 16),
+        out.update(I_uv=sec("I_uv", np.float32, 2 * N).reshape(N, 2), rec=sec("rec", np.float32, 16 * NR).reshape(NR, 16), gkey=sec("gkey", np.uint64, NR),
                    T_final=sec("T_final", np.float32, N), last=sec("last", np.int32, N),
                    g_count=sec("g_count", np.int32, ntiles), g_start=sec("g_start", np.int32, ntiles),
                    b_count=sec("b_count", np.int32, ntiles), b_start=sec("b_start", np.int32, ntiles))

@@ -67,6 +67,12 @@ def test_stage_parity(name, tile):
             assert np.abs(gr[val, j] - ref).max(initial=0) <= 1e-6 * np.abs(rec[val, R["QA"]]).max(initial=1)
         for j, key in ((5, "CR"), (6, "CG"), (7, "CB")):
             assert np.abs(gr[val, j] - rec[val, R[key]]).max(initial=0) < 1e-6
+        # the record's pixel (x | y << 16); the depth sort key (top 40 bits of
+        # the FP64 depth) equal or, where the depth sits on a key boundary, one off
+        anchor = np.ascontiguousarray(gr[val, 11]).view(np.int32)
+        np.testing.assert_array_equal(anchor, (np.arange(fr.npx) % W + (np.arange(fr.npx) // W << 16))[val])
+        kd = g["gkey"][sl][val].astype(np.int64) - (rec[val, R["DEPTH"]].view(np.uint64) >> np.uint64(24)).astype(np.int64)
+        assert np.abs(kd).max(initial=0) <= 1
         sig = rec[isb, R["SIGMA"]]
         assert np.abs(gr[isb, 10] - sig).max(initial=0) <= 1e-6 * max(sig.max(initial=1), 1)
         # per-tile lists: same entries in the same order
