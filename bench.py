@@ -379,6 +379,7 @@ def main():
         gv = capture(vs)
         ms_v = time_replays(gv, args.steps, args.warmup)
         _, lc = vs.r.query(vs.state)
+        lst = stage_profile(vs)
         lerr = None
         if not args.no_parity:
             lerr = parity_check(lat, cams, vs.images.detach().cpu().numpy(), samples=4000,
@@ -386,7 +387,7 @@ def main():
         out["variants"]["lattice_m4"] = {
             "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
             "gaussians": int(cams.n_views * scene.num_prims * 91), "gauss_pairs": int(lc[1]),
-            "image_max_abs_err_sampled": lerr,
+            "image_max_abs_err_sampled": lerr, "stage_ms": {k: round(v, 4) for k, v in lst.items()},
             "what": "4 Gaussians per flat sub-triangle edge (91 per patch and view) instead of one per pixel, "
                     "log-scales set to 0.6 x the lattice spacing"}
         log(f"[bench] lattice variant: {ms_v:.3f} ms/step, {lc[1]} pairs, sampled image err {lerr}")
