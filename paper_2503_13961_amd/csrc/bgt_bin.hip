@@ -3,10 +3,11 @@
 // boundary points go to every tile their radius reaches, sorted by primitive
 // id.  The sort is a two-level radix split: a counting pass on the tile id
 // (the high key digit) places each pair in its tile's segment, then each
-// segment is sorted on the low digits (depth, raster index) or (primitive,
-// raster index) with a bitonic network in LDS.  The low digits make every
-// key unique, so the result does not depend on the order of the atomics that
-// filled the segment.
+// segment is sorted on the low digits (depth, record index) or (primitive,
+// record index): runs of 64 keys sorted in registers by one wave each, then
+// merged pairwise by rank in LDS (segments beyond the LDS buffer: a bitonic
+// network in global memory).  The low digits make every key unique, so the
+// result does not depend on the order of the atomics that filled the segment.
 #include "bgt_internal.h"
 
 namespace bgt {
@@ -232,8 +233,33 @@ __device__ __forceinline__ void bitonic_steps(int n2, CmpX cmpx) {
 
 struct NoGet {};
 
+// Ascending bitonic sort of one key per lane across the wave (64 keys),
+// through lane exchanges only (no LDS, no barriers).
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long x, int lane) {
+    for (int kk = 2; kk <= 64; kk <<= 1)
+        for (int j = kk >> 1; j >= 1; j >>= 1) {
+            const unsigned long long y = __shfl_xor(x, j, 64);
+            // the lower lane of a pair keeps the smaller key in ascending runs
+            const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
+            x = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+        }
+    return x;
+}
+
+// Keys of the sorted a[0, n) below x (UPPER: not above x).
+template <bool UPPER>
+__device__ __forceinline__ int rank_in(const unsigned long long *a, int n, unsigned long long x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (UPPER ? a[mid] <= x : a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, int lat_per_view) {
-    __shared__ unsigned long long keys[kSortLds];
+    __shared__ unsigned long long keys[2][kSortLds];
     const int t = blockIdx.x, which = blockIdx.y;
     const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
     if (cnt == 0) return;
@@ -247,36 +273,44 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
         return;
     }
     const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
+    const int v = view_of_tile(vt, t);
+    uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (cnt <= 64) {
-        // short lists (most boundary lists, border tiles): one wave, one key
-        // per lane, the bitonic network through lane exchanges, no barriers
-        if (threadIdx.x >= 64) return;
-        const int lane = threadIdx.x;
-        unsigned long long x = lane < cnt ? src[start + lane] : ~0ull;
-        for (int kk = 2; kk <= 64; kk <<= 1)
-            for (int j = kk >> 1; j >= 1; j >>= 1) {
-                const unsigned long long y = __shfl_xor(x, j, 64);
-                // the lower lane of a pair keeps the smaller key in ascending runs
-                const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
-                x = keep_min ? (y < x ? y : x) : (y < x ? x : y);
-            }
-        const int v = view_of_tile(vt, t);
-        uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+        // short lists (most boundary lists, border tiles): one wave, one key per lane
+        if (wave != 0) return;
+        const unsigned long long x = wave_sort64(lane < cnt ? src[start + lane] : ~0ull, lane);
         if (lane < cnt) dst[start + lane] = (uint32_t)record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
         return;
     }
-    int n2 = 1;
-    while (n2 < cnt) n2 <<= 1;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) keys[i] = i < cnt ? src[start + i] : ~0ull;
+    // Runs of 64 keys sorted in registers, one wave per run (padded with
+    // ~0, above every key), then merged pairwise by rank: a key's place in
+    // the merged run is its place in its own run plus the number of keys of
+    // the other run before it (keys of the first run go before equal keys of
+    // the second; only the padding repeats).
+    const int n64 = (cnt + 63) & ~63, nruns = n64 >> 6;
+    for (int run = wave; run < nruns; run += blockDim.x >> 6) {
+        const int i = run * 64 + lane;
+        keys[0][i] = wave_sort64(i < cnt ? src[start + i] : ~0ull, lane);
+    }
     __syncthreads();
-    bitonic_steps<NoGet>(n2, [&](int a, int b) {
-        const unsigned long long x = keys[a], y = keys[b];
-        if (y < x) { keys[a] = y; keys[b] = x; }
-    });
-    const int v = view_of_tile(vt, t);
-    uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+    int cur = 0;
+    for (int L = 64; L < n64; L <<= 1) {
+        const unsigned long long *a = keys[cur];
+        unsigned long long *b = keys[cur ^ 1];
+        for (int i = threadIdx.x; i < n64; i += blockDim.x) {
+            const int p0 = i & ~(2 * L - 1);
+            const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
+            const unsigned long long x = a[i];
+            const int pos = i < mid ? (i - p0) + rank_in<false>(a + mid, end - mid, x)
+                                    : (i - mid) + rank_in<true>(a + p0, mid - p0, x);
+            b[p0 + pos] = x;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
     for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[cur][i] & 0xFFFFFFull), lat_per_view);
 }
 
 // Segments longer than the LDS buffer: same network on global memory, one

@@ -339,52 +339,96 @@ __device__ __forceinline__ unsigned long long raster_pixel(const TriSetup &ts, i
     return ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - tri);
 }
 
-__global__ void k_raster(Consts k, ViewTable vt, const VertRec *verts, unsigned long long *zbuf, int32_t *big,
-                         int64_t *counters) {
+// Set-ups of a wave's 64 triangles, for the lanes that rasterize their pixels.
+struct RasterWaveLds {
+    int32_t start[64];      // first pixel of the triangle in the wave's pixel sequence
+    int32_t X[3][64], Y[3][64];
+    double iz[3][64];
+    int64_t A[64];
+    int32_t own[64];        // top-left ownership bits of the three edges
+    int32_t i0[64], j0[64], bw[64];
+    int32_t px_off[64], W[64];
+    uint32_t tri[64];
+};
+
+// One lane per (view, sub-triangle) sets the triangle up; then the wave
+// rasterizes the bounding boxes of its 64 triangles together, one pixel per
+// lane over the concatenated boxes, so that lanes are not held by the
+// largest box of the wave.  Coverage and the z-buffer word are those of
+// raster_pixel (exact int64 edge functions, FP64 1/z plane).
+__global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const VertRec *verts,
+                                                unsigned long long *zbuf, int32_t *big, int64_t *counters) {
+    __shared__ RasterWaveLds R[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    RasterWaveLds &Rw = R[wave];
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t per_view = (int64_t)k.L2 * k.P;
-    if (idx >= per_view * vt.n) return;
-    const int v = (int)(idx / per_view);
-    const int64_t sp = idx % per_view;
-    const int s = (int)(sp / k.P), p = (int)(sp % k.P);
-    const ViewInfo vi = vt.v[v];
-    TriSetup ts;
-    if (!tri_setup(k, vi, verts + (int64_t)v * k.VL * k.P, s, p, ts)) return;
-    const int64_t area = (int64_t)(ts.i1 - ts.i0 + 1) * (ts.j1 - ts.j0 + 1);
-    if (area > kBigTriPixels) {
-        const long long slot = atomicAdd((unsigned long long *)&counters[C_BIGTRI], 1ull);
-        if (slot < k.cap_big) big[slot] = (int32_t)idx;
-        else atomicOr((unsigned long long *)&counters[C_OVERFLOW], 4ull);
-        return;
-    }
-    const uint32_t tri = (uint32_t)(p * k.L2 + s);
-    unsigned long long *zb = zbuf + vi.px_off;
-    // The edge functions are affine in the pixel centre: stepped exactly in
-    // int64 from the bbox corner.
-    const int64_t px0 = 256 * (int64_t)ts.i0 + 128, py0 = 256 * (int64_t)ts.j0 + 128;
-    int64_t Er[3], sx[3], sy[3];
+    int area = 0;
+    if (idx < per_view * vt.n) {
+        const int v = (int)(idx / per_view);
+        const int64_t sp = idx % per_view;
+        const int s = (int)(sp / k.P), p = (int)(sp % k.P);
+        const ViewInfo vi = vt.v[v];
+        TriSetup ts;
+        if (tri_setup(k, vi, verts + (int64_t)v * k.VL * k.P, s, p, ts)) {
+            const int64_t a = (int64_t)(ts.i1 - ts.i0 + 1) * (ts.j1 - ts.j0 + 1);
+            if (a > kBigTriPixels) {
+                const long long slot = atomicAdd((unsigned long long *)&counters[C_BIGTRI], 1ull);
+                if (slot < k.cap_big) big[slot] = (int32_t)idx;
+                else atomicOr((unsigned long long *)&counters[C_OVERFLOW], 4ull);
+            } else {
+                area = (int)a;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int a = (c + 1) % 3, b = (c + 2) % 3;
-        Er[c] = edge_fn(ts.X[a], ts.Y[a], ts.X[b], ts.Y[b], px0, py0);
-        sx[c] = -256 * (ts.Y[b] - ts.Y[a]);  // +1 pixel in x
-        sy[c] = 256 * (ts.X[b] - ts.X[a]);   // +1 pixel in y
-    }
-    for (int j = ts.j0; j <= ts.j1; ++j) {
-        int64_t E0 = Er[0], E1 = Er[1], E2 = Er[2];
-        for (int i = ts.i0; i <= ts.i1; ++i) {
-            const bool in = (E0 > 0 || (E0 == 0 && ts.own[0])) && (E1 > 0 || (E1 == 0 && ts.own[1])) &&
-                            (E2 > 0 || (E2 == 0 && ts.own[2]));
-            if (in) {
-                const double key =
-                    fma((double)E2, ts.iz[2], fma((double)E1, ts.iz[1], (double)E0 * ts.iz[0])) / (double)ts.A;
-                const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
-                const unsigned long long c = ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - tri);
-                atomicMax(&zb[(int64_t)j * vi.W + i], c);
+                for (int c = 0; c < 3; ++c) {
+                    Rw.X[c][lane] = (int32_t)ts.X[c];
+                    Rw.Y[c][lane] = (int32_t)ts.Y[c];
+                    Rw.iz[c][lane] = ts.iz[c];
+                }
+                Rw.A[lane] = ts.A;
+                Rw.own[lane] = (ts.own[0] ? 1 : 0) | (ts.own[1] ? 2 : 0) | (ts.own[2] ? 4 : 0);
+                Rw.i0[lane] = ts.i0;
+                Rw.j0[lane] = ts.j0;
+                Rw.bw[lane] = ts.i1 - ts.i0 + 1;
+                Rw.px_off[lane] = vi.px_off;
+                Rw.W[lane] = vi.W;
+                Rw.tri[lane] = (uint32_t)(p * k.L2 + s);
             }
-            E0 += sx[0]; E1 += sx[1]; E2 += sx[2];
         }
-        Er[0] += sy[0]; Er[1] += sy[1]; Er[2] += sy[2];
+    }
+    int incl = area;  // inclusive scan of the box areas over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    Rw.start[lane] = incl - area;
+    const int total = __shfl(incl, 63, 64);
+    __syncthreads();
+    for (int base = 0; base < total; base += 64) {
+        const int e = base + lane;
+        if (e >= total) break;
+        // the triangle holding pixel e: the last one starting at or before it
+        // (a triangle with an empty box starts where the next one does)
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Rw.start[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int q = lo, r = e - Rw.start[q], bw = Rw.bw[q];
+        const int dy = (int)(((float)r + 0.5f) / (float)bw);  // exact: r < 256, never within 1/512 of an integer
+        const int i = Rw.i0[q] + (r - dy * bw), j = Rw.j0[q] + dy;
+        TriSetup ts;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ts.X[c] = Rw.X[c][q];
+            ts.Y[c] = Rw.Y[c][q];
+            ts.iz[c] = Rw.iz[c][q];
+            ts.own[c] = (Rw.own[q] >> c) & 1;
+        }
+        ts.A = Rw.A[q];
+        const unsigned long long c = raster_pixel(ts, i, j, Rw.tri[q]);
+        if (c) atomicMax(&zbuf[Rw.px_off[q] + (int64_t)j * Rw.W[q] + i], c);
     }
 }
 
