@@ -3,11 +3,15 @@
 // the EWA projection and the boundary radius to the BG-Triangle parameters:
 //   dl/dp_ijk   = sum_q B^n_ijk(I_uv(q)) dl/dS_q     (Supplementary Sec. C)
 //   dl/dp^c_ijk = sum_q B^n_ijk(I_uv(q)) dl/dc_q     (Eq. 4)
-// plus log-scale, rotation, opacity and sharpness.  One wave covers an 8x8
-// pixel block; pixels of the same primitive are summed across the wave
-// (segmented by primitive id) before one atomic per parameter.  In the
-// lattice variant a second launch walks the lattice Gaussians, 64
-// consecutive records (one or two patches) per wave, at their nodes' (u, v).
+// plus log-scale, rotation, opacity and sharpness.  A workgroup covers a
+// 32x32 pixel region, its waves one 8x8 block at a time; pixels of the same
+// primitive are summed across the wave (segmented by primitive id) and the
+// wave sums across the region in an LDS table keyed by primitive, which
+// issues one global atomic per (region, primitive, parameter): the
+// primitives' gradient words are the hottest addresses of the pass, and
+// same-address atomics from many workgroups serialize.  In the lattice
+// variant a second launch walks the lattice Gaussians, 1024 consecutive
+// records (about a dozen patches) per workgroup, at their nodes' (u, v).
 #include "bgt_internal.h"
 #include "bgt_sh.h"
 #include "bgt_wave.h"
@@ -33,9 +37,11 @@ __device__ __forceinline__ void bern_f(float u, float v, float w, float *B) {
 
 // One chunk of up to 64 of a wave's NV per-lane values (from `value`, taken
 // on the lanes where `mine`): reduce-scattered over the wave, then each lane
-// holding a total adds it to its target.
+// holding a total adds it to row `slot` of the workgroup's LDS table, or,
+// without a row (the table is full), to its global target.
 template <int BASE, int NV, typename V, typename T>
-__device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int gl, int lane) {
+__device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int gl, int lane, float *table,
+                                             int slot) {
     constexpr int N = NV - BASE < 64 ? NV - BASE : 64;
     float v[N];
 #pragma unroll
@@ -43,9 +49,54 @@ __device__ __forceinline__ void reduce_chunk(V &value, T &target, bool mine, int
     wave_reduce_scatter<N>(v, lane);
     const int j = BASE + scatter_index(lane);
     if (j < BASE + N && v[0] != 0.f) {
-        float *t = target(j, gl);
-        if (t) unsafeAtomicAdd(t, v[0]);
+        if (slot >= 0) {
+            atomicAdd(&table[slot * NV + j], v[0]);
+        } else {
+            float *t = target(j, gl);
+            if (t) unsafeAtomicAdd(t, v[0]);
+        }
     }
+}
+
+// Row of primitive p (wave-uniform) in the workgroup's table: open
+// addressing over the rows' primitive ids, claimed by compare-and-swap;
+// -1 when every row holds another primitive.
+template <int SLOTS>
+__device__ __forceinline__ int table_slot(int *slot_prim, int p, int lane) {
+    int s = -1;
+    if (lane == 0) {
+        const int h = (int)(((unsigned)p * 2654435761u) >> 16) & (SLOTS - 1);
+        for (int n = 0; n < SLOTS; ++n) {
+            const int q = (h + n) & (SLOTS - 1);
+            const int old = atomicCAS(&slot_prim[q], -1, p);
+            if (old == -1 || old == p) {
+                s = q;
+                break;
+            }
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(s);
+}
+
+constexpr int kRegion = 32;      // pixels per side of a workgroup's region
+constexpr int kRegionPasses = 4; // 8x8 blocks per wave: (32/8)^2 blocks over 4 waves
+constexpr int kLatPerGroup = 256 * kRegionPasses;
+
+// view, region origin of workgroup `reg` (regions of kRegion px, row-major per view)
+__device__ __forceinline__ int region_view(const ViewTable &vt, int reg, int &rx0, int &ry0) {
+    int acc = 0;
+    for (int v = 0; v < vt.n; ++v) {
+        const int nx = (vt.v[v].W + kRegion - 1) / kRegion, ny = (vt.v[v].H + kRegion - 1) / kRegion;
+        if (reg < acc + nx * ny) {
+            const int l = reg - acc;
+            rx0 = (l % nx) * kRegion;
+            ry0 = (l / nx) * kRegion;
+            return v;
+        }
+        acc += nx * ny;
+    }
+    rx0 = ry0 = 0;
+    return -1;
 }
 
 template <int DEG, bool EXT, bool LAT>
@@ -59,10 +110,35 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
     // coefficients (at most 15 per channel)
     constexpr int TM = EXT ? 6 : 1, KM = EXT ? 15 : 0;
     constexpr int NV = 6 * NCP + 7 * TM + 2 + 3 * KM;
-    const int lane = threadIdx.x & 63;
-    // global 8x8 block (wave-uniform: its view is found with scalar loads)
-    const int wblock = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    // locate the view and pixel of this lane
+    constexpr int SLOTS = NV > 100 ? 32 : 64;
+    __shared__ int slot_prim[SLOTS];
+    __shared__ float table[SLOTS * NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) slot_prim[i] = -1;
+    for (int i = threadIdx.x; i < SLOTS * NV; i += blockDim.x) table[i] = 0.f;
+    int rx0 = 0, ry0 = 0, rv = 0;
+    if constexpr (!LAT) rv = region_view(vt, blockIdx.x, rx0, ry0);
+    __syncthreads();
+    auto target = [&](int j, int gl) -> float * {
+        if (j < 3 * NCP) return gr.ctrl + (int64_t)j * k.P + gl;  // [d][c] with j = d NCP + c
+        if (j < 6 * NCP) return gr.color + (int64_t)(j - 3 * NCP) * k.P + gl;
+        const int r = j - 6 * NCP;
+        if (r < 3 * TM) {
+            const int d = r / TM, t = r % TM;
+            return t < k.T ? gr.log_scale + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
+        }
+        if (r < 7 * TM) {
+            const int d = (r - 3 * TM) / TM, t = (r - 3 * TM) % TM;
+            return t < k.T ? gr.quat + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
+        }
+        if (r == 7 * TM) return gr.opacity + gl;
+        if (r == 7 * TM + 1) return gr.sharp + gl;
+        const int h = r - 7 * TM - 2, c = h / (KM > 0 ? KM : 1), jj = h % (KM > 0 ? KM : 1);
+        return jj < k.K ? gr.sh + ((int64_t)c * k.K + jj) * k.P + gl : nullptr;
+    };
+#pragma unroll 1
+    for (int pass = 0; pass < kRegionPasses; ++pass) {
+    // locate the view and pixel (or lattice record) of this lane
     int pix = -1, prim = -1;
     float dS[3] = {0.f, 0.f, 0.f}, dcol[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dop = 0.f, dsh = 0.f;
@@ -84,7 +160,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
     if constexpr (LAT) {
         // record total_px + i: view i / (P NL), patch, node (a, b) at (a, b) / M
         const int64_t per_view = (int64_t)k.P * k.NL;
-        const int64_t i = (int64_t)wblock * 64 + lane;
+        const int64_t i = (int64_t)blockIdx.x * kLatPerGroup + pass * 256 + threadIdx.x;
         if (i < (int64_t)vt.n * per_view) {
             v0 = (int)(i / per_view);
             const int64_t r = i - v0 * per_view;
@@ -95,9 +171,12 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             pix = vt.total_px + (int)i;
             prim = p;
         }
-    } else {
-        int x0, y0;
-        if (block8_pixel(vt, wblock, lane, v0, x0, y0)) pix = vt.v[v0].px_off + y0 * vt.v[v0].W + x0;
+    } else if (rv >= 0) {
+        // block wave + 4 pass of the region's 4x4 blocks of 8x8 pixels
+        const int b = wave + 4 * pass;
+        const int x0 = rx0 + (b & 3) * 8 + (lane & 7), y0 = ry0 + (b >> 2) * 8 + (lane >> 3);
+        v0 = rv;
+        if (x0 < vt.v[rv].W && y0 < vt.v[rv].H) pix = vt.v[rv].px_off + y0 * vt.v[rv].W + x0;
     }
     {
         if (pix >= 0 && (LAT || (st.pflags[pix] & PF_VALID))) {
@@ -343,31 +422,27 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
         const int h = r - 7 * TM - 2;
         return KM > 0 ? Yv[h % (KM > 0 ? KM : 1)] * dcol[h / (KM > 0 ? KM : 1)] : 0.f;
     };
-    auto target = [&](int j, int gl) -> float * {
-        if (j < 3 * NCP) return gr.ctrl + (int64_t)j * k.P + gl;  // [d][c] with j = d NCP + c
-        if (j < 6 * NCP) return gr.color + (int64_t)(j - 3 * NCP) * k.P + gl;
-        const int r = j - 6 * NCP;
-        if (r < 3 * TM) {
-            const int d = r / TM, t = r % TM;
-            return t < k.T ? gr.log_scale + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
-        }
-        if (r < 7 * TM) {
-            const int d = (r - 3 * TM) / TM, t = (r - 3 * TM) % TM;
-            return t < k.T ? gr.quat + ((int64_t)d * k.T + t) * k.P + gl : nullptr;
-        }
-        if (r == 7 * TM) return gr.opacity + gl;
-        if (r == 7 * TM + 1) return gr.sharp + gl;
-        const int h = r - 7 * TM - 2, c = h / (KM > 0 ? KM : 1), jj = h % (KM > 0 ? KM : 1);
-        return jj < k.K ? gr.sh + ((int64_t)c * k.K + jj) * k.P + gl : nullptr;
-    };
     for (unsigned long long pending = __ballot(act); pending;) {
         const int gl = __builtin_amdgcn_readlane(prim, __ffsll((long long)pending) - 1);
         const bool mine = act && prim == gl;
         pending &= ~__ballot(mine);
-        reduce_chunk<0, NV>(value, target, mine, gl, lane);
-        if constexpr (NV > 64) reduce_chunk<64, NV>(value, target, mine, gl, lane);
-        if constexpr (NV > 128) reduce_chunk<128, NV>(value, target, mine, gl, lane);
-        if constexpr (NV > 192) reduce_chunk<192, NV>(value, target, mine, gl, lane);
+        const int slot = table_slot<SLOTS>(slot_prim, gl, lane);
+        reduce_chunk<0, NV>(value, target, mine, gl, lane, table, slot);
+        if constexpr (NV > 64) reduce_chunk<64, NV>(value, target, mine, gl, lane, table, slot);
+        if constexpr (NV > 128) reduce_chunk<128, NV>(value, target, mine, gl, lane, table, slot);
+        if constexpr (NV > 192) reduce_chunk<192, NV>(value, target, mine, gl, lane, table, slot);
+    }
+    }  // passes
+    // the region's sums: one global atomic per (primitive, parameter)
+    __syncthreads();
+    for (int i = threadIdx.x; i < SLOTS * NV; i += blockDim.x) {
+        const int s = i / NV, j = i - s * NV;
+        const int p = slot_prim[s];
+        const float val = table[i];
+        if (p >= 0 && val != 0.f) {
+            float *t = target(j, p);
+            if (t) unsafeAtomicAdd(t, val);
+        }
     }
 }
 
@@ -375,9 +450,12 @@ hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs
                             const StatePtrs &st, const GradPtrs &gr, hipStream_t s) {
     const bool ext = k.T > 1 || k.K > 0;  // resolution-3 maps or SH colour
     // pixel records (in the lattice variant: boundary points only), then the lattice Gaussians
+    int64_t regions = 0;
+    for (int v = 0; v < vt.n; ++v)
+        regions += (int64_t)((vt.v[v].W + kRegion - 1) / kRegion) * ((vt.v[v].H + kRegion - 1) / kRegion);
     for (int lat = 0; lat < (k.NL > 0 ? 2 : 1); ++lat) {
-        const int64_t waves = lat ? ((int64_t)vt.n * k.P * k.NL + 63) / 64 : vt.total_b8;
-        dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+        const int64_t groups = lat ? ((int64_t)vt.n * k.P * k.NL + kLatPerGroup - 1) / kLatPerGroup : regions;
+        dim3 grid((unsigned)groups), block(256);
 #define BGT_PB(D, E, LT) hipLaunchKernelGGL((k_param_bwd<D, E, LT>), grid, block, 0, s, k, vt, pr, cams, st, gr, st.patch)
 #define BGT_PB_CASE(D)                                  \
     case D:                                             \
