@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--tile", default="auto", help="8, 16, 32 or auto (the autotuner picks tile and batch)")
     ap.add_argument("--batch", type=int, default=64, help="Gaussians per LDS batch when --tile is given")
     ap.add_argument("--workload", default="sphere2k_16v_800")
+    ap.add_argument("--lattice", type=int, default=0,
+                    help="time the lattice variant with this many Gaussians per sub-triangle edge (for profiling)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the variant without blending coefficients")
@@ -282,6 +284,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     scene, cams, desc = S.workload(args.workload)
+    if args.lattice:
+        scene = S.lattice_scaled(scene, m=args.lattice, L=4)
+        desc += f", lattice variant m={args.lattice}"
     log(f"[bench] {desc}")
     params = scene_tensors(scene, dev)
     camt = torch.from_numpy(cams.cams).to(dev)
@@ -303,7 +308,7 @@ def main():
         log(f"[bench] autotuned tile {tile}, batch {batch} in {tune['seconds']} s: {tune['timings']}")
     else:
         tile, batch = int(args.tile), args.batch
-    r = Renderer(0, tile=tile, batch=batch)
+    r = Renderer(0, tile=tile, batch=batch, lattice=args.lattice)
     step = Step(r, scene.degree, params, camt, wh, target)
     if args.profile_run and args.eager:
         for _ in range(args.warmup + args.steps):
