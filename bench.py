@@ -369,8 +369,10 @@ def main():
         vs = Step(Renderer(0, tile=tile, batch=batch), full.degree, scene_tensors(full, dev), camt, wh, target)
         gv = capture(vs)
         ms_v = time_replays(gv, args.steps, args.warmup)
+        ast = stage_profile(vs)
         out["variants"]["attr_maps_r3_sh3"] = {
             "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+            "stage_ms": {k: round(v, 4) for k, v in ast.items()},
             "what": "resolution-3 rotation and scale maps and degree-3 SH colour (the paper's full model)"}
         log(f"[bench] variant with resolution-3 maps and SH degree 3: {ms_v:.3f} ms/step")
         del vs, gv

@@ -643,12 +643,12 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                     // view-dependent colour: sum_j Y_j(d) sh_j, d from the camera centre to S_q
                     double dv[3] = {S[0] - Cc[0], S[1] - Cc[1], S[2] - Cc[2]};
                     const double il = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-                    double Y[15];
-                    sh_basis<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il, Y, nullptr);
                     const float *shc = src + patch_sh_off(NCP, k.T);
-                    for (int j = 0; j < k.K; ++j)
+                    sh_basis_cb<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il,
+                                        [&](int j, double Yj, double, double, double) {
 #pragma unroll
-                        for (int dd = 0; dd < 3; ++dd) col[dd] += Y[j] * (double)shc[3 * j + dd];
+                        for (int dd = 0; dd < 3; ++dd) col[dd] += Yj * (double)shc[3 * j + dd];
+                    });
                 }
             }
         }
@@ -805,12 +805,12 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
                 for (int c = 0; c < 3; ++c)
                     dv[c] = S[c] + ((double)cm[c] * cm[9] + (double)cm[3 + c] * cm[10] + (double)cm[6 + c] * cm[11]);
                 const double il = 1.0 / sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-                double Y[15];
-                sh_basis<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il, Y, nullptr);
                 const float *shc = src + patch_sh_off(NCP, k.T);
-                for (int j = 0; j < k.K; ++j)
+                sh_basis_cb<double>(sh_degree_of(k.K), dv[0] * il, dv[1] * il, dv[2] * il,
+                                    [&](int j, double Yj, double, double, double) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) col[d] += Y[j] * (double)shc[3 * j + d];
+                    for (int d = 0; d < 3; ++d) col[d] += Yj * (double)shc[3 * j + d];
+                });
             }
         }
         Ewa e;

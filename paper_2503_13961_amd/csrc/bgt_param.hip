@@ -390,15 +390,17 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                         const float len = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), il = 1.f / len;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) dv[c] *= il;
-                        float dY[15][3];
-                        sh_basis<float>(sh_degree_of(k.K), dv[0], dv[1], dv[2], Yv, dY);
+                        // g = sum_j (dl/dc . sh_j) grad Y_j, taken as the basis is built
                         const float *shc = rec + patch_sh_off(NCP, k.T);
                         float gd[3] = {0.f, 0.f, 0.f};
-                        for (int j = 0; j < k.K; ++j) {
+                        sh_basis_cb<float>(sh_degree_of(k.K), dv[0], dv[1], dv[2],
+                                           [&](int j, float Yj, float gx, float gy, float gz) {
+                            Yv[j] = Yj;
                             const float w = dcol[0] * shc[3 * j] + dcol[1] * shc[3 * j + 1] + dcol[2] * shc[3 * j + 2];
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) gd[c] += w * dY[j][c];
-                        }
+                            gd[0] += w * gx;
+                            gd[1] += w * gy;
+                            gd[2] += w * gz;
+                        });
                         const float dot = dv[0] * gd[0] + dv[1] * gd[1] + dv[2] * gd[2];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) dS[c] += (gd[c] - dv[c] * dot) * il;

@@ -12,13 +12,9 @@ namespace bgt {
 // lattice triangle holding it; R = 1 is the single texel (weights 1, 0, 0).
 template <typename T>
 __device__ __forceinline__ void theta_weights(int R, T u, T v, int *ti, T *tw) {
-    if (R == 1) {
-        ti[0] = ti[1] = ti[2] = 0;
-        tw[0] = T(1);
-        tw[1] = tw[2] = T(0);
-        return;
-    }
-    const int m = R - 1;
+    // every output is a select, not a store under a branch, so that the
+    // caller's arrays stay in registers
+    const int m = R > 1 ? R - 1 : 1;
     const T U = m * u, V = m * v;
     int ia = (int)floor(U), ib = (int)floor(V);
     ia = ia < 0 ? 0 : (ia > m - 1 ? m - 1 : ia);
@@ -26,56 +22,51 @@ __device__ __forceinline__ void theta_weights(int R, T u, T v, int *ti, T *tw) {
     if (ia + ib > m - 1) ib = m - 1 - ia;  // on the hypotenuse
     const T fu = U - ia, fv = V - ib;
     auto node = [m](int a, int b) { return a * (m + 1) - a * (a - 1) / 2 + b; };
-    if (fu + fv <= T(1)) {
-        ti[0] = node(ia, ib);     tw[0] = T(1) - fu - fv;
-        ti[1] = node(ia + 1, ib); tw[1] = fu;
-        ti[2] = node(ia, ib + 1); tw[2] = fv;
-    } else {
-        ti[0] = node(ia + 1, ib);     tw[0] = T(1) - fv;
-        ti[1] = node(ia, ib + 1);     tw[1] = T(1) - fu;
-        ti[2] = node(ia + 1, ib + 1); tw[2] = fu + fv - T(1);
-    }
+    const bool one = R == 1, lower = fu + fv <= T(1);
+    ti[0] = one ? 0 : (lower ? node(ia, ib) : node(ia + 1, ib));
+    ti[1] = one ? 0 : (lower ? node(ia + 1, ib) : node(ia, ib + 1));
+    ti[2] = one ? 0 : (lower ? node(ia, ib + 1) : node(ia + 1, ib + 1));
+    tw[0] = one ? T(1) : (lower ? T(1) - fu - fv : T(1) - fv);
+    tw[1] = one ? T(0) : (lower ? fu : T(1) - fu);
+    tw[2] = one ? T(0) : (lower ? fv : fu + fv - T(1));
 }
 
 // Real SH of bands 1..D (Condon-Shortley phase, m = -l..l in a band) at the
-// unit vector (x, y, z); with dY, also their Cartesian gradients.  The
-// normalisations are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (times sqrt 2 for
-// m != 0) written out per function.
-template <typename T>
-__device__ __forceinline__ void sh_basis(int D, T x, T y, T z, T *Y, T (*dY)[3]) {
+// unit vector (x, y, z): f(k, Y_k, dY_k/dx, dY_k/dy, dY_k/dz) is called for
+// k = 0 .. (D+1)^2 - 2 in order.  The normalisations are
+// sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (times sqrt 2 for m != 0) written
+// out per function.  Every k is a constant at its call, so whatever f
+// indexes or accumulates stays in registers (a loop over a stored basis
+// with a run-time bound would put it in scratch memory).
+template <typename T, typename F>
+__device__ __forceinline__ void sh_basis_cb(int D, T x, T y, T z, F &&put) {
     const T pi = T(3.14159265358979323846);
-    int k = 0;
-    auto put = [&](T val, T gx, T gy, T gz) {
-        Y[k] = val;
-        if (dY) { dY[k][0] = gx; dY[k][1] = gy; dY[k][2] = gz; }
-        ++k;
-    };
     if (D >= 1) {
         const T c = sqrt(T(3) / (T(4) * pi));
-        put(-c * y, T(0), -c, T(0));
-        put(c * z, T(0), T(0), c);
-        put(-c * x, -c, T(0), T(0));
+        put(0, -c * y, T(0), -c, T(0));
+        put(1, c * z, T(0), T(0), c);
+        put(2, -c * x, -c, T(0), T(0));
     }
     if (D >= 2) {
         const T a = T(0.5) * sqrt(T(15) / pi), b = T(0.25) * sqrt(T(5) / pi), c = T(0.25) * sqrt(T(15) / pi);
-        put(a * x * y, a * y, a * x, T(0));
-        put(-a * y * z, T(0), -a * z, -a * y);
-        put(b * (T(2) * z * z - x * x - y * y), -T(2) * b * x, -T(2) * b * y, T(4) * b * z);
-        put(-a * x * z, -a * z, T(0), -a * x);
-        put(c * (x * x - y * y), T(2) * c * x, -T(2) * c * y, T(0));
+        put(3, a * x * y, a * y, a * x, T(0));
+        put(4, -a * y * z, T(0), -a * z, -a * y);
+        put(5, b * (T(2) * z * z - x * x - y * y), -T(2) * b * x, -T(2) * b * y, T(4) * b * z);
+        put(6, -a * x * z, -a * z, T(0), -a * x);
+        put(7, c * (x * x - y * y), T(2) * c * x, -T(2) * c * y, T(0));
     }
     if (D >= 3) {
         const T a = T(0.25) * sqrt(T(35) / (T(2) * pi)), b = T(0.5) * sqrt(T(105) / pi);
         const T c = T(0.25) * sqrt(T(21) / (T(2) * pi)), e = T(0.25) * sqrt(T(7) / pi), g = T(0.25) * sqrt(T(105) / pi);
         const T xx = x * x, yy = y * y, zz = z * z;
-        put(-a * y * (T(3) * xx - yy), -T(6) * a * x * y, -a * (T(3) * xx - T(3) * yy), T(0));
-        put(b * x * y * z, b * y * z, b * x * z, b * x * y);
-        put(-c * y * (T(4) * zz - xx - yy), T(2) * c * x * y, -c * (T(4) * zz - xx - T(3) * yy), -T(8) * c * y * z);
-        put(e * z * (T(2) * zz - T(3) * xx - T(3) * yy), -T(6) * e * x * z, -T(6) * e * y * z,
+        put(8, -a * y * (T(3) * xx - yy), -T(6) * a * x * y, -a * (T(3) * xx - T(3) * yy), T(0));
+        put(9, b * x * y * z, b * y * z, b * x * z, b * x * y);
+        put(10, -c * y * (T(4) * zz - xx - yy), T(2) * c * x * y, -c * (T(4) * zz - xx - T(3) * yy), -T(8) * c * y * z);
+        put(11, e * z * (T(2) * zz - T(3) * xx - T(3) * yy), -T(6) * e * x * z, -T(6) * e * y * z,
             e * (T(6) * zz - T(3) * xx - T(3) * yy));
-        put(-c * x * (T(4) * zz - xx - yy), -c * (T(4) * zz - T(3) * xx - yy), T(2) * c * x * y, -T(8) * c * x * z);
-        put(g * z * (xx - yy), T(2) * g * x * z, -T(2) * g * y * z, g * (xx - yy));
-        put(-a * x * (xx - T(3) * yy), -a * (T(3) * xx - T(3) * yy), T(6) * a * x * y, T(0));
+        put(12, -c * x * (T(4) * zz - xx - yy), -c * (T(4) * zz - T(3) * xx - yy), T(2) * c * x * y, -T(8) * c * x * z);
+        put(13, g * z * (xx - yy), T(2) * g * x * z, -T(2) * g * y * z, g * (xx - yy));
+        put(14, -a * x * (xx - T(3) * yy), -a * (T(3) * xx - T(3) * yy), T(6) * a * x * y, T(0));
     }
 }
 
