@@ -71,7 +71,7 @@ struct BoundaryLds {
     int brun[CAP];
     int run_prim[CAP], run_start[CAP + 1];
     int wsum[33];
-    int n_runs, nbl;
+    int n_runs, nbl, max_rows;
     union {
         int bp[CAP];                // each point's primitive, while the runs are found
         unsigned map[RM][TS * TS];  // then gamma* bits per (run, pixel in thread order)
@@ -241,32 +241,65 @@ __device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInf
     return best;
 }
 
+// Pixel rows [y0, y1] of the tile that a point's disc can reach, one row
+// of margin each side (the per-pixel test decides); the whole tile for a
+// radius that is not finite or exceeds two tiles.
+template <int TS>
+__device__ __forceinline__ void disc_rows(float yb, float sg, int &y0, int &y1) {
+    if (!(sg < (float)(2 * TS))) {
+        y0 = 0;
+        y1 = TS - 1;
+        return;
+    }
+    y0 = (int)fmaxf(floorf(yb - sg) - 1.0f, 0.0f);
+    y1 = (int)fminf(ceilf(yb + sg) + 1.0f, (float)(TS - 1));
+}
+
 // Scatter-min of every staged point over the pixels of its disc, into the
 // maps of the first B.NMAP runs (gamma bits compare as unsigned integers).
+// The (point, row) items of all mapped points are spread over the threads,
+// and a row visits the pixels its chord of the disc can reach: the points'
+// discs differ in size and a thread per point waited for the largest.
 template <int TS, typename BL>
 __device__ __forceinline__ void build_gamma_maps(BL &B) {
     using G = TileGeom<TS>;
     const int nmap = B.n_runs < B.NMAP ? B.n_runs : B.NMAP;
     for (int i = threadIdx.x; i < nmap * G::NT; i += blockDim.x) B.map[i / G::NT][i % G::NT] = 0x3F800000u;
+    if (threadIdx.x == 0) B.max_rows = 0;
     __syncthreads();
     for (int e = threadIdx.x; e < B.nbl; e += blockDim.x) {
+        if (B.brun[e] >= B.NMAP) continue;
+        int y0, y1;
+        disc_rows<TS>((float)hi16(B.bxy[e]) + B.bdy[e], B.bs[e], y0, y1);
+        if (y1 >= y0) atomicMax(&B.max_rows, y1 - y0 + 1);
+    }
+    __syncthreads();
+    const int R = B.max_rows;
+    for (int it = threadIdx.x; it < B.nbl * R; it += blockDim.x) {
+        const int e = it / R, row = it - e * R;
         const int r = B.brun[e];
         if (r >= B.NMAP) continue;
         const int bix = lo16(B.bxy[e]), biy = hi16(B.bxy[e]);
         const float bdx = B.bdx[e], bdy = B.bdy[e], sg = B.bs[e];
-        const float rf = sg + fabsf(bdx) + fabsf(bdy);
-        const int rad = rf < (float)(2 * TS) ? (int)ceilf(rf) + 1 : 2 * TS;  // NaN/inf -> whole tile
-        const int x0 = max(bix - rad, 0), x1 = min(bix + rad, TS - 1);
-        const int y0 = max(biy - rad, 0), y1 = min(biy + rad, TS - 1);
-        for (int y = y0; y <= y1; ++y)
-            for (int x = x0; x <= x1; ++x) {
-                const float dx = (float)(x - bix) - bdx, dy = (float)(y - biy) - bdy;
-                const float d = bdist(dx, dy);
-                if (d < sg) {
-                    const float g = gamma_fn(d, sg);
-                    if (g < 1.0f) atomicMin(&B.map[r][G::tid_of(x, y)], __float_as_uint(g));
-                }
+        int y0, y1;
+        disc_rows<TS>((float)biy + bdy, sg, y0, y1);
+        const int y = y0 + row;
+        if (y > y1) continue;
+        const float dy = (float)(y - biy) - bdy;
+        int x0 = 0, x1 = TS - 1;
+        if (sg < (float)(2 * TS)) {
+            const float xb = (float)bix + bdx, h = sqrtf(fmaxf(sg * sg - dy * dy, 0.0f));
+            x0 = (int)fmaxf(floorf(xb - h) - 1.0f, 0.0f);
+            x1 = (int)fminf(ceilf(xb + h) + 1.0f, (float)(TS - 1));
+        }
+        for (int x = x0; x <= x1; ++x) {
+            const float dx = (float)(x - bix) - bdx;
+            const float d = bdist(dx, dy);
+            if (d < sg) {
+                const float g = gamma_fn(d, sg);
+                if (g < 1.0f) atomicMin(&B.map[r][G::tid_of(x, y)], __float_as_uint(g));
             }
+        }
     }
     __syncthreads();
 }
