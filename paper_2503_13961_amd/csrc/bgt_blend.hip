@@ -446,9 +446,20 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
-    stage_boundary(B, st, bs0, bc, ox, oy, vi);
     const bool slow_b = bc > BoundaryCap<TS>::value;
     if (slow_b && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_BIGBLIST], 1ull);
+    if (st.g_count[t] == 0) {
+        // no Gaussian reaches the tile (most of the background): T = 1
+        if (inside) {
+            image[3 * (int64_t)pix + 0] = k.bg[0];
+            image[3 * (int64_t)pix + 1] = k.bg[1];
+            image[3 * (int64_t)pix + 2] = k.bg[2];
+            st.T_final[pix] = 1.0f;
+            st.last[pix] = 0;
+        }
+        return;
+    }
+    stage_boundary(B, st, bs0, bc, ox, oy, vi);
     const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     build_gamma_maps<TS>(B);
 
@@ -562,6 +573,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     BatchLds<TS, K> &S = U.loop.S;
     float *acc = U.loop.acc;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int gc = st.g_count[t];
+    if (gc == 0) return;  // no Gaussian reaches the tile: nothing to differentiate
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
     const int tl = t - vi.tile_off, tx = tl % vi.tiles_x, ty = tl / vi.tiles_x;
@@ -570,7 +583,6 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int px = tx * TS + lx, py = ty * TS + ly;
     const bool inside = px < vi.W && py < vi.H;
     const int pix = vi.px_off + py * vi.W + px;
-    const int gc = st.g_count[t];
     int h = -1, mylast = 0;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f, im0 = 0.f, im1 = 0.f, im2 = 0.f;
     if (inside) {
