@@ -259,7 +259,7 @@ __device__ __forceinline__ int rank_in(const unsigned long long *a, int n, unsig
 }
 
 __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, int lat_per_view) {
-    __shared__ unsigned long long keys[2][kSortLds];
+    __shared__ unsigned long long keys[kSortLds];
     const int t = blockIdx.x, which = blockIdx.y;
     const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
     if (cnt == 0) return;
@@ -287,30 +287,40 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
     // ~0, above every key), then merged pairwise by rank: a key's place in
     // the merged run is its place in its own run plus the number of keys of
     // the other run before it (keys of the first run go before equal keys of
-    // the second; only the padding repeats).
+    // the second; only the padding repeats).  In place: every thread ranks its
+    // keys (at most kSortLds / 256) first and all write after a barrier, so
+    // the block needs one buffer (16 KB) and twice as many blocks fit a CU.
+    constexpr int PER = kSortLds / 256;
     const int n64 = (cnt + 63) & ~63, nruns = n64 >> 6;
     for (int run = wave; run < nruns; run += blockDim.x >> 6) {
         const int i = run * 64 + lane;
-        keys[0][i] = wave_sort64(i < cnt ? src[start + i] : ~0ull, lane);
+        keys[i] = wave_sort64(i < cnt ? src[start + i] : ~0ull, lane);
     }
     __syncthreads();
-    int cur = 0;
     for (int L = 64; L < n64; L <<= 1) {
-        const unsigned long long *a = keys[cur];
-        unsigned long long *b = keys[cur ^ 1];
-        for (int i = threadIdx.x; i < n64; i += blockDim.x) {
-            const int p0 = i & ~(2 * L - 1);
-            const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
-            const unsigned long long x = a[i];
-            const int pos = i < mid ? (i - p0) + rank_in<false>(a + mid, end - mid, x)
-                                    : (i - mid) + rank_in<true>(a + p0, mid - p0, x);
-            b[p0 + pos] = x;
+        unsigned long long x[PER];
+        int pos[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + q * 256;
+            pos[q] = -1;
+            x[q] = 0ull;
+            if (i < n64) {
+                const int p0 = i & ~(2 * L - 1);
+                const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
+                x[q] = keys[i];
+                pos[q] = i < mid ? i + rank_in<false>(keys + mid, end - mid, x[q])
+                                 : p0 + (i - mid) + rank_in<true>(keys + p0, mid - p0, x[q]);
+            }
         }
-        cur ^= 1;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (pos[q] >= 0) keys[pos[q]] = x[q];
         __syncthreads();
     }
     for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[cur][i] & 0xFFFFFFull), lat_per_view);
+        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
 }
 
 // Segments longer than the LDS buffer: same network on global memory, one
