@@ -203,18 +203,50 @@ def cpu_baseline(scene, cams, nviews):
             "seconds": round(dt, 3), "cpu": platform.processor() or platform.machine()}
 
 
-def profiled_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of
-    this workload, or None when there is none or the library sources changed
-    since it was taken."""
+def profiled(workload, kernel):
+    """(HBM bytes, SQ counters) per launch of `kernel` from the committed
+    rocprofv3 summary of this workload; (None, {}) when there is none or the
+    library sources changed since it was taken."""
     from paper_2503_13961_amd import profiling
     m = profiling.read_counters(os.path.join(ROOT, "profiles", f"kernels_{workload}.md"))
     if not m or m.get("source_sha256") != profiling.source_digest():
-        return None
-    b = m.get("bytes", {}).get(kernel)
-    if not b or b.get("fetch") is None or b.get("write") is None:
-        return None
-    return b["fetch"] + b["write"]
+        return None, {}
+    b = m.get("bytes", {}).get(kernel) or {}
+    traffic = None if b.get("fetch") is None or b.get("write") is None else b["fetch"] + b["write"]
+    return traffic, m.get("sq", {}).get(kernel, {})
+
+
+def copy_bandwidth(dev, mib=1024, reps=5):
+    """Device-to-device copy of `mib` MiB, read + written bytes per second (GB/s)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def path_bytes(counters, npx, ntiles):
+    """Algorithmic HBM bytes of one whole fwd+bwd step, each buffer the method
+    must produce or consume counted once per essential read or write: per
+    pixel the index map and (u, v) written and read, image, transmittance
+    and stop index written, the backward's reads; per foreground pixel its
+    Gaussian written and read back by the parameter pass; per boundary pixel
+    its list entries, record and gradient; per Gaussian-tile pair the key
+    emitted, sorted, the value and the record read in the forward and again
+    in the backward with the gradient read-modify-write; per boundary pair
+    the same with its 16-byte record; per tile its list ranges."""
+    gp, bp, fg, nb = counters[1], counters[2], counters[3], counters[4]
+    return (npx * (12 + 12 + 20 + 24) + fg * (44 + 48) + nb * (4 + 4 + 16 + 24)
+            + gp * (12 + 24 + 4 + 44 + 4 + 44 + 72) + bp * (12 + 24 + 4 + 16 + 4 + 16 + 24) + ntiles * 24)
 
 
 def parity_check(scene, cams, images, samples=6000, seed=0, views=None, **mode):
@@ -454,12 +486,22 @@ def main():
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
     achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
     kname = f"bgt::k_{dom}<{tile}, {batch}>"
-    traffic = profiled_traffic(args.workload, kname)
+    traffic, sq = profiled(args.workload, kname)
+    issue = 256 * 2.4e9 * stages[dom] * 1e-3   # wave-instruction slots of the launch (one per CU per cycle)
     out["roofline"] = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": None if traffic is None else round(traffic / 1e9, 4),
                        "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                       "algorithmic_bytes": int(alg[dom]), "kernel_ms": round(stages[dom], 4)}
+                       "algorithmic_bytes": int(alg[dom]), "kernel_ms": round(stages[dom], 4),
+                       "valu_issue_frac": round(sq["SQ_INSTS_VALU"] / issue, 3) if "SQ_INSTS_VALU" in sq else None,
+                       "lds_issue_frac": round(sq["SQ_INSTS_LDS"] / issue, 3) if "SQ_INSTS_LDS" in sq else None}
+    # the whole step against the HBM roofline, and a measured copy bandwidth
+    pb = path_bytes(counters, npx, ntiles)
+    cp = copy_bandwidth(dev)
+    out["path_roofline"] = {"algorithmic_bytes": int(pb), "achieved": round(pb / (ms * 1e-3) / 1e9, 1),
+                            "unit": "GB/s", "frac": round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "copy_gbs_measured": round(cp, 1),
+                            "frac_of_copy": round(pb / (ms * 1e-3) / 1e9 / cp, 4)}
     out["counters"] = {"gauss_pairs": counters[1], "boundary_pairs": counters[2], "foreground_px": counters[3],
                        "boundary_px": counters[4]}
     if not args.no_parity:

@@ -138,7 +138,9 @@ def markdown(res, focus=("k_blend_bwd", "k_blend_fwd", "k_gen", "k_param_bwd")):
     mach = {"source_sha256": res["source_sha256"], "workload": res["workload"],
             "bytes": {k: {"fetch": v.get("fetch_bytes"), "write": v.get("write_bytes"), "avg_us": v.get("avg_us")}
                       for k, v in res["kernels"].items()
-                      if k.startswith("bgt::") and ("fetch_bytes" in v or "write_bytes" in v)}}
+                      if k.startswith("bgt::") and ("fetch_bytes" in v or "write_bytes" in v)},
+            "sq": {k: {c: x for c, x in v.items() if c.startswith("SQ_")}
+                   for k, v in res["kernels"].items() if k.startswith("bgt::") and any(c.startswith("SQ_") for c in v)}}
     L += ["", "<!-- counters " + json.dumps(mach, sort_keys=True) + " -->"]
     return "\n".join(L) + "\n"
 
