@@ -27,6 +27,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(N.EXPORTS) == names
 
 
+def test_binding_constants_match_the_header():
+    """The binding's copies of the header's sizes (a state-layout array one
+    entry short would be overrun by bgt_state_layout)."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "bgt.h")).read()
+    for name in ("BGT_STATE_FIELDS", "BGT_MAX_VIEWS", "BGT_MAX_ADAM_GROUPS", "BGT_FLAG_NO_BOUNDARY", "BGT_NUM_STAGES"):
+        m = re.search(rf"#define {name} (\d+)", hdr)
+        assert m and int(m.group(1)) == getattr(N, name), name
+
+
 def test_default_config_is_valid_and_checks_reject_bad_values():
     c = N.bgt_default_config()
     assert N.bgt_validate_config(c) == N.BGT_OK
