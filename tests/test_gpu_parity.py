@@ -212,6 +212,34 @@ def test_tile_size_and_determinism():
         np.testing.assert_array_equal(G.run_gpu(sc, cams, tile=tile)["images"], base["images"])
 
 
+def test_gradients_repeat_across_runs():
+    """Forward and backward of the same inputs, four times on one state: the
+    gradients agree to 1e-5 of each tensor's largest entry (the float
+    atomics of the sums may add in any order, which moves the last bits, but
+    no contribution may be lost or counted twice)."""
+    import torch
+    from paper_2503_13961_amd.render import Renderer, scene_tensors
+    G.log("[repeat] sphere2k_16v_mixed: gradients of four runs")
+    sc, cams, _ = S.workload("sphere2k_16v_mixed")
+    dev = torch.device("cuda", 0)
+    r = Renderer(0)
+    params = scene_tensors(sc, dev)
+    camt = torch.from_numpy(cams.cams).to(dev)
+    wh = np.ascontiguousarray(cams.wh, np.int32)
+    gi = torch.from_numpy((np.sign(np.random.default_rng(0).random((cams.num_pixels, 3)) - 0.5)
+                           / (3 * cams.num_pixels)).astype(np.float32)).to(dev)
+    runs, state, images = [], None, None
+    for _ in range(4):
+        images, state = r.forward(sc.degree, params, camt, wh, state=state, images=images)
+        g = r.backward(sc.degree, params, camt, wh, images, gi, state)
+        torch.cuda.synchronize()
+        runs.append({k: v.cpu().numpy().copy() for k, v in g.items()})
+    for run in runs[1:]:
+        for k, ref in runs[0].items():
+            e = np.abs(run[k] - ref).max() / max(np.abs(ref).max(), 1e-30)
+            assert e <= 1e-5, (k, e)
+
+
 def test_everything_behind_the_camera():
     """All geometry behind z_near: background image and zero gradients."""
     G.log("[edge] behind camera")
