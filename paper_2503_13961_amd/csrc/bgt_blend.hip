@@ -469,6 +469,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     int last = gc;
     const float amax = k.alpha_max, tmin = k.t_min;
     const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
+    // can an entry's run lack a gamma* map (more runs than maps, or a list
+    // beyond the stage)?  Only then do the loops below look for such entries
+    const bool rare = slow_b || B.n_runs > RM;
     // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
     const float e_min = kE * k.kappa2;
     SlotPrefetch pf;
@@ -483,9 +486,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
             for (int c0 = 0; c0 < nk; c0 += 64) {
                 unsigned long long mine = row_mask<K>(S.xr, S.yr, c0, nk, lane, wx0, wy0);
                 if (row_all(done, lane)) mine = 0;  // this row has stopped
-                for (int hb = 0; hb < 64 && c0 + hb < nk; hb += 32) {
+#pragma unroll
+                for (int hb = 0; hb < 64; hb += 32) {
                     unsigned mm = (unsigned)(mine >> hb);
-                    while (__any(mm != 0u)) {
+                    if (__any(mm != 0u)) do {
                         // each row composites its own next entry: branch-free per
                         // lane, a lane that does not composite it takes alpha = 0,
                         // which leaves T and C bit-identical
@@ -505,15 +509,15 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         const bool mapped = r >= 0 && r < RM;
                         float gam = __uint_as_float(B.map[min(max(r, 0), RM - 1)][tid]);
                         gam = mapped ? gam : 1.0f;
-                        if (__any(live && r != -1 && !mapped)) {  // rare: runs without a map, big lists
+                        if (rare && __any(live && r != -1 && !mapped)) {  // runs without a map, big lists
                             int arg;
                             if (live && r >= RM) gam = gamma_lds(B, r, lx, ly, &arg);
                             else if (live && r == -2) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
                         }
+                        // w = 0 (gamma* = 1 for another patch's Gaussian) gives
+                        // a = 0 with no test: T and C stay as they are
                         const float w = own ? gam : 1.0f - gam;
-                        live = live && w > 0.0f;
-                        float a = ex.w * w * support_exp2(e);
-                        a = a > amax ? amax : a;
+                        float a = fminf(ex.w * w * support_exp2(e), amax);
                         a = live ? a : 0.0f;
                         const float ta = T * a;
                         C0 += ta * c.x;
@@ -521,7 +525,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         C2 += ta * c.z;
                         T = T * (1.0f - a);
                         if (live && T < tmin) { done = true; last = base + kk + 1; }
-                    }
+                    } while (__any(mm != 0u));
                 }
             }
         }
