@@ -87,7 +87,7 @@ template <int TS, int K>
 struct BatchLds {
     float2 m[TS * TS / 64][K];  // per-wave mean offsets
     float4 e[K];                // conic in exponent form kE (a, 2b, c), opacity
-    float4 c[K];                // colour, unused
+    float4 c[K];                // colour; w: exponent below which no pixel of a 4x4 sub-block is in the support
     int2 pr[K];                 // primitive id, run index
     int xr[K], yr[K];
 };
@@ -322,9 +322,23 @@ struct SlotPrefetch {
     }
 };
 
-template <int TS, int K>
+// For pixels q within rho of a point p, the triangle inequality in the conic's
+// norm gives |q - mu|_Q >= |p - mu|_Q - sqrt(lambda_max(Q)) rho.  So no pixel
+// of a 4x4 sub-block (its centres within rho = 1.5 sqrt 2 of the block's
+// centre) has d^T Q d <= kappa^2 when the centre's exponent is below
+// kE (kappa + sqrt(lambda_max) rho)^2; the bound is widened by 1e-3 (relative
+// and absolute) so that FP32 rounding of either side never drops a live pixel.
+__device__ __forceinline__ float sub_block_bound(float qa, float qb, float qc, float kappa) {
+    const float h = 0.5f * (qa - qc);
+    const float lmax = 0.5f * (qa + qc) + sqrtf(h * h + qb * qb);
+    const float rad = (kappa + sqrtf(fmaxf(lmax, 0.0f)) * 2.1214f) * 1.001f + 1e-3f;
+    return kE * rad * rad;
+}
+
+// BOUND: also store the sub-block bound (the forward's row masks use it)
+template <int TS, int K, bool BOUND>
 __device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, int kk, int ox, int oy,
-                                           const int *run_prim, int n_runs, bool slow_b) {
+                                           const int *run_prim, int n_runs, bool slow_b, float kappa) {
     using G = TileGeom<TS>;
     // tile-relative pixel the Gaussian's mean is stored against
     const int a = __float_as_int(P.r2.w);
@@ -333,7 +347,7 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetc
     for (int w = 0; w < G::NT / 64; ++w)
         S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
     S.e[kk] = make_float4(kE * P.r0.z, 2.0f * kE * P.r0.w, kE * P.r1.x, P.r2.x);
-    S.c[kk] = make_float4(P.r1.y, P.r1.z, P.r1.w, 0.f);
+    S.c[kk] = make_float4(P.r1.y, P.r1.z, P.r1.w, BOUND ? sub_block_bound(P.r0.z, P.r0.w, P.r1.x, kappa) : 0.f);
     const int g = __float_as_int(P.r2.y);
     // a tile whose boundary list overflowed the LDS stage has its last staged
     // run cut short (n_runs counts complete runs only): a primitive not among
@@ -350,19 +364,30 @@ __device__ __forceinline__ bool touches4(int xr, int yr, int x0, int y0) {
     return !(hi16(xr) < x0 || lo16(xr) > x0 + 3 || hi16(yr) < y0 || lo16(yr) > y0 + 3);
 }
 
-// Which of the batch entries [c0, c0 + 64) (below n) touch this lane's 4x4
-// sub-block: one ballot per sub-block of the wave's 8x8 block at (wx0, wy0),
-// each lane keeping its own row's.
-template <int K>
-__device__ __forceinline__ unsigned long long row_mask(const int *xr, const int *yr, int c0, int n, int lane, int wx0,
-                                                       int wy0) {
+// Which of the batch entries [c0, c0 + 64) (below n) can reach this lane's
+// 4x4 sub-block: one ballot per sub-block of the wave's 8x8 block at
+// (wx0, wy0), each lane keeping its own row's.  An entry counts when its
+// support box touches the sub-block and the sub-block's centre is within the
+// conic bound of sub_block_bound (an entry skipped here has no live pixel
+// there, so the result does not change).
+template <int TS, int K>
+__device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
+                                                       int wx0, int wy0) {
     const int j = c0 + lane, jj = j < K ? j : K - 1;
     const bool in = j < n;
-    const int a = xr[jj], b = yr[jj];
-    const unsigned long long m0 = __ballot(in && touches4(a, b, wx0, wy0));
-    const unsigned long long m1 = __ballot(in && touches4(a, b, wx0 + 4, wy0));
-    const unsigned long long m2 = __ballot(in && touches4(a, b, wx0, wy0 + 4));
-    const unsigned long long m3 = __ballot(in && touches4(a, b, wx0 + 4, wy0 + 4));
+    const int a = S.xr[jj], b = S.yr[jj];
+    const float2 m = S.m[wave][jj];
+    const float4 ex = S.e[jj];
+    const float thr = S.c[jj].w;
+    // exponents at the sub-block centres (1.5 | 5.5, 1.5 | 5.5) of the wave's block
+    const float dx0 = 1.5f - m.x, dx1 = 5.5f - m.x, dy0 = 1.5f - m.y, dy1 = 5.5f - m.y;
+    const float by0 = ex.y * dy0, by1 = ex.y * dy1, cy0 = ex.z * dy0 * dy0, cy1 = ex.z * dy1 * dy1;
+    const bool n0 = fmaf(dx0, fmaf(ex.x, dx0, by0), cy0) < thr, n1 = fmaf(dx1, fmaf(ex.x, dx1, by0), cy0) < thr;
+    const bool n2 = fmaf(dx0, fmaf(ex.x, dx0, by1), cy1) < thr, n3 = fmaf(dx1, fmaf(ex.x, dx1, by1), cy1) < thr;
+    const unsigned long long m0 = __ballot(in && !n0 && touches4(a, b, wx0, wy0));
+    const unsigned long long m1 = __ballot(in && !n1 && touches4(a, b, wx0 + 4, wy0));
+    const unsigned long long m2 = __ballot(in && !n2 && touches4(a, b, wx0, wy0 + 4));
+    const unsigned long long m3 = __ballot(in && !n3 && touches4(a, b, wx0 + 4, wy0 + 4));
     const int q = lane >> 4;
     return q == 0 ? m0 : (q == 1 ? m1 : (q == 2 ? m2 : m3));
 }
@@ -474,17 +499,18 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     const bool rare = slow_b || B.n_runs > RM;
     // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
     const float e_min = kE * k.kappa2;
+    const float kappa = sqrtf(k.kappa2);
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, gc, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K, true>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, kappa);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
         pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
         const int nk = min(K, gc - base);
         if (!__all(done)) {
             for (int c0 = 0; c0 < nk; c0 += 64) {
-                unsigned long long mine = row_mask<K>(S.xr, S.yr, c0, nk, lane, wx0, wy0);
+                unsigned long long mine = row_mask<TS, K>(S, wave, c0, nk, lane, wx0, wy0);
                 if (row_all(done, lane)) mine = 0;  // this row has stopped
 #pragma unroll
                 for (int hb = 0; hb < 64; hb += 32) {
@@ -530,7 +556,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();  // everyone is done with this batch
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K, true>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, kappa);
     }
     if (inside) {
         image[3 * (int64_t)pix + 0] = C0 + T * k.bg[0];
@@ -626,7 +652,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     SlotPrefetch pf;
     pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
     pf.issue(st, gs0, nlast, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
         const int cur_gp = pf.gp;
@@ -736,7 +762,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 }
             }
         }
-        if (pf.gp >= 0) stage_slot<TS, K>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (first, i.e. lowest raster

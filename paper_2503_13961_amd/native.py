@@ -134,7 +134,10 @@ def lib():
 def bgt_default_config(**overrides) -> bgt_config:
     c = bgt_config()
     lib().bgt_default_config(C.byref(c))
+    fields = {f[0] for f in bgt_config._fields_}
     for k, v in overrides.items():
+        if k not in fields:  # a ctypes structure would take it as a plain attribute
+            raise TypeError(f"bgt_config has no field {k!r} (fields: {sorted(fields)})")
         if k == "bg":
             c.bg = (C.c_float * 3)(*v)
         else:

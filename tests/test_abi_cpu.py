@@ -52,6 +52,9 @@ def test_default_config_is_valid_and_checks_reject_bad_values():
     # flags: only the no-boundary bit is defined
     assert N.bgt_validate_config(N.bgt_default_config(flags=N.BGT_FLAG_NO_BOUNDARY)) == N.BGT_OK
     assert N.bgt_validate_config(N.bgt_default_config(flags=2)) == N.BGT_E_INVALID
+    # a misspelt or unknown option is an error, not a silently ignored attribute
+    with pytest.raises(TypeError):
+        N.bgt_default_config(no_boundary=True)
 
 
 def test_prims_and_views_validation():
