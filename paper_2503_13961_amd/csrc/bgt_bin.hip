@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
     int v, x, y;
     const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
     const ViewInfo vi = vt.v[v];
-    const int TS = k.tile;
+    const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
     int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;
     unsigned long long gkey = 0ull, bkey = 0ull;
     if (act) {
@@ -133,13 +133,13 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
             const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
             // (in the lattice variant a pixel record is a boundary point only)
             if (k.NL == 0 && lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
-                gt0 = lo16(gx) / TS; gt1 = hi16(gx) / TS; gu0 = lo16(gy) / TS; gu1 = hi16(gy) / TS;
+                gt0 = lo16(gx) >> TSH; gt1 = hi16(gx) >> TSH; gu0 = lo16(gy) >> TSH; gu1 = hi16(gy) >> TSH;
             }
             gkey = (st.gkey[pix] << 24) | (unsigned long long)lp;
             if (fl & PF_BOUNDARY) {
                 const int bx = __float_as_int(r3.z), by = __float_as_int(r3.w);
                 if (lo16(bx) <= hi16(bx) && lo16(by) <= hi16(by)) {
-                    bt0 = lo16(bx) / TS; bt1 = hi16(bx) / TS; bu0 = lo16(by) / TS; bu1 = hi16(by) / TS;
+                    bt0 = lo16(bx) >> TSH; bt1 = hi16(bx) >> TSH; bu0 = lo16(by) >> TSH; bu1 = hi16(by) >> TSH;
                 }
                 const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
                 bkey = ((unsigned long long)prim << 24) | (unsigned long long)lp;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_scatter_lattice(Consts k, ViewTable vt,
     const bool act = i < (int64_t)vt.n * per_view;
     const int v = act ? (int)(i / per_view) : 0;
     const ViewInfo vi = vt.v[v];
-    const int TS = k.tile;
+    const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
     int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0;
     unsigned long long gkey = 0ull;
     if (act) {
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_scatter_lattice(Consts k, ViewTable vt,
         const float4 r3 = st.rec[rid * 4 + 3];
         const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
         if (lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
-            gt0 = lo16(gx) / TS; gt1 = hi16(gx) / TS; gu0 = lo16(gy) / TS; gu1 = hi16(gy) / TS;
+            gt0 = lo16(gx) >> TSH; gt1 = hi16(gx) >> TSH; gu0 = lo16(gy) >> TSH; gu1 = hi16(gy) >> TSH;
         }
         const int lr = vi.W * vi.H + (int)(i - v * per_view);
         gkey = (st.gkey[rid] << 24) | (unsigned long long)lr;

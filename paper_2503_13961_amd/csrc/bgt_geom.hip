@@ -699,12 +699,12 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                                      __int_as_float(pack16(bi0, bi1)), __int_as_float(pack16(bj0, bj1)));
                 st.gkey[pix] = ((unsigned long long)__double_as_longlong(tz)) >> 24;
                 // tiles reached by the Gaussian's support and by the boundary disc
-                const int TS = k.tile;
+                const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
                 // (in the lattice variant the pixel records are boundary points only)
                 if (gi0 <= gi1 && gj0 <= gj1 && k.NL == 0) {
-                    gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS;
+                    gt0 = gi0 >> TSH; gt1 = gi1 >> TSH; gu0 = gj0 >> TSH; gu1 = gj1 >> TSH;
                 }
-                if (bi0 <= bi1 && bj0 <= bj1) { bt0 = bi0 / TS; bt1 = bi1 / TS; bu0 = bj0 / TS; bu1 = bj1 / TS; }
+                if (bi0 <= bi1 && bj0 <= bj1) { bt0 = bi0 >> TSH; bt1 = bi1 >> TSH; bu0 = bj0 >> TSH; bu1 = bj1 >> TSH; }
             }
             fg = true;
             isb = (flags & PF_BOUNDARY) != 0;
@@ -829,8 +829,8 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
             rec[3] = make_float4(__int_as_float(pack16(gi0, gi1)), __int_as_float(pack16(gj0, gj1)),
                                  __int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)));
             st.gkey[vt.total_px + i] = ((unsigned long long)__double_as_longlong(e.tz)) >> 24;
-            const int TS = k.tile;
-            if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 / TS; gt1 = gi1 / TS; gu0 = gj0 / TS; gu1 = gj1 / TS; }
+            const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
+            if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 >> TSH; gt1 = gi1 >> TSH; gu0 = gj0 >> TSH; gu1 = gj1 >> TSH; }
         } else {
             // behind z_near: empty ranges, never listed
             rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
