@@ -18,6 +18,10 @@
 
 namespace bgt {
 
+// the hardware reciprocal (within 1 ulp): the gradient terms below need far
+// less than correctly rounded division, which takes ten instructions
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int DEG>
 __device__ __forceinline__ void bern_f(float u, float v, float w, float *B) {
     constexpr float fact[6] = {1.f, 1.f, 2.f, 6.f, 24.f, 120.f};
@@ -240,7 +244,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 float t[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) t[r] = W[3 * r] * S[0] + W[3 * r + 1] * S[1] + W[3 * r + 2] * S[2] + cm[9 + r];
-                const float iz = 1.f / t[2];
+                const float iz = rcp(t[2]);
                 const float J00 = fx * iz, J02 = -fx * t[0] * iz * iz, J11 = fy * iz, J12 = -fy * t[1] * iz * iz;
                 float Tm[6];
 #pragma unroll
@@ -274,8 +278,8 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 }
 #pragma unroll
                 for (int d = 0; d < 4; ++d) qn += q[d] * q[d];
-                qn = sqrtf(qn);
-                const float qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
+                const float iqn = __builtin_amdgcn_rsqf(qn);  // 1 / |q|
+                const float qw = q[0] * iqn, qx = q[1] * iqn, qy = q[2] * iqn, qz = q[3] * iqn;
                 const float R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
                                     2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
                                     2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
@@ -296,7 +300,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 const float SB = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
                 const float SC = V[3] * V[3] + V[4] * V[4] + V[5] * V[5] + k.dilation;
                 // conic = inverse: a = C/det, b = -B/det, c = A/det
-                const float det = SA * SC - SB * SB, idet = 1.f / det, id2 = idet * idet;
+                const float det = SA * SC - SB * SB, idet = rcp(det), id2 = idet * idet;
                 // dl/dmu = Q (m0, m1) plus the boundary point's own position gradient
                 const float dmux = (SC * m0 - SB * m1) * idet + dbx;
                 const float dmuy = (SA * m1 - SB * m0) * idet + dby;
@@ -334,8 +338,8 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                     float gy = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.f * qy * dR[8]);
                     float gz = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
                     const float dot = qw * gw + qx * gx + qy * gy + qz * gz;
-                    dq[0] = (gw - qw * dot) / qn; dq[1] = (gx - qx * dot) / qn;
-                    dq[2] = (gy - qy * dot) / qn; dq[3] = (gz - qz * dot) / qn;
+                    dq[0] = (gw - qw * dot) * iqn; dq[1] = (gx - qx * dot) * iqn;
+                    dq[2] = (gy - qy * dot) * iqn; dq[3] = (gz - qz * dot) * iqn;
                 }
                 // dJ = dTm W^T (J has four non-zero entries)
                 float dJ00 = dTm[0] * W[0] + dTm[1] * W[1] + dTm[2] * W[2];
@@ -345,19 +349,20 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                 if (dsig != 0.f) {
                     // sigma = 3 sqrt(lambda_max(r_b^2 J J^T + low-pass)), r_b = r_ref / sharpness
                     const float sh = raw[7];
-                    const float rb = k.r_ref / sh, r2 = rb * rb;
+                    const float ish = rcp(sh), rb = k.r_ref * ish, r2 = rb * rb;
                     const float ma = r2 * (J00 * J00 + J02 * J02) + k.dilation;
                     const float mb = r2 * J02 * J12;
                     const float mc = r2 * (J11 * J11 + J12 * J12) + k.dilation;
                     const float hd = 0.5f * (ma - mc);
                     const float sq = sqrtf(hd * hd + mb * mb);
                     const float lam = 0.5f * (ma + mc) + sq;
-                    const float dlam = dsig * 1.5f / sqrtf(lam);
+                    const float dlam = dsig * 1.5f * __builtin_amdgcn_rsqf(lam);
                     float dma, dmb, dmc;
                     if (sq > 0.f) {
-                        dma = dlam * (0.5f + 0.5f * hd / sq);
-                        dmc = dlam * (0.5f - 0.5f * hd / sq);
-                        dmb = dlam * mb / sq;
+                        const float isq = rcp(sq);
+                        dma = dlam * (0.5f + 0.5f * hd * isq);
+                        dmc = dlam * (0.5f - 0.5f * hd * isq);
+                        dmb = dlam * mb * isq;
                     } else {
                         dma = dmc = 0.5f * dlam;
                         dmb = 0.f;
@@ -367,7 +372,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                     dJ12 += r2 * J02 * dmb + 2.f * r2 * J12 * dmc;
                     dJ11 += 2.f * r2 * J11 * dmc;
                     const float dr2 = dma * (J00 * J00 + J02 * J02) + dmb * J02 * J12 + dmc * (J11 * J11 + J12 * J12);
-                    dsh = dr2 * 2.f * rb * (-k.r_ref / (sh * sh));
+                    dsh = dr2 * 2.f * rb * (-rb * ish);
                 }
                 // mu = (fx t_x/t_z + cx, fy t_y/t_z + cy) and J(t)
                 const float iz2 = iz * iz, iz3 = iz2 * iz;
@@ -387,7 +392,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
                         for (int c = 0; c < 3; ++c) C[c] = -(W[c] * cm[9] + W[3 + c] * cm[10] + W[6 + c] * cm[11]);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) dv[c] = S[c] - C[c];
-                        const float len = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), il = 1.f / len;
+                        const float len = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), il = rcp(len);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) dv[c] *= il;
                         // g = sum_j (dl/dc . sh_j) grad Y_j, taken as the basis is built
