@@ -63,6 +63,10 @@ def lib():
         L.orc_theta.argtypes = [C.c_int, C.c_double, C.c_double, ip, dp]
         L.orc_theta.restype = C.c_int
         L.orc_frame_grad.restype = C.c_int
+        L.orc_frame_zkeys.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_frame_zkeys.restype = None
+        L.orc_gamma_star.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, ip]
+        L.orc_gamma_star.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -79,7 +83,7 @@ class _Config(C.Structure):
     _fields_ = [("L", C.c_int), ("tile", C.c_int), ("z_near", C.c_double), ("g_min", C.c_double),
                 ("t_min", C.c_double), ("alpha_max", C.c_double), ("dilation", C.c_double),
                 ("r_ref", C.c_double), ("bg", C.c_double * 3), ("no_boundary", C.c_int),
-                ("lattice", C.c_int)]
+                ("lattice", C.c_int), ("exact_keys", C.c_int)]
 
 
 @dataclass
@@ -96,11 +100,12 @@ class Config:
     bg: tuple = (0.0, 0.0, 0.0)
     no_boundary: bool = False  # the ablation variant without blending coefficients (w = 1)
     lattice: int = 0           # m >= 2: m Gaussians per flat sub-triangle edge instead of one per pixel
+    exact_keys: bool = False   # untruncated FP64 depth keys (to show what the 40-bit truncation changes)
 
     def c(self) -> _Config:
         return _Config(self.L, self.tile, self.z_near, self.g_min, self.t_min, self.alpha_max,
                        self.dilation, self.r_ref, (C.c_double * 3)(*self.bg), int(self.no_boundary),
-                       int(self.lattice))
+                       int(self.lattice), int(self.exact_keys))
 
     @property
     def kappa2(self) -> float:
@@ -216,6 +221,13 @@ class Frame:
         lib().orc_frame_raster(self._h, _ip(it), _dp(iu), isb.ctypes.data, val.ctypes.data)
         return it, iu, isb.astype(bool), val.astype(bool)
 
+    def zkeys(self):
+        """Depth-key bits of each pixel's winner: the FP64 pattern of 1/z,
+        truncated to its high 40 bits unless the frame uses exact keys."""
+        out = np.zeros(self.npx, np.uint64)
+        lib().orc_frame_zkeys(self._h, out.ctypes.data)
+        return out
+
     def records(self, rendered=False):
         """Records [H*W + nlat][GR]: one per pixel (the pixel's Gaussian, or
         in the lattice variant its boundary point only), then the lattice
@@ -258,6 +270,15 @@ class Frame:
         n = lib().orc_pixel_trace(self._h, int(pix), cap, _ip(g), _dp(a), _dp(T), _dp(w))
         n = min(n, cap)
         return g[:n], a[:n], T[:n], w[:n]
+
+    def gamma_star(self, pix, prim):
+        """gamma* of primitive `prim` at pixel `pix` and the record index of
+        the boundary point its gradient is routed to (-1: none in range)."""
+        g = np.zeros(1)
+        a = np.zeros(1, np.int32)
+        if lib().orc_gamma_star(self._h, int(pix), int(prim), _dp(g), _ip(a)):
+            raise ValueError("gamma_star failed")
+        return float(g[0]), int(a[0])
 
     def grad(self, grad_image):
         sc = self.scene

@@ -48,8 +48,6 @@
 
 /* boundary distances below this many pixels are the cone point of |q - b| */
 #define D_KINK 1e-6
-/* boundary distance ratios d/sigma closer than this are ties (gamma_star) */
-#define ARG_TIE 1e-5
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -78,6 +76,8 @@ typedef struct {
     int no_boundary;     /* the ablation variant without blending coefficients */
     int lattice;         /* 0: one Gaussian per foreground pixel (Sec. 3.2); m >= 2: instead a
                             lattice of m Gaussians per flat sub-triangle edge on every patch */
+    int exact_keys;      /* 1: depth test and Gaussian order on the untruncated FP64 depths
+                            (only to show what the 40-bit truncation changes) */
 } orc_config;
 
 /* per-pixel Gaussian record (doubles) */
@@ -95,6 +95,7 @@ typedef struct {
     int tiles_x, tiles_y, ntiles;
     double kappa2;
     int32_t *I_tri;      /* [H*W] sub-triangle id, -1 background */
+    uint64_t *zkey;      /* [H*W] the winner's depth-key bits (truncated unless exact_keys) */
     double *I_uv;        /* [H*W][2] */
     uint8_t *is_b;       /* [H*W] boundary flag (and Gaussian valid) */
     uint8_t *valid;      /* [H*W + nlat] record is a rendered Gaussian */
@@ -231,6 +232,9 @@ static void rasterize(orc_frame *f) {
     int VL = (L + 1) * (L + 2) / 2;
     size_t npx = (size_t)f->W * f->H;
     uint64_t *zbuf = (uint64_t *)calloc(npx, sizeof(uint64_t));
+    /* exact_keys: the full FP64 key and the winning id beside it */
+    uint64_t *zfull = f->cfg.exact_keys ? (uint64_t *)calloc(npx, sizeof(uint64_t)) : NULL;
+    uint32_t *ztri = f->cfg.exact_keys ? (uint32_t *)calloc(npx, sizeof(uint32_t)) : NULL;
     rvert *rv = (rvert *)malloc(sizeof(rvert) * VL);
     double cp[64 * 3];
     const double lim = 1048576.0; /* 2^20 px */
@@ -300,7 +304,13 @@ static void rasterize(orc_frame *f) {
                     memcpy(&kb, &key, 8);
                     uint64_t cand = ((kb >> 24) << 24) | (uint64_t)(0xFFFFFFu - tri);
                     size_t pix = (size_t)j * f->W + (size_t)i;
-                    if (cand > zbuf[pix]) zbuf[pix] = cand;
+                    if (zfull) {   /* largest key, lower id on an exactly equal key */
+                        if (zbuf[pix] == 0 || kb > zfull[pix] || (kb == zfull[pix] && tri < ztri[pix])) {
+                            zfull[pix] = kb;
+                            ztri[pix] = tri;
+                            zbuf[pix] = (uint64_t)(0xFFFFFFu - tri) | ((uint64_t)1 << 40);
+                        }
+                    } else if (cand > zbuf[pix]) zbuf[pix] = cand;
                 }
         }
     }
@@ -309,9 +319,12 @@ static void rasterize(orc_frame *f) {
         if (zbuf[pix] == 0) { f->I_tri[pix] = -1; f->I_uv[2 * pix] = f->I_uv[2 * pix + 1] = 0.0; continue; }
         int tri = (int)(0xFFFFFFu - (uint32_t)(zbuf[pix] & 0xFFFFFFu));
         f->I_tri[pix] = tri;
+        f->zkey[pix] = zfull ? zfull[pix] : (zbuf[pix] >> 24) << 24;
     }
     free(rv);
     free(zbuf);
+    free(zfull);
+    free(ztri);
 }
 
 /* Perspective-correct barycentrics of the pixel centre in the winning flat
@@ -670,7 +683,7 @@ static int build_lists(orc_frame *f, int which) {
             double z = r[GR_DEPTH];
             uint64_t zb;
             memcpy(&zb, &z, 8);
-            key = zb >> 24;
+            key = f->cfg.exact_keys ? zb : zb >> 24;   /* z > 0: bit order is numeric order */
         } else {
             key = (uint64_t)(int64_t)r[GR_PRIM];
         }
@@ -704,7 +717,7 @@ static int build_lists(orc_frame *f, int which) {
 
 void orc_frame_free(orc_frame *f) {
     if (!f) return;
-    free(f->I_tri); free(f->I_uv); free(f->is_b); free(f->valid); free(f->has_rec); free(f->rec);
+    free(f->I_tri); free(f->zkey); free(f->I_uv); free(f->is_b); free(f->valid); free(f->has_rec); free(f->rec);
     free(f->g_start); free(f->g_list); free(f->b_start); free(f->b_list);
     free(f);
 }
@@ -737,12 +750,13 @@ orc_frame *orc_frame_create(const orc_scene *sc, const float *cam, int W, int H,
     }
     size_t nrec = npx + (size_t)f->nlat;
     f->I_tri = (int32_t *)malloc(npx * sizeof(int32_t));
+    f->zkey = (uint64_t *)calloc(npx, sizeof(uint64_t));
     f->I_uv = (double *)calloc(2 * npx, sizeof(double));
     f->is_b = (uint8_t *)calloc(npx, 1);
     f->valid = (uint8_t *)calloc(nrec, 1);
     f->has_rec = (uint8_t *)calloc(npx, 1);
     f->rec = (double *)calloc(nrec * GR_N, sizeof(double));
-    if (!f->I_tri || !f->I_uv || !f->is_b || !f->valid || !f->has_rec || !f->rec) { orc_frame_free(f); return NULL; }
+    if (!f->I_tri || !f->zkey || !f->I_uv || !f->is_b || !f->valid || !f->has_rec || !f->rec) { orc_frame_free(f); return NULL; }
     if (I_tri_in) {
         memcpy(f->I_tri, I_tri_in, npx * sizeof(int32_t));
         if (I_uv_in) memcpy(f->I_uv, I_uv_in, 2 * npx * sizeof(double));
@@ -772,6 +786,12 @@ void orc_frame_raster(const orc_frame *f, int32_t *I_tri, double *I_uv, uint8_t 
     if (valid) memcpy(valid, f->has_rec, npx);   /* the pixel's Gaussian record exists */
 }
 
+/* depth-key bits of each pixel's winning sub-triangle (0: background or a
+ * frame made from a given index map) */
+void orc_frame_zkeys(const orc_frame *f, uint64_t *out) {
+    memcpy(out, f->zkey, (size_t)f->W * f->H * sizeof(uint64_t));
+}
+
 /* records [H*W + nlat][GR_N] and which of them are rendered Gaussians */
 void orc_frame_records(const orc_frame *f, double *rec, uint8_t *rendered) {
     size_t nrec = (size_t)f->W * f->H + f->nlat;
@@ -796,12 +816,11 @@ static double gamma_fn(double d, double sigma) {
 
 /* gamma* of primitive g at pixel centre (qx,qy): the smallest gamma over the
  * boundary points of g listed for this tile; returns 1 when none is within
- * range.  *arg receives the point the gradient of gamma* is routed to, or -1
- * when none is within range: the points are scanned in raster order and a
- * point takes over only when its d/sigma is below the current one's by more
- * than ARG_TIE, so near-equal ratios (the pixel-centred boundary points of a
- * planar patch are at equal distances, with radii that differ in the sixth
- * digit) are ties that go to the lower raster index. */
+ * range.  *arg receives the point the gradient of gamma* is routed to: the
+ * minimiser of d/sigma among the points with d/sigma < 1 (gamma is
+ * increasing in d/sigma, so it is the point that attains the minimum of
+ * Eq. 7), the lowest raster index among exactly equal ratios, or -1 when no
+ * point is within range.  The list holds g's points in raster order. */
 static double gamma_star(const orc_frame *f, int tile, int g, double qx, double qy, int *arg) {
     double best = 1.0, rbest = 1.0;
     *arg = -1;
@@ -813,9 +832,21 @@ static double gamma_star(const orc_frame *f, int tile, int g, double qx, double 
         double d = sqrt(dx * dx + dy * dy), ratio = d / r[GR_SIGMA];
         double gm = gamma_fn(d, r[GR_SIGMA]);
         if (gm < best) best = gm;
-        if (ratio < 1.0 && (*arg < 0 || ratio < rbest - ARG_TIE)) { rbest = ratio; *arg = bp; }
+        if (ratio < 1.0 && (*arg < 0 || ratio < rbest)) { rbest = ratio; *arg = bp; }
     }
     return best;
+}
+
+/* gamma* of primitive g at pixel `pix` and the boundary point its gradient
+ * goes to (record index, -1 for none); for the routing checks */
+int orc_gamma_star(const orc_frame *f, int pix, int g, double *gamma, int32_t *arg) {
+    if (!f || pix < 0 || pix >= f->W * f->H || !gamma || !arg) return ORC_EINVAL;
+    int x = pix % f->W, y = pix / f->W;
+    int tile = (y / f->cfg.tile) * f->tiles_x + x / f->cfg.tile;
+    int a;
+    *gamma = gamma_star(f, tile, g, x + 0.5, y + 0.5, &a);
+    *arg = a;
+    return ORC_OK;
 }
 
 typedef struct {
