@@ -28,6 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd Mpixels/s at 800×800, 16 views batched vs per-view, at 1e-4 error"
+IMG_TOL, GRAD_TOL = 1e-4, 1e-3
+GRAD_FLOOR = 5e-2  # per-element gradient error is relative to max(|ref|, GRAD_FLOOR * max|ref|)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -53,6 +55,7 @@ def parse():
     ap.add_argument("--no-train-step", action="store_true",
                     help="skip timing the optimisation step (fwd + Eq. 9 loss + bwd + Adam)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip timing the other configurations")
     ap.add_argument("--cpu-views", type=int, default=16, help="views in the oracle's timed sample")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the batched graph replays (for rocprofv3); prints the JSON line")
@@ -182,25 +185,86 @@ def algorithmic(counters, npx, ntiles, P, ncp):
     return {"blend_fwd": fwd, "blend_bwd": bwd}
 
 
-def cpu_baseline(scene, cams, nviews):
-    """The FP64 oracle, fwd+bwd, on the first `nviews` views (a bounded sample)."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name or platform.processor() or platform.machine(), os.cpu_count()
+
+
+def oracle_config(**mode):
+    """The oracle's constants at the float32 values the library uses."""
     import oracle
-    from paper_2503_13961_amd import scenes as S
-    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
-                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
-    t0 = time.perf_counter()
-    px = 0
+    return oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
+                         dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)), **mode)
+
+
+def reference_leg(scene, cams, images, grads, target, scale, nviews):
+    """The FP64 oracle on the first `nviews` views of the workload, forward and
+    backward: every pixel of its image, and the dense gradient of the timed
+    step's L1 loss with the oracle's own cotangent sign(C - target) * scale.
+    Its forward + backward time is the CPU baseline.  Against it, the timed
+    replay's own outputs: every pixel of every view, and (when all views are
+    taken) the replay's gradients per element.  The two L1 cotangents differ
+    exactly where the target lies between the two images (|C_oracle -
+    target| below the image error there); the patches whose Gaussians reach
+    those pixels differentiate a different loss on the two sides and are
+    left out of the gradient comparison, and counted."""
+    import oracle
+    cfg = oracle_config()
+    off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
+    t_oracle, px, img_err, ref, ambiguous, excluded = 0.0, 0, 0.0, None, 0, set()
     for v in range(nviews):
         W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        sl = slice(off[v], off[v + 1])
+        t0 = time.perf_counter()
         fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
         img = fr.render()[0]
-        gi = np.sign(img - S.l1_target(W * H, seed=v)) / (3 * W * H)
-        fr.grad(gi)
+        gi = np.sign(img - target[sl]) * scale
+        g = fr.grad(gi)
+        t_oracle += time.perf_counter() - t0
         px += W * H
-    dt = time.perf_counter() - t0
-    return {"value": px / dt / 1e6, "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nviews} of the {cams.n_views} views ({px} px), forward + backward, FP64, OpenMP",
-            "seconds": round(dt, 3), "cpu": platform.processor() or platform.machine()}
+        ref = g if ref is None else {k: ref[k] + g[k] for k in ref}
+        err = float(np.abs(images[sl] - img).max())
+        img_err = max(img_err, err)
+        amb = np.nonzero((np.sign(images[sl] - target[sl]) != np.sign(img - target[sl])).any(axis=1))[0]
+        ambiguous += len(amb)
+        if len(amb):
+            prim = fr.records()[:, oracle.GR["PRIM"]].astype(np.int64)
+            for q in amb:
+                excluded.update(int(prim[x]) for x in fr.trace(int(q))[0])
+        del fr
+    cores = oracle.num_threads()
+    cpu, logical = cpu_model()
+    out = {"cpu_baseline": {"value": px / t_oracle / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+                            "sample": f"{nviews} of the {cams.n_views} views ({px} px), forward + backward, FP64, "
+                                      f"OpenMP", "seconds": round(t_oracle, 3), "cpu": cpu,
+                            "logical_cpus": logical},
+           "image_max_abs_err": img_err, "image_pixels_checked": px}
+    if nviews == cams.n_views and grads is not None:
+        P = scene.num_prims
+        keep = np.ones(P, bool)
+        keep[sorted(excluded)] = False
+        gr = {}
+        for k, r in ref.items():
+            got = np.asarray(grads[k], np.float64).reshape(r.shape)
+            scale_k = np.abs(r).max()
+            err = np.abs(got - r) / max(scale_k, 1e-300)
+            rel = np.abs(got - r) / np.maximum(np.abs(r), GRAD_FLOOR * scale_k)
+            gr[k] = {"max_err_over_max": float(err[..., keep].max(initial=0.0)),
+                     "per_element_rel": float(rel[..., keep].max(initial=0.0)),
+                     "max_err_over_max_incl_excluded": float(err.max(initial=0.0))}
+        out["grads"] = gr
+        out["ambiguous_channels"] = int(ambiguous)
+        out["patches_excluded"] = int((~keep).sum())
+    return out
 
 
 def profiled(workload, kernel):
@@ -234,7 +298,7 @@ def copy_bandwidth(dev, mib=1024, reps=5):
     return gbs
 
 
-def path_bytes(counters, npx, ntiles):
+def path_bytes(counters, npx, ntiles, backward=True):
     """Algorithmic HBM bytes of one whole fwd+bwd step, each buffer the method
     must produce or consume counted once per essential read or write: per
     pixel the index map and (u, v) written and read, image, transmittance
@@ -245,16 +309,17 @@ def path_bytes(counters, npx, ntiles):
     in the backward with the gradient read-modify-write; per boundary pair
     the same with its 16-byte record; per tile its list ranges."""
     gp, bp, fg, nb = counters[1], counters[2], counters[3], counters[4]
-    return (npx * (12 + 12 + 20 + 24) + fg * (44 + 48) + nb * (4 + 4 + 16 + 24)
-            + gp * (12 + 24 + 4 + 44 + 4 + 44 + 72) + bp * (12 + 24 + 4 + 16 + 4 + 16 + 24) + ntiles * 24)
+    fwd = npx * (12 + 12 + 20) + fg * 44 + nb * (4 + 4 + 16) + gp * (12 + 24 + 4 + 44) + bp * (12 + 24 + 4 + 16) \
+        + ntiles * 24
+    bwd = npx * 24 + fg * 48 + nb * 24 + gp * (4 + 44 + 72) + bp * (4 + 16 + 24)
+    return fwd + (bwd if backward else 0)
 
 
 def parity_check(scene, cams, images, samples=6000, seed=0, views=None, **mode):
     """Image parity of the timed replay's output on sampled pixels of every
     view (or of `views`); `mode` sets the oracle's variant (e.g. lattice=4)."""
     import oracle
-    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
-                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)), **mode)
+    cfg = oracle_config(**mode)
     rng = np.random.default_rng(seed)
     off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
     worst = 0.0
@@ -267,38 +332,101 @@ def parity_check(scene, cams, images, samples=6000, seed=0, views=None, **mode):
     return worst
 
 
-def grad_parity_check(scene, cams, renderer, params, camt, wh, per_view=48, seed=1):
-    """Gradient parity at the full workload in the timed launch configuration.
-    The cotangent is an L1-loss sign pattern on `per_view` sampled pixels of
-    every view and zero elsewhere, so the oracle's backward (which skips
-    pixels with a zero cotangent) stays bounded; every parameter array is
-    compared to 1e-3 of its largest oracle entry."""
+class ForwardStep:
+    """The forward pass alone (all stages up to the image)."""
+
+    def __init__(self, renderer, degree, params, camt, wh):
+        self.r, self.degree, self.params, self.camt, self.wh = renderer, degree, params, camt, wh
+        self.npx = int((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
+        self.images, self.state = renderer.forward(degree, params, camt, wh, check=True)
+
+    def __call__(self):
+        self.r.forward(self.degree, self.params, self.camt, self.wh, state=self.state, images=self.images,
+                       check=False)
+
+
+# The workload list's configurations, each timed at its own size (the metric
+# line above is the 16 x 800^2 batch) with the (tile, batch) the autotuner
+# picks: (name, forward only, autotuner candidates ("all" or a list), views
+# whose every pixel is checked against the oracle (None: all), sampled
+# pixels in each other view)
+CONFIGS = [
+    ("random64", True, "all", None, 0),
+    ("sphere2k_1v", False, "all", None, 0),
+    ("sphere2k_16v_mixed", False, "all", None, 0),
+    ("box20k_cubic", False, "all", None, 0),
+    ("sphere50k_32v", False, [(8, 64), (16, 64), (32, 64)], [0], 1500),
+]
+
+
+def time_configs(dev, steps, warmup, parity=True):
+    """Mpixels/s, HBM fraction of the algorithmic bytes and image parity of
+    every configuration of the workload list (the last one autotuned over
+    tile sizes 8, 16 and 32)."""
     import torch
+    from paper_2503_13961_amd import scenes as S
+    from paper_2503_13961_amd.render import Renderer, scene_tensors
+    out = {}
+    for name, fwd_only, cands, full_views, per_view in CONFIGS:
+        scene, cams, desc = S.workload(name)
+        params = scene_tensors(scene, dev)
+        camt = torch.from_numpy(cams.cams).to(dev)
+        wh = np.ascontiguousarray(cams.wh, dtype=np.int32)
+        rec = {"what": desc + (", forward only" if fwd_only else ", forward + L1 cotangent + backward")}
+        if cands:
+            from paper_2503_13961_amd.autotune import CANDIDATES, autotune
+            tune = autotune(scene.degree, params, camt, wh, candidates=CANDIDATES if cands == "all" else cands,
+                            cache=False)
+            tile, batch = tune["tile"], tune["batch"]
+            rec["autotune_ms"] = {k: round(v, 4) for k, v in tune["timings"].items()}
+        else:
+            tile, batch = 16, 64
+        r = Renderer(0, tile=tile, batch=batch)
+        if fwd_only:
+            step = ForwardStep(r, scene.degree, params, camt, wh)
+        else:
+            step = Step(r, scene.degree, params, camt, wh, torch.from_numpy(S.l1_target(cams.num_pixels)).to(dev))
+        _, counters = r.query(step.state)
+        g = capture(step)
+        ms = time_replays(g, steps, warmup)
+        npx = step.npx
+        ntiles = sum(((int(w) + tile - 1) // tile) * ((int(h) + tile - 1) // tile) for w, h in wh)
+        pb = path_bytes(counters, npx, ntiles, backward=not fwd_only)
+        rec.update({"views": int(cams.n_views), "pixels": npx, "prims": scene.num_prims, "degree": scene.degree,
+                    "tile": tile, "batch": batch, "ms_per_step": round(ms, 4),
+                    "value": round(npx / (ms * 1e-3) / 1e6, 2), "unit": "Mpixels/s",
+                    "algorithmic_bytes": int(pb), "hbm_frac": round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        if parity:
+            img = step.images.detach().cpu().numpy()
+            views = range(cams.n_views) if full_views is None else full_views
+            err = full_frame_error(scene, cams, img, views)
+            rec["image_max_abs_err_full_views"] = err
+            rec["full_views"] = len(views)
+            if per_view:
+                rest = [v for v in range(cams.n_views) if v not in set(views)]
+                es = parity_check(scene, cams, img, samples=per_view * cams.n_views, views=rest)
+                rec["image_max_abs_err_sampled"] = es
+                rec["sampled"] = f"{per_view} px in each of the other {len(rest)} views"
+                err = max(err, es)
+            rec["image_ok"] = bool(err <= IMG_TOL)
+        log(f"[bench] config {name}: {rec}")
+        out[name] = rec
+        del g, step, r
+        torch.cuda.synchronize()
+    return out
+
+
+def full_frame_error(scene, cams, images, views):
+    """Largest |image - oracle| over every pixel of the given views."""
     import oracle
-    cfg = oracle.Config(z_near=float(np.float32(0.2)), alpha_max=float(np.float32(0.99)),
-                        dilation=float(np.float32(0.3)), r_ref=float(np.float32(1e-2)))
-    rng = np.random.default_rng(seed)
+    cfg = oracle_config()
     off = np.concatenate([[0], np.cumsum(cams.wh[:, 0].astype(np.int64) * cams.wh[:, 1])])
-    gi = np.zeros((int(off[-1]), 3), np.float32)
-    for v in range(cams.n_views):
-        n = int(off[v + 1] - off[v])
-        pix = off[v] + rng.choice(n, size=min(per_view, n), replace=False)
-        gi[pix] = np.sign(rng.standard_normal((len(pix), 3))).astype(np.float32) / gi.size
-    images, state = renderer.forward(scene.degree, params, camt, wh, check=True)
-    grads = renderer.backward(scene.degree, params, camt, wh, images, torch.from_numpy(gi).to(camt.device), state)
-    torch.cuda.synchronize()
-    ref = None
-    for v in range(cams.n_views):
+    worst = 0.0
+    for v in views:
         W, H = int(cams.wh[v, 0]), int(cams.wh[v, 1])
         fr = oracle.Frame(scene, cams.cams[v], W, H, cfg)
-        g = fr.grad(gi[off[v]:off[v + 1]].astype(np.float64))
-        ref = g if ref is None else {k: ref[k] + g[k] for k in ref}
+        worst = max(worst, float(np.abs(images[off[v]:off[v + 1]] - fr.render()[0]).max()))
         del fr
-    worst = {}
-    for k, r in ref.items():
-        got = grads[k].detach().cpu().numpy().astype(np.float64).reshape(r.shape)
-        scale = np.abs(r).max()
-        worst[k] = float(np.abs(got - r).max() / scale) if scale > 0 else float(np.abs(got).max())
     return worst
 
 
@@ -367,6 +495,7 @@ def main():
     if tune is not None:
         out["autotune_ms"] = {k: round(v, 4) for k, v in tune["timings"].items()}
     images_batched = step.images.detach().cpu().numpy()
+    grads_batched = {k: v.detach().cpu().numpy() for k, v in step.grads.items()}  # the replay's own gradients
     if args.profile_run:
         print(json.dumps(out), flush=True)
         return
@@ -478,6 +607,8 @@ def main():
                                   "norms); decision + rebuilt arrays (includes one host read of the count)"}
         log(f"[bench] densify: {out['densify']}")
         del pst, new
+    if not args.no_configs:
+        out["configs"] = time_configs(dev, args.steps, args.warmup, parity=not args.no_parity)
     stages = stage_profile(step)
     out["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
     log(f"[bench] stages {out['stage_ms']}")
@@ -504,18 +635,25 @@ def main():
                             "frac_of_copy": round(pb / (ms * 1e-3) / 1e9 / cp, 4)}
     out["counters"] = {"gauss_pairs": counters[1], "boundary_pairs": counters[2], "foreground_px": counters[3],
                        "boundary_px": counters[4]}
-    if not args.no_parity:
-        err = parity_check(scene, cams, images_batched)
-        gerr = grad_parity_check(scene, cams, r, params, camt, wh)
-        gmax = max(gerr.values())
-        out["parity"] = {"image_max_abs_err_sampled": err, "image_tolerance": 1e-4,
-                         "grad_max_rel_err_sampled": gmax, "grad_tolerance": 1e-3,
-                         "ok": bool(err <= 1e-4 and gmax <= 1e-3)}
-        log(f"[bench] parity: sampled image max abs err {err:.2e}; gradients {gerr}")
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(scene, cams, args.cpu_views)
-        out["cpu_baseline"] = cb
-        log(f"[bench] cpu baseline {cb}")
+    if not (args.no_parity and args.no_cpu_baseline):
+        nv = cams.n_views if not args.no_parity else min(args.cpu_views, cams.n_views)
+        ref = reference_leg(scene, cams, images_batched, grads_batched, S.l1_target(cams.num_pixels),
+                            1.0 / (3 * npx), nv)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = ref["cpu_baseline"]
+            log(f"[bench] cpu baseline {ref['cpu_baseline']}")
+        if not args.no_parity:
+            gw = max(max(v["max_err_over_max"], v["per_element_rel"]) for v in ref["grads"].values())
+            out["parity"] = {"image_max_abs_err": ref["image_max_abs_err"], "image_pixels": ref["image_pixels_checked"],
+                             "image_tolerance": IMG_TOL, "grads": ref["grads"], "grad_tolerance": GRAD_TOL,
+                             "grad_floor": GRAD_FLOOR, "ambiguous_l1_channels": ref["ambiguous_channels"],
+                             "patches_excluded": ref["patches_excluded"],
+                             "what": "every pixel of the timed replay's images and the replay's own gradients "
+                                     "(dense L1 cotangent) against the FP64 oracle; per-element error relative "
+                                     "to max(|ref|, floor * max|ref|)",
+                             "ok": bool(ref["image_max_abs_err"] <= IMG_TOL and gw <= GRAD_TOL)}
+            log(f"[bench] parity: image {ref['image_max_abs_err']:.2e} on {ref['image_pixels_checked']} px; "
+                f"gradients {ref['grads']}; excluded patches {ref['patches_excluded']}")
     print(json.dumps(out), flush=True)
 
 

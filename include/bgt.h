@@ -20,6 +20,16 @@
  *    allocates nothing per call, so calls are safe under stream capture.
  *  - Errors are return codes.  Argument errors give BGT_E_INVALID before any
  *    work is enqueued; bgt_last_error(ctx) has the text.
+ *  - Capacity overflow.  The pair lists live in the caller's state, sized by
+ *    pair_factor and bpair_factor; a forward pass that needs more clamps the
+ *    lists (its images and gradients are then incomplete) and records the
+ *    overflow on the device, also inside a captured graph.  The device
+ *    copies the bits into a word of pinned host memory that the context
+ *    owns, so the next bgt_render_fwd or bgt_render_bwd on the context that
+ *    runs after the device has executed that pass returns BGT_E_OVERFLOW
+ *    without waiting for the device and enqueues nothing; bgt_query always
+ *    reports it.  Reporting clears the word.  The caller then grows the
+ *    capacities (a new context), resizes the state and recomputes.
  *  - A context is not thread-safe; use one context per host thread.
  *
  * Layouts (structure of arrays, float32)
@@ -144,8 +154,10 @@ bgt_status bgt_validate_prims(const bgt_prims *prims, const bgt_config *cfg);
 bgt_status bgt_validate_views(const bgt_views *views);
 
 /* Create a context on HIP device `device`; device -1 gives a host-only
- * context that can size and validate but not enqueue work.  *out is NULL on
- * failure. */
+ * context that can size and validate but not enqueue work.  A device context
+ * allocates its 8-byte overflow word of pinned host memory here (freed by
+ * bgt_destroy).  *out is NULL
+ * on failure. */
 bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out);
 void bgt_destroy(bgt_ctx *ctx);
 /* Text of the last error on this context (never NULL). */
@@ -167,8 +179,9 @@ bgt_status bgt_state_size(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
  * inspection and tests.  Order: counters, zbuf(u64), I_tri(i32), I_uv(f32x2),
  * pflags(u8), rec(f32x16), gkey(u64), T_final(f32), last(i32), verts,
  * g_count, g_start, g_cursor, b_count, b_start, b_cursor, g_keys(u64),
- * g_list(u32), b_keys(u64), b_list(u32), dgauss(f32x12), big_tris, scan. */
-#define BGT_STATE_FIELDS 24
+ * g_list(u32), b_keys(u64), b_list(u32), dgauss(f32x12), brec64(f64x3),
+ * big_tris, scan. */
+#define BGT_STATE_FIELDS 25
 bgt_status bgt_state_layout(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
                             int64_t *offsets);
 
@@ -185,10 +198,12 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
 
 /* Synchronizes `stream` and reads the state's counters (host out[8]):
  * [0] overflow flags (bit0 Gaussian pairs, bit1 boundary pairs, bit2 big
- * triangle queue), [1] Gaussian pairs, [2] boundary pairs, [3] foreground
- * pixels, [4] boundary pixels, [5] big triangles, [6] tiles needing the
- * global sort, [7] tiles whose boundary list exceeded LDS.  Returns
- * BGT_E_OVERFLOW when any overflow flag is set. */
+ * triangle queue) of this state's last forward pass together with those of
+ * every forward pass on the context not yet reported, [1] Gaussian pairs,
+ * [2] boundary pairs, [3] foreground pixels, [4] boundary pixels, [5] big
+ * triangles, [6] tiles needing the global sort, [7] tiles whose boundary
+ * list exceeded LDS.  Returns BGT_E_OVERFLOW when any overflow flag is set
+ * (and clears the context's record of it). */
 bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters,
                      void *stream);
 

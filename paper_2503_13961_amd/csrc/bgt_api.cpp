@@ -18,6 +18,9 @@ struct bgt_ctx {
     bool recorded[BGT_NUM_STAGES] = {};
     hipEvent_t ev0[BGT_NUM_STAGES] = {}, ev1[BGT_NUM_STAGES] = {};
     int last_stage = -1;
+    // sticky overflow bits of the forward passes on this context, written by
+    // the device into pinned host memory and cleared when reported
+    unsigned long long *ovf_host = nullptr, *ovf_dev = nullptr;
 };
 
 namespace {
@@ -26,7 +29,8 @@ using namespace bgt;
 
 enum Field {
     F_COUNTERS, F_ZBUF, F_ITRI, F_IUV, F_PFLAGS, F_REC, F_GKEY, F_TFINAL, F_LAST, F_VERTS, F_GCOUNT, F_GSTART,
-    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_DGAUSS, F_BIGTRI, F_SCAN, F_END
+    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_DGAUSS, F_BREC64, F_BIGTRI,
+    F_SCAN, F_END
 };
 static_assert(F_END + 1 == BGT_STATE_FIELDS, "state field count");
 
@@ -52,6 +56,22 @@ bgt_status hip_fail(bgt_ctx *ctx, hipError_t e, const char *where) {
 }
 
 int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Takes (and clears) the context's sticky overflow bits; no device wait: a
+// pass that has not run yet is seen by a later call.
+unsigned long long take_overflow(bgt_ctx *ctx) {
+    if (!ctx->ovf_host || !__atomic_load_n(ctx->ovf_host, __ATOMIC_ACQUIRE)) return 0;
+    return __atomic_exchange_n(ctx->ovf_host, 0ull, __ATOMIC_ACQ_REL);
+}
+
+bgt_status overflow_status(bgt_ctx *ctx, unsigned long long bits) {
+    char msg[160];
+    snprintf(msg, sizeof msg,
+             "an earlier forward pass on this context exceeded a capacity (bits 0x%llx: 1 Gaussian pairs, "
+             "2 boundary pairs, 4 big triangles); its outputs are incomplete: raise pair_factor/bpair_factor",
+             bits);
+    return fail(ctx, BGT_E_OVERFLOW, msg);
+}
 
 bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Shape &sh) {
     bgt_status s;
@@ -149,6 +169,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_BKEYS, 8 * k.cap_b);
     put(F_BLIST, 4 * k.cap_b);
     put(F_DGAUSS, 48 * NR);
+    put(F_BREC64, 24 * N);
     put(F_BIGTRI, 4 * k.cap_big);
     {
         sh.off[F_SCAN] = o;
@@ -185,6 +206,7 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.b_keys = (unsigned long long *)(b + sh.off[F_BKEYS]);
     p.b_list = (uint32_t *)(b + sh.off[F_BLIST]);
     p.dgauss = (float *)(b + sh.off[F_DGAUSS]);
+    p.brec64 = (double *)(b + sh.off[F_BREC64]);
     p.big_tris = (int32_t *)(b + sh.off[F_BIGTRI]);
     p.scan_tmp = (int32_t *)(b + sh.off[F_SCAN]);
     p.bigsort_q = (int32_t *)(b + sh.bigsort_off);
@@ -285,6 +307,22 @@ bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out) {
     if (!ctx) return BGT_E_NOMEM;
     ctx->cfg = c;
     ctx->device = device;
+    if (device >= 0) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || (cur != device && hipSetDevice(device) != hipSuccess) ||
+            hipHostMalloc((void **)&ctx->ovf_host, sizeof(unsigned long long),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            delete ctx;
+            return BGT_E_HIP;
+        }
+        *ctx->ovf_host = 0;
+        if (hipHostGetDevicePointer((void **)&ctx->ovf_dev, ctx->ovf_host, 0) != hipSuccess) {
+            hipHostFree(ctx->ovf_host);
+            delete ctx;
+            return BGT_E_HIP;
+        }
+        if (cur >= 0 && cur != device) hipSetDevice(cur);
+    }
     *out = ctx;
     return BGT_OK;
 }
@@ -295,6 +333,7 @@ void bgt_destroy(bgt_ctx *ctx) {
         if (ctx->ev0[i]) hipEventDestroy(ctx->ev0[i]);
         if (ctx->ev1[i]) hipEventDestroy(ctx->ev1[i]);
     }
+    if (ctx->ovf_host) hipHostFree(ctx->ovf_host);
     delete ctx;
 }
 
@@ -381,6 +420,7 @@ bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     if (s != BGT_OK) return s;
     if (!images || !state) return fail(ctx, BGT_E_INVALID, "images or state is null");
     if (state_bytes < (size_t)sh.off[F_END]) return fail(ctx, BGT_E_NOMEM, "state buffer too small");
+    if (const unsigned long long ov = take_overflow(ctx)) return overflow_status(ctx, ov);
     if ((s = use_device(ctx)) != BGT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const StatePtrs sp = state_ptrs(sh, state);
@@ -407,6 +447,8 @@ bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         StageTimer tm(ctx, 3, st);
         if ((e = launch_blend_fwd(sh.k, sh.vt, sp, images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_fwd");
     }
+    if (ctx->ovf_dev && (e = launch_note_overflow(sp, ctx->ovf_dev, st)) != hipSuccess)
+        return hip_fail(ctx, e, "overflow note");
     return BGT_OK;
 }
 
@@ -422,6 +464,7 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         !grads->sharpness)
         return fail(ctx, BGT_E_INVALID, "null gradient array");
     if (state_bytes < (size_t)sh.off[F_END]) return fail(ctx, BGT_E_NOMEM, "state buffer too small");
+    if (const unsigned long long ov = take_overflow(ctx)) return overflow_status(ctx, ov);
     if ((s = use_device(ctx)) != BGT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const StatePtrs sp = state_ptrs(sh, state);
@@ -651,7 +694,10 @@ bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_
     counters[5] = c[C_BIGTRI];
     counters[6] = c[C_BIGSORT];
     counters[7] = c[C_BIGBLIST];
-    if (c[C_OVERFLOW]) return fail(ctx, BGT_E_OVERFLOW, "pair capacity exceeded; raise pair_factor/bpair_factor");
+    // this state's last pass, and any pass on the context since the last report
+    const unsigned long long ov = (unsigned long long)c[C_OVERFLOW] | take_overflow(ctx);
+    counters[0] = (int64_t)ov;
+    if (ov) return overflow_status(ctx, ov);
     return BGT_OK;
 }
 

@@ -348,6 +348,21 @@ __global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st, in
     }
 }
 
+// Copies the pass's overflow bits, when there are any, into the context's
+// word of pinned host memory: a later call on the context (and bgt_query)
+// reads it without waiting for the device.  A plain system-scope store, not
+// an atomic, so nothing depends on the host bridge's atomics.
+__global__ void k_note_overflow(const int64_t *counters, unsigned long long *flag) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long f = (unsigned long long)counters[C_OVERFLOW];
+    if (f) __hip_atomic_store(flag, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_note_overflow(const StatePtrs &st, unsigned long long *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_note_overflow, dim3(1), dim3(64), 0, s, (const int64_t *)st.counters, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s) {
     const int n = vt.total_tiles;
     const int nb = (n + kScanBlock - 1) / kScanBlock;

@@ -97,8 +97,12 @@ struct BatchLds {
 // patch) lands there up to rounding, so distances below kDKink pixels count
 // as 0 for the position gradient
 constexpr float kDKink = 1e-6f;
-// boundary distance ratios d/sigma closer than this are ties (gamma_lds)
-constexpr float kArgTie = 1e-5f;
+// Bound on |d/sigma in FP32 - d/sigma in FP64| for the staged boundary
+// points (offsets of at most a few pixels from their pixel centres, radii
+// >= 3 sqrt(0.3)): FP32 rounds the stored offsets and radius and the
+// distance and ratio.  Points whose FP32 ratios are within twice this of the
+// smallest are re-decided from the FP64 records.
+constexpr float kRatioBand = 4e-6f;
 
 // -log2(e)/2: G = exp(-d^T Q d / 2) = 2^(kE d^T Q d)
 constexpr float kE = -0.5f * 1.44269504088896341f;
@@ -195,50 +199,126 @@ __device__ __forceinline__ float gamma_fn(float d, float sigma) {
     return g < 1.0f ? g : 1.0f;
 }
 
-// gamma* from the LDS points of run r (the exact minimum, bit-identical to
-// the map), and in *arg the entry its gradient is routed to: scanned in index
-// (raster) order, an entry takes over only when its d/sigma is below the
-// current one's by more than kArgTie, so near-equal ratios are ties that go
-// to the lower index; -1 when no point is within range
+// The boundary point the gradient of gamma* goes to (Suppl. Sec. C, dl/db):
+// the minimiser of d/sigma among the points with d/sigma < 1, the lowest list
+// (raster) index among exactly equal ratios.  The FP32 pass finds the
+// smallest ratio and the first point attaining it; when another point lies
+// within 2 kRatioBand of it, the order is decided again on the FP64 records
+// of the points in that band, which the generation pass keeps for every
+// boundary point, so the choice is the one exact arithmetic makes.
+struct ArgScan {
+    float best = 1.0f;   // gamma* (FP32, the value the forward used)
+    float q1 = 2.0f;     // smallest ratio below 1, and the runner-up
+    float q2 = 2.0f;
+    int e1 = -1;
+    __device__ __forceinline__ void add(float g, float q, int e) {
+        if (g < best) best = g;
+        if (!(q < 1.0f)) return;
+        if (q < q1) { q2 = q1; q1 = q; e1 = e; }
+        else if (q < q2) q2 = q;
+    }
+    __device__ __forceinline__ bool ambiguous() const { return e1 >= 0 && q2 - q1 <= 2.0f * kRatioBand; }
+};
+
+// d/sigma in FP64 from pixel (x, y) to the boundary point of record bpix,
+// whose pixel is (bx, by) (same frame as x, y)
+__device__ __forceinline__ double ratio64(const StatePtrs &st, int bpix, int x, int y, int bx, int by) {
+    const double *b = st.brec64 + (int64_t)bpix * 3;
+    const double dx = (double)(x - bx) - b[0], dy = (double)(y - by) - b[1];
+    return sqrt(dx * dx + dy * dy) / b[2];
+}
+
+// gamma* of run r at tile pixel (lx, ly) from the LDS points (the exact
+// minimum, bit-identical to the map)
 template <typename BL>
-__device__ __forceinline__ float gamma_lds(const BL &B, int r, int lx, int ly, int *arg) {
-    float best = 1.0f, rbest = 1.0f;
-    *arg = -1;
+__device__ __forceinline__ float gamma_lds_value(const BL &B, int r, int lx, int ly) {
+    float best = 1.0f;
     for (int e = B.run_start[r]; e < B.run_start[r + 1]; ++e) {
         const float dx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], dy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
-        const float d = bdist(dx, dy), q = __fdiv_rn(d, B.bs[e]);
-        const float g = gamma_fn(d, B.bs[e]);
+        const float g = gamma_fn(bdist(dx, dy), B.bs[e]);
         if (g < best) best = g;
-        if (q < 1.0f && (*arg < 0 || q < rbest - kArgTie)) { rbest = q; *arg = e; }
     }
     return best;
 }
 
+// FP64 decision among the LDS entries of [e0, e1) whose FP32 ratio at tile
+// pixel (lx, ly) is below 1 and within 2 kRatioBand of the smallest, q1
+// (only near-ties come here)
+template <typename BL>
+__device__ __forceinline__ int redecide_lds(const BL *B, const StatePtrs &st, int bs0, int e0, int e1, float q1, int lx,
+                                         int ly) {
+    double rb = 2.0;
+    int arg = -1;
+    for (int e = e0; e < e1; ++e) {
+        const float dx = (float)(lx - lo16(B->bxy[e])) - B->bdx[e], dy = (float)(ly - hi16(B->bxy[e])) - B->bdy[e];
+        const float q32 = __fdiv_rn(bdist(dx, dy), B->bs[e]);
+        if (!(q32 < 1.0f && q32 <= q1 + 2.0f * kRatioBand)) continue;
+        const double q = ratio64(st, (int)st.b_list[bs0 + e], lx, ly, lo16(B->bxy[e]), hi16(B->bxy[e]));
+        if (q < rb) { rb = q; arg = e; }
+    }
+    return arg;
+}
+
+// ... and in *arg the LDS entry the gradient goes to (-1: none in range)
+template <typename BL>
+__device__ __forceinline__ float gamma_lds(const BL &B, const StatePtrs &st, int bs0, int r, int lx, int ly,
+                                           int *arg) {
+    ArgScan a;
+    const int e0 = B.run_start[r], e1 = B.run_start[r + 1];
+    for (int e = e0; e < e1; ++e) {
+        const float dx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], dy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
+        const float d = bdist(dx, dy);
+        a.add(gamma_fn(d, B.bs[e]), __fdiv_rn(d, B.bs[e]), e);
+    }
+    *arg = a.ambiguous() ? redecide_lds(&B, st, bs0, e0, e1, a.q1, lx, ly) : a.e1;
+    return a.best;
+}
+
 // gamma* straight from global memory (tiles with more boundary points than
-// the LDS stage holds); *arg = entry index in the tile's list
-__device__ __forceinline__ float gamma_global(const StatePtrs &st, const ViewInfo &vi, int bs0, int bc, int g,
-                                              int px, int py, int *arg) {
+// the LDS stage holds); with `arg`, also the entry of the tile's list the
+// gradient goes to
+__device__ __forceinline__ int first_of_prim(const StatePtrs &st, int bs0, int bc, int g) {
     int lo = 0, hi = bc;  // first entry with prim >= g
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         const int pm = __float_as_int(st.rec[(int64_t)st.b_list[bs0 + mid] * 4 + 2].y);
         if (pm < g) lo = mid + 1; else hi = mid;
     }
-    float best = 1.0f, rbest = 1.0f;
-    *arg = -1;
-    for (int e = lo; e < bc; ++e) {
-        const int bpix = (int)st.b_list[bs0 + e];
+    return lo;
+}
+
+__device__ __forceinline__ float gamma_global(const StatePtrs &st, int bs0, int bc, int g, int px, int py, int *arg) {
+    ArgScan a;
+    const int e0 = first_of_prim(st, bs0, bc, g);
+    int e1 = e0;
+    for (; e1 < bc; ++e1) {
+        const int bpix = (int)st.b_list[bs0 + e1];
         const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
         if (__float_as_int(r2.y) != g) break;
         const float4 r0 = st.rec[(int64_t)bpix * 4];
-        const int a = __float_as_int(r2.w);
-        const float dx = (float)(px - lo16(a)) - r0.x, dy = (float)(py - hi16(a)) - r0.y;
-        const float d = bdist(dx, dy), q = __fdiv_rn(d, r2.z);
-        const float gm = gamma_fn(d, r2.z);
-        if (gm < best) best = gm;
-        if (q < 1.0f && (*arg < 0 || q < rbest - kArgTie)) { rbest = q; *arg = e; }
+        const int c = __float_as_int(r2.w);
+        const float dx = (float)(px - lo16(c)) - r0.x, dy = (float)(py - hi16(c)) - r0.y;
+        const float d = bdist(dx, dy);
+        a.add(gamma_fn(d, r2.z), __fdiv_rn(d, r2.z), e1);
     }
-    return best;
+    if (arg) {
+        *arg = a.e1;
+        if (a.ambiguous()) {
+            double rb = 2.0;
+            for (int e = e0; e < e1; ++e) {
+                const int bpix = (int)st.b_list[bs0 + e];
+                const float4 r0 = st.rec[(int64_t)bpix * 4];
+                const float4 r2 = st.rec[(int64_t)bpix * 4 + 2];
+                const int c = __float_as_int(r2.w);
+                const float dx = (float)(px - lo16(c)) - r0.x, dy = (float)(py - hi16(c)) - r0.y;
+                const float q32 = __fdiv_rn(bdist(dx, dy), r2.z);
+                if (!(q32 < 1.0f && q32 <= a.q1 + 2.0f * kRatioBand)) continue;
+                const double q = ratio64(st, bpix, px, py, lo16(c), hi16(c));
+                if (q < rb) { rb = q; *arg = e; }
+            }
+        }
+    }
+    return a.best;
 }
 
 // Pixel rows [y0, y1] of the tile that a point's disc can reach, one row
@@ -364,15 +444,14 @@ __device__ __forceinline__ bool touches4(int xr, int yr, int x0, int y0) {
     return !(hi16(xr) < x0 || lo16(xr) > x0 + 3 || hi16(yr) < y0 || lo16(yr) > y0 + 3);
 }
 
-// Which of the batch entries [c0, c0 + 64) (below n) can reach this lane's
-// 4x4 sub-block: one ballot per sub-block of the wave's 8x8 block at
-// (wx0, wy0), each lane keeping its own row's.  An entry counts when its
-// support box touches the sub-block and the sub-block's centre is within the
-// conic bound of sub_block_bound (an entry skipped here has no live pixel
-// there, so the result does not change).
+// Which of the batch entries [c0, c0 + 64) (below n) can reach each 4x4
+// sub-block of the wave's 8x8 block at (wx0, wy0): one ballot per sub-block.
+// An entry counts when its support box touches the sub-block and the
+// sub-block's centre is within the conic bound of sub_block_bound (an entry
+// left out has no live pixel there, so the result does not change).
 template <int TS, int K>
-__device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
-                                                       int wx0, int wy0) {
+__device__ __forceinline__ void sub_block_masks(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
+                                                int wx0, int wy0, unsigned long long (&mb)[4]) {
     const int j = c0 + lane, jj = j < K ? j : K - 1;
     const bool in = j < n;
     const int a = S.xr[jj], b = S.yr[jj];
@@ -384,12 +463,20 @@ __device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K> &S,
     const float by0 = ex.y * dy0, by1 = ex.y * dy1, cy0 = ex.z * dy0 * dy0, cy1 = ex.z * dy1 * dy1;
     const bool n0 = fmaf(dx0, fmaf(ex.x, dx0, by0), cy0) < thr, n1 = fmaf(dx1, fmaf(ex.x, dx1, by0), cy0) < thr;
     const bool n2 = fmaf(dx0, fmaf(ex.x, dx0, by1), cy1) < thr, n3 = fmaf(dx1, fmaf(ex.x, dx1, by1), cy1) < thr;
-    const unsigned long long m0 = __ballot(in && !n0 && touches4(a, b, wx0, wy0));
-    const unsigned long long m1 = __ballot(in && !n1 && touches4(a, b, wx0 + 4, wy0));
-    const unsigned long long m2 = __ballot(in && !n2 && touches4(a, b, wx0, wy0 + 4));
-    const unsigned long long m3 = __ballot(in && !n3 && touches4(a, b, wx0 + 4, wy0 + 4));
+    mb[0] = __ballot(in && !n0 && touches4(a, b, wx0, wy0));
+    mb[1] = __ballot(in && !n1 && touches4(a, b, wx0 + 4, wy0));
+    mb[2] = __ballot(in && !n2 && touches4(a, b, wx0, wy0 + 4));
+    mb[3] = __ballot(in && !n3 && touches4(a, b, wx0 + 4, wy0 + 4));
+}
+
+// ... this lane's row's mask (the forward's rows walk their own sub-block)
+template <int TS, int K>
+__device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
+                                                       int wx0, int wy0) {
+    unsigned long long mb[4];
+    sub_block_masks<TS, K>(S, wave, c0, n, lane, wx0, wy0, mb);
     const int q = lane >> 4;
-    return q == 0 ? m0 : (q == 1 ? m1 : (q == 2 ? m2 : m3));
+    return q == 0 ? mb[0] : (q == 1 ? mb[1] : (q == 2 ? mb[2] : mb[3]));
 }
 
 // index of the lowest set bit of m; 0 when m is 0, so that a row with
@@ -536,9 +623,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         float gam = __uint_as_float(B.map[min(max(r, 0), RM - 1)][tid]);
                         gam = mapped ? gam : 1.0f;
                         if (rare && __any(live && r != -1 && !mapped)) {  // runs without a map, big lists
-                            int arg;
-                            if (live && r >= RM) gam = gamma_lds(B, r, lx, ly, &arg);
-                            else if (live && r == -2) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                            if (live && r >= RM) gam = gamma_lds_value(B, r, lx, ly);
+                            else if (live && r == -2) gam = gamma_global(st, bs0, bc, g, px, py, nullptr);
                         }
                         // w = 0 (gamma* = 1 for another patch's Gaussian) gives
                         // a = 0 with no test: T and C stay as they are
@@ -578,6 +664,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 // over rows and waves in LDS, then added to global memory once per tile.  The
 // boundary terms accumulate per (run, pixel) and go to the minimising
 // boundary point at the end of the tile.
+// (the waves-per-EU hint keeps the register count at 96, five waves per
+// SIMD, without spills: the FP64 arg-min decision of the rare in-loop path
+// would otherwise push it to 104 and four waves)
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
@@ -681,9 +770,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 if (mapped) {
                     gam = __uint_as_float(B.map[r][tid]);
                 } else if (r >= 0) {
-                    if (live) gam = gamma_lds(B, r, lx, ly, &arg);
+                    if (live) gam = gamma_lds(B, st, bs0, r, lx, ly, &arg);
                 } else if (r == -2) {
-                    if (live) gam = gamma_global(st, vi, bs0, bc, g, px, py, &arg);
+                    if (live) gam = gamma_global(st, bs0, bc, g, px, py, &arg);
                 }
                 const float w = own ? gam : 1.0f - gam;
                 live = live && w > 0.0f;
@@ -726,14 +815,15 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                             ddy = (float)(py - hi16(a)) - r0.y;
                             sg = r2.z;
                         }
-                        const float d = sqrtf(ddx * ddx + ddy * ddy);
-                        const float dd = dgm * LN2 / sg * gam;
+                        const float d = bdist(ddx, ddy);
+                        const float gb = gamma_fn(d, sg);  // gamma of the routed point
+                        const float dd = dgm * LN2 / sg * gb;
                         float *dst = st.dgauss + (int64_t)bpix * 12;
                         if (d > kDKink) {
                             unsafeAtomicAdd(&dst[10], -dd * ddx / d);
                             unsafeAtomicAdd(&dst[11], -dd * ddy / d);
                         }
-                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gam);
+                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gb);
                     }
                 }
                 // wave totals, scattered over the lanes of row 0 with bit 2 set,
@@ -765,24 +855,26 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
-    // The arg-min is searched again over the run (first, i.e. lowest raster
-    // index, among equal minima).
+    // The arg-min is searched again over the run (gamma_lds: the smallest
+    // d/sigma, near-ties decided in FP64, the lowest raster index among
+    // exactly equal ratios).
     __syncthreads();  // the loaders' last flush reads acc, which bacc overlays
     float(&bacc)[BoundaryCap<TS>::value][3] = U.bacc;
     for (int i = tid; i < BoundaryCap<TS>::value * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
     const int nmap = B.n_runs < RM ? B.n_runs : RM;
+    for (int r = 0; r < nmap; ++r) {  // not unrolled: one copy of the arg-min search
+        float dg = 0.f;               // dgr[r] by selects (r is uniform; dgr stays in registers)
 #pragma unroll
-    for (int r = 0; r < RM; ++r) {
-        const float dg = dgr[r];
-        if (r >= nmap) continue;
+        for (int i = 0; i < RM; ++i) dg = i == r ? dgr[i] : dg;
         if (dg == 0.f) continue;
         int e = -1;
-        const float gam = gamma_lds(B, r, lx, ly, &e);
-        if (e < 0 || !(gam < 1.0f)) continue;
+        const float gst = gamma_lds(B, st, bs0, r, lx, ly, &e);
+        if (e < 0 || !(gst < 1.0f)) continue;
         const float ddx = (float)(lx - lo16(B.bxy[e])) - B.bdx[e], ddy = (float)(ly - hi16(B.bxy[e])) - B.bdy[e];
         const float sg = B.bs[e];
-        const float d = sqrtf(ddx * ddx + ddy * ddy);
+        const float d = bdist(ddx, ddy);
+        const float gam = gamma_fn(d, sg);  // gamma of the routed point (gamma* up to FP32 rounding)
         const float dd = dg * LN2 / sg * gam;
         if (d > kDKink) {
             atomicAdd(&bacc[e][0], -dd * ddx / d);

@@ -685,6 +685,11 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                     const double lam_max = 0.5 * (ma + mc) + sqrt(0.25 * (ma - mc) * (ma - mc) + mb * mb);
                     const double sg = 3.0 * sqrt(lam_max);
                     sigma = (float)sg;
+                    // the FP64 point, for the exact arg-min of the backward
+                    double *b64 = st.brec64 + (int64_t)pix * 3;
+                    b64[0] = mux - (x + 0.5);
+                    b64[1] = muy - (y + 0.5);
+                    b64[2] = sg;
                     centre_range(mux, sg, vi.W, bi0, bi1);
                     centre_range(muy, sg, vi.H, bj0, bj1);
                     flags |= PF_BOUNDARY;

@@ -186,6 +186,7 @@ struct StatePtrs {
     unsigned long long *g_keys, *b_keys;
     uint32_t *g_list, *b_list;
     float *dgauss;         // [records][12]
+    double *brec64;        // [pixels][3] boundary points in FP64: mu - pixel centre (x, y), sigma
     int32_t *big_tris;     // [cap_big] queue of raster items
     int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
     int32_t *scan_tmp;     // block sums
@@ -253,6 +254,7 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s);
 hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s);
+hipError_t launch_note_overflow(const StatePtrs &st, unsigned long long *flag, hipStream_t s);
 hipError_t launch_blend_fwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, float *image,
                             hipStream_t s);
 hipError_t launch_blend_bwd(const Consts &k, const ViewTable &vt, const StatePtrs &st,

@@ -15,14 +15,15 @@ LIB_PATH = os.path.join(HERE, "libbgt.so")
 BGT_OK, BGT_E_INVALID, BGT_E_NOMEM, BGT_E_OVERFLOW, BGT_E_HIP, BGT_E_UNSUPPORTED = range(6)
 BGT_MAX_VIEWS = 64
 BGT_FLAG_NO_BOUNDARY = 1  # bgt_config.flags: the variant without blending coefficients (w = 1)
-BGT_STATE_FIELDS = 24
+BGT_STATE_FIELDS = 25
 STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey", "T_final", "last",
                      "verts", "g_count", "g_start", "g_cursor", "b_count", "b_start", "b_cursor",
-                     "g_keys", "g_list", "b_keys", "b_list", "dgauss", "big_tris", "scan", "end"]
+                     "g_keys", "g_list", "b_keys", "b_list", "dgauss", "brec64", "big_tris", "scan", "end"]
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
            "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query", "bgt_profile",
-           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_l1_cotangent", "bgt_adam_step",
+           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_l1_cotangent",
+           "bgt_adam_step",
            "bgt_default_densify_config", "bgt_stats_accumulate", "bgt_densify_plan", "bgt_densify_apply"]
 BGT_NUM_STAGES = 6
 STAGE_NAMES = ["raster", "generation", "binning", "blend_fwd", "blend_bwd", "param_bwd"]

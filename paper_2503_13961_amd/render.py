@@ -91,8 +91,14 @@ class Renderer:
                 state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             if images is None:
                 images = torch.empty((npx, 3), dtype=torch.float32, device=self.device)
-            N.bgt_render_fwd(self.ctx, self.prims_struct(degree, params), self.views_struct(cams, wh),
-                             _ptr(images), _ptr(state), state.numel(), _stream())
+            try:
+                N.bgt_render_fwd(self.ctx, self.prims_struct(degree, params), self.views_struct(cams, wh),
+                                 _ptr(images), _ptr(state), state.numel(), _stream())
+            except N.BgtError as err:  # an earlier unchecked pass on this context overflowed
+                if err.status != N.BGT_E_OVERFLOW or not check:
+                    raise
+                self._grow()
+                continue
             if not check:
                 return images, state
             st, _ = N.bgt_query(self.ctx, _ptr(state), state.numel(), _stream())

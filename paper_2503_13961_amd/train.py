@@ -106,3 +106,70 @@ class TrainStep:
                         self.grads)
         self.opt.step(self.grads)
         return loss
+
+    # ------------------------------------------------ a checked training loop
+
+    def _snapshot(self):
+        """Device copies of everything a step changes: parameters, Adam moments, step count."""
+        names = self.opt.names
+        return ({k: self.params[k].clone() for k in names}, {k: self.opt.m[k].clone() for k in names},
+                {k: self.opt.v[k].clone() for k in names}, self.opt.step_count.clone())
+
+    def _restore(self, snap):
+        p, m, v, t = snap
+        for k in self.opt.names:
+            self.params[k].copy_(p[k])
+            self.opt.m[k].copy_(m[k])
+            self.opt.v[k].copy_(v[k])
+        self.opt.step_count.copy_(t)
+
+    def _capture(self):
+        self()  # warm-up outside the capture (first launches load the kernels)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self()
+        torch.cuda.synchronize()
+        return g
+
+    def run(self, steps: int, check_every: int = 8, graph: bool = True) -> dict:
+        """Take `steps` optimisation steps (replayed from one captured graph,
+        or eagerly) and check for a pair-capacity overflow every `check_every`
+        steps.  The pair lists are sized when the loop starts; as training
+        moves the patches (larger Gaussians reach more tiles) a forward pass
+        can need more, and its lists are then cut short.  The library records
+        that on the device (a sticky flag in pinned memory that bgt_query
+        reads), so at each check, after the group of steps: if any of them
+        overflowed, the parameters, moments and step count go back to their
+        values at the previous check, the capacities double, the state is
+        resized, the graph is captured again and the group is taken again.
+        Returns {"steps", "recoveries", "checks"}."""
+        snap = self._snapshot()
+        g = self._capture() if graph else None
+        if g is not None:
+            self._restore(snap)  # the warm-up and the captured launch both stepped
+        done = recoveries = checks = 0
+        while done < steps:
+            n = min(check_every, steps - done)
+            for _ in range(n):
+                if g is not None:
+                    g.replay()
+                else:
+                    self()
+            st, _ = self.r.query(self.state)  # syncs; includes every pass since the last check
+            checks += 1
+            if st == N.BGT_OK:
+                done += n
+                snap = self._snapshot()
+                continue
+            recoveries += 1
+            self._restore(snap)
+            g = None  # the captured kernels hold the old context's capacities
+            self.r._grow()
+            self.images, self.state = self.r.forward(self.degree, self.params, self.cams, self.wh)
+            self.grad_images = torch.empty_like(self.images)
+            if graph:
+                g = self._capture()
+                self._restore(snap)
+        torch.cuda.synchronize()
+        return {"steps": done, "recoveries": recoveries, "checks": checks}

@@ -91,3 +91,36 @@ def grad_error(g, ref):
     """Worst absolute error relative to the tensor's largest reference entry."""
     scale = np.abs(ref).max()
     return float(np.abs(g - ref).max() / scale) if scale > 0 else float(np.abs(g).max())
+
+
+# Per-element gradient tolerance: |g - ref| <= GRAD_REL * max(|ref|, GRAD_FLOOR
+# * max|ref|) for every element of a tensor.  Entries at least 1/20 of the
+# tensor's largest are held to 1e-3 of themselves; smaller ones to 5e-5 of the
+# largest.  The floor is set by the discrete cut-offs of the rendering (the
+# support G >= g_min and the stop at T < T_min, both 2^-15): where FP32 and
+# FP64 fall on different sides of one, a pixel's term moves by up to about
+# 3e-5 of its size, and an entry whose terms cancel keeps that as an absolute
+# error of up to about 3e-5 of the largest entries.
+GRAD_REL = 1e-3
+GRAD_FLOOR = 5e-2
+
+
+def grad_rel_error(g, ref, floor=GRAD_FLOOR):
+    """Worst per-element relative error |g - ref| / max(|ref|, floor max|ref|)."""
+    g, ref = np.asarray(g, np.float64).reshape(-1), np.asarray(ref, np.float64).reshape(-1)
+    scale = np.abs(ref).max(initial=0.0)
+    if scale == 0:
+        return float(np.abs(g).max(initial=0.0))
+    return float((np.abs(g - ref) / np.maximum(np.abs(ref), floor * scale)).max())
+
+
+def check_grads(got, ref, tol=GRAD_REL, skip=()):
+    """Assert both gradient measures for every array: the worst error over
+    the tensor's largest entry, and the per-element relative error above."""
+    for k in ref:
+        if k in skip:
+            continue
+        g, r = np.asarray(got[k], np.float64).reshape(ref[k].shape), ref[k]
+        e, el = grad_error(g, r), grad_rel_error(g, r)
+        log(f"    {k}: max err / max|ref| = {e:.2e}, per element {el:.2e}  (max|ref| {np.abs(r).max():.2e})")
+        assert e <= tol and el <= tol, (k, e, el)

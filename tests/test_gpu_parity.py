@@ -2,7 +2,8 @@
 
 Integer outputs (index map, boundary set, per-tile sorted lists) must be
 bit-exact; images within 1e-4 max abs per channel; gradients within 1e-3 of
-each tensor's largest reference entry.
+each tensor's largest reference entry and, per element, within 1e-3 of the
+entry itself (entries below 1/20 of the largest: of that floor).
 """
 import numpy as np
 import pytest
@@ -130,10 +131,7 @@ def test_gradient_parity(name):
     gi = G.l1_cotangent(img_ref, S.l1_target(cams.num_pixels))
     g = G.run_gpu(sc, cams, tile=16, grad_images=gi)
     ref = oracle.grad_views(frames, gi)
-    for k in ref:
-        e = G.grad_error(g["grads"][k], ref[k])
-        G.log(f"    {k}: max err / max|ref| = {e:.3e}  (max|ref| {np.abs(ref[k]).max():.3e})")
-        assert e <= GRAD_TOL, k
+    G.check_grads(g["grads"], ref, GRAD_TOL)
 
 
 @pytest.mark.parametrize("W,tile", [(300, 16), (200, 32)])
@@ -153,10 +151,7 @@ def test_boundary_lists_over_the_lds_stage(W, tile):
     G.log(f"    {g['counters'][7]} tiles over the stage; image max abs err {err:.3e}")
     assert err <= IMG_TOL
     ref = oracle.grad_views(frames, gi)
-    for k in ref:
-        e = G.grad_error(g["grads"][k], ref[k])
-        G.log(f"    {k}: {e:.3e}")
-        assert e <= GRAD_TOL, k
+    G.check_grads(g["grads"], ref, GRAD_TOL)
 
 
 @pytest.mark.parametrize("name", ["random64", "sphere_small", "degree3", "random64_r3_sh3"])
@@ -181,12 +176,7 @@ def test_without_coefficients_parity(name):
     assert err <= IMG_TOL
     ref = oracle.grad_views(frames, gi)
     assert not g["grads"]["sharpness"].any()
-    for k in ref:
-        if k == "sharpness":
-            continue
-        e = G.grad_error(g["grads"][k], ref[k])
-        G.log(f"    {k}: {e:.3e}")
-        assert e <= GRAD_TOL, k
+    G.check_grads(g["grads"], ref, GRAD_TOL, skip=("sharpness",))
 
 
 def test_batched_equals_per_view():
