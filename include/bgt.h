@@ -155,8 +155,8 @@ bgt_status bgt_validate_views(const bgt_views *views);
 
 /* Create a context on HIP device `device`; device -1 gives a host-only
  * context that can size and validate but not enqueue work.  A device context
- * allocates its 8-byte overflow word of pinned host memory here (freed by
- * bgt_destroy).  *out is NULL
+ * allocates its 8-byte overflow word of pinned host memory here (the only
+ * allocation the library makes; it is freed by bgt_destroy).  *out is NULL
  * on failure. */
 bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out);
 void bgt_destroy(bgt_ctx *ctx);
@@ -225,6 +225,19 @@ bgt_status bgt_loss_workspace_size(const bgt_views *views, size_t *bytes);
 bgt_status bgt_loss(bgt_ctx *ctx, const bgt_views *views, const float *images, const float *targets,
                     float lambda, float *loss, float *grad_images, void *workspace, size_t workspace_bytes,
                     void *stream);
+
+/* bgt_loss without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a fixed 64 MiB device array inside the
+ * library, one per GPU, held until the process ends; its address is looked up
+ * when a context is created on that GPU.  Views whose
+ * bgt_loss_workspace_size exceeds 64 MiB (about 1.86 M pixels in all) give
+ * BGT_E_NOMEM before any work is enqueued.  The call allocates nothing.
+ * Every call on one GPU shares the array: calls that overlap on a GPU (other
+ * streams, other host threads) race on it; calls in order on one stream do
+ * not.  Results are bit-identical to bgt_loss's. */
+bgt_status bgt_loss_noalloc(bgt_ctx *ctx, const bgt_views *views, const float *images, const float *targets,
+                            float lambda, float *loss, float *grad_images, void *stream);
 
 /* Cotangent of an L1 loss scale * sum |C - target| over n values (images
  * and targets device arrays of n floats): grad = scale * sign(C - target),

@@ -291,6 +291,11 @@ bgt_status loss_table(const bgt_views *vw, float lambda, LossTable &lt, int64_t 
 
 }  // namespace
 
+namespace bgt {
+int ctx_device(const bgt_ctx *ctx) { return ctx->device; }
+bgt_status ctx_fail(bgt_ctx *ctx, bgt_status st, const char *msg) { return fail(ctx, st, msg); }
+}  // namespace bgt
+
 extern "C" {
 
 bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out) {
@@ -316,7 +321,8 @@ bgt_status bgt_create(const bgt_config *cfg, int device, bgt_ctx **out) {
             return BGT_E_HIP;
         }
         *ctx->ovf_host = 0;
-        if (hipHostGetDevicePointer((void **)&ctx->ovf_dev, ctx->ovf_host, 0) != hipSuccess) {
+        if (hipHostGetDevicePointer((void **)&ctx->ovf_dev, ctx->ovf_host, 0) != hipSuccess ||
+            static_scratch_init(device) != hipSuccess) {  // the device address of bgt_loss_noalloc's workspace
             hipHostFree(ctx->ovf_host);
             delete ctx;
             return BGT_E_HIP;

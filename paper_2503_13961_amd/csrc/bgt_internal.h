@@ -255,6 +255,15 @@ hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, 
                       const StatePtrs &st, hipStream_t s);
 hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs &st, hipStream_t s);
 hipError_t launch_note_overflow(const StatePtrs &st, unsigned long long *flag, hipStream_t s);
+
+// context internals for the entry points outside bgt_api.cpp
+int ctx_device(const bgt_ctx *ctx);
+bgt_status ctx_fail(bgt_ctx *ctx, bgt_status st, const char *msg);
+// the static loss workspace of bgt_loss_noalloc (bgt_static.hip): its device
+// address is fetched once per device, with that device current
+hipError_t static_scratch_init(int device);
+size_t static_scratch_bytes();
+void *static_scratch(int device);
 hipError_t launch_blend_fwd(const Consts &k, const ViewTable &vt, const StatePtrs &st, float *image,
                             hipStream_t s);
 hipError_t launch_blend_bwd(const Consts &k, const ViewTable &vt, const StatePtrs &st,

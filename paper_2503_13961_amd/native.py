@@ -22,7 +22,7 @@ STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
            "bgt_state_layout", "bgt_render_fwd", "bgt_render_bwd", "bgt_query", "bgt_profile",
-           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_l1_cotangent",
+           "bgt_stage_times", "bgt_loss_workspace_size", "bgt_loss", "bgt_loss_noalloc", "bgt_l1_cotangent",
            "bgt_adam_step",
            "bgt_default_densify_config", "bgt_stats_accumulate", "bgt_densify_plan", "bgt_densify_apply"]
 BGT_NUM_STAGES = 6
@@ -114,6 +114,7 @@ def lib():
         L.bgt_query.argtypes = [vp, vp, C.c_size_t, i64p, vp]
         L.bgt_loss_workspace_size.argtypes = [C.POINTER(bgt_views), C.POINTER(C.c_size_t)]
         L.bgt_loss.argtypes = [vp, C.POINTER(bgt_views), vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]
+        L.bgt_loss_noalloc.argtypes = [vp, C.POINTER(bgt_views), vp, vp, C.c_float, vp, vp, vp]
         L.bgt_l1_cotangent.argtypes = [vp, C.c_int64, vp, vp, C.c_float, vp, vp]
         L.bgt_adam_step.argtypes = [vp, C.POINTER(bgt_adam_group), C.c_int32, C.c_float, C.c_float, C.c_float,
                                     vp, vp]
@@ -228,6 +229,11 @@ def bgt_loss(ctx, views, images_ptr, targets_ptr, lam, loss_ptr, grad_images_ptr
              stream=0) -> int:
     return _check(ctx, lib().bgt_loss(ctx, C.byref(views), images_ptr, targets_ptr, lam, loss_ptr, grad_images_ptr,
                                       workspace_ptr, workspace_bytes, stream))
+
+
+def bgt_loss_noalloc(ctx, views, images_ptr, targets_ptr, lam, loss_ptr, grad_images_ptr, stream=0) -> int:
+    return _check(ctx, lib().bgt_loss_noalloc(ctx, C.byref(views), images_ptr, targets_ptr, lam, loss_ptr,
+                                              grad_images_ptr, stream))
 
 
 def bgt_l1_cotangent(ctx, n, images_ptr, targets_ptr, scale, grad_ptr, stream=0) -> int:
