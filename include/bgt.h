@@ -196,13 +196,15 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
                           const float *images, const float *grad_images, void *state,
                           size_t state_bytes, const bgt_grads *grads, void *stream);
 
-/* Synchronizes `stream` and reads the state's counters (host out[8]):
+/* Synchronizes `stream` and reads the state's counters (host out[10]):
  * [0] overflow flags (bit0 Gaussian pairs, bit1 boundary pairs, bit2 big
  * triangle queue) of this state's last forward pass together with those of
  * every forward pass on the context not yet reported, [1] Gaussian pairs,
  * [2] boundary pairs, [3] foreground pixels, [4] boundary pixels, [5] big
  * triangles, [6] tiles needing the global sort, [7] tiles whose boundary
- * list exceeded LDS.  Returns BGT_E_OVERFLOW when any overflow flag is set
+ * list exceeded LDS, [8] tiles with more boundary runs (primitives) than
+ * the forward's gamma* maps hold (their other runs are searched per pixel),
+ * [9] reserved (0).  Returns BGT_E_OVERFLOW when any overflow flag is set
  * (and clears the context's record of it). */
 bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_t *counters,
                      void *stream);

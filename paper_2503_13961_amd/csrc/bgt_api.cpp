@@ -700,6 +700,8 @@ bgt_status bgt_query(bgt_ctx *ctx, const void *state, size_t state_bytes, int64_
     counters[5] = c[C_BIGTRI];
     counters[6] = c[C_BIGSORT];
     counters[7] = c[C_BIGBLIST];
+    counters[8] = c[C_MANYRUNS];
+    counters[9] = 0;
     // this state's last pass, and any pass on the context since the last report
     const unsigned long long ov = (unsigned long long)c[C_OVERFLOW] | take_overflow(ctx);
     counters[0] = (int64_t)ov;

@@ -24,16 +24,20 @@ namespace bgt {
 // points staged in LDS.  The budget keeps 5-6 workgroups per CU at 16 px; on
 // the 2000-patch sphere at 16 px a tile has at most 13 runs (mean 4.4) and
 // 157 points (the 20,000-patch box: 24 and 251).  Runs and tiles beyond it
-// take the slower paths, never a wrong one.  The backward also keeps a
-// dl/dgamma* sum per mapped (run, pixel), so it maps fewer runs.
+// take the slower paths, never a wrong one.  A 32 px tile meets about four
+// times the runs; its workgroup of 16 waves is one per CU whatever its LDS
+// (registers bound it), so it maps 24.  The backward keeps a dl/dgamma* sum
+// per (run, pixel) in registers for the first kDgrRuns runs only; a mapped
+// run beyond those sends its boundary terms to the arg-min point at once.
 template <int TS>
 struct RunMapsFwd {
-    static constexpr int value = 12;
+    static constexpr int value = TS >= 32 ? 24 : 12;
 };
 template <int TS>
 struct RunMapsBwd {
-    static constexpr int value = 12;
+    static constexpr int value = TS >= 32 ? 24 : 12;
 };
+constexpr int kDgrRuns = 12;
 template <int TS>
 struct BoundaryCap {
     static constexpr int value = TS >= 32 ? 512 : (TS >= 16 ? 256 : 128);
@@ -573,6 +577,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     }
     stage_boundary(B, st, bs0, bc, ox, oy, vi);
     const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
+    if (B.n_runs > RM && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_MANYRUNS], 1ull);
     build_gamma_maps<TS>(B);
 
     const int gs0 = st.g_start[t], gc = st.g_count[t];
@@ -685,9 +690,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         float bacc[BoundaryCap<TS>::value][3];
     };
     __shared__ TailLds U;
-    float dgr[RM];  // sums of dl/dgamma* per mapped run at this pixel (uniform index: indexed registers)
+    constexpr int RD = kDgrRuns < RM ? kDgrRuns : RM;
+    float dgr[RD];  // sums of dl/dgamma* per tracked run at this pixel (uniform index: indexed registers)
 #pragma unroll
-    for (int i = 0; i < RM; ++i) dgr[i] = 0.f;
+    for (int i = 0; i < RD; ++i) dgr[i] = 0.f;
     __shared__ int max_last;
     BatchLds<TS, K> &S = U.loop.S;
     float *acc = U.loop.acc;
@@ -765,6 +771,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
                 bool live = base + kk < mylast && (own || r != -1) && e >= e_min;
                 const bool mapped = r >= 0 && r < RM;
+                const bool tracked = r >= 0 && r < RD;  // (uniform) dgr holds its dl/dgamma*
                 float gam = 1.0f;
                 int arg = -1;
                 if (mapped) {
@@ -798,7 +805,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 const float gx = dG * dx, gy = dG * dy;
                 if (r != -1) {
                     const float dgm = (smooth && gam < 1.0f) ? (own ? 1.0f : -1.0f) * dalpha * o * Gv : 0.0f;
-                    if (mapped) {
+                    if (mapped && !tracked && __any(dgm != 0.0f)) {  // the arg-min where it is needed
+                        if (dgm != 0.0f) gamma_lds(B, st, bs0, r, lx, ly, &arg);
+                    }
+                    if (tracked) {
                         if (__any(dgm != 0.0f)) dgr[r] += dgm;  // only near the run's boundary points
                     } else if (dgm != 0.0f && arg >= 0) {
                         float ddx, ddy, sg;
@@ -862,11 +872,11 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     float(&bacc)[BoundaryCap<TS>::value][3] = U.bacc;
     for (int i = tid; i < BoundaryCap<TS>::value * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
-    const int nmap = B.n_runs < RM ? B.n_runs : RM;
+    const int nmap = B.n_runs < RD ? B.n_runs : RD;
     for (int r = 0; r < nmap; ++r) {  // not unrolled: one copy of the arg-min search
         float dg = 0.f;               // dgr[r] by selects (r is uniform; dgr stays in registers)
 #pragma unroll
-        for (int i = 0; i < RM; ++i) dg = i == r ? dgr[i] : dg;
+        for (int i = 0; i < RD; ++i) dg = i == r ? dgr[i] : dg;
         if (dg == 0.f) continue;
         int e = -1;
         const float gst = gamma_lds(B, st, bs0, r, lx, ly, &e);

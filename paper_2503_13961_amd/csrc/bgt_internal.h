@@ -27,6 +27,7 @@ enum Counter {
     C_BIGBLIST = 7,
     C_BIGSORT_Q = 8,  // queue length for the global-memory sort (g in low, b via C_BIGSORT_QB)
     C_BIGSORT_QB = 9,
+    C_MANYRUNS = 10,  // tiles with more boundary runs than the forward's gamma* maps
     C_NUM = 16
 };
 // The per-wave foreground and boundary tallies go to kStripes slots 64 bytes

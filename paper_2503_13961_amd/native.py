@@ -209,8 +209,8 @@ def bgt_render_bwd(ctx, prims, views, images_ptr, grad_images_ptr, state_ptr, st
 
 
 def bgt_query(ctx, state_ptr, state_bytes, stream=0):
-    """Returns (status, counters[8]); status may be BGT_E_OVERFLOW."""
-    out = (C.c_int64 * 8)()
+    """Returns (status, counters[10]); status may be BGT_E_OVERFLOW."""
+    out = (C.c_int64 * 10)()
     st = lib().bgt_query(ctx, state_ptr, state_bytes, out, stream)
     if st not in (BGT_OK, BGT_E_OVERFLOW):
         raise BgtError(st, bgt_last_error(ctx))
