@@ -177,11 +177,12 @@ def algorithmic(counters, npx, ntiles, P, ncp):
                 12 B image, 4 B transmittance, 4 B stop index written;
                 per tile 16 B of list ranges.
       backward: the forward's reads again, plus per pixel 12 B image and
-                12 B cotangent read, and per Gaussian pair a 36 B gradient
-                read-modify-write (9 floats), per boundary pair 12 B."""
+                12 B cotangent read, per Gaussian pair its 36 B of sums
+                written (9 floats), per boundary pair a 12 B gradient
+                read-modify-write."""
     gp, bp = counters[1], counters[2]
     fwd = gp * (4 + 48) + bp * (4 + 16) + npx * (4 + 12 + 4 + 4) + ntiles * 16
-    bwd = gp * (4 + 48 + 2 * 36) + bp * (4 + 16 + 2 * 12) + npx * (4 + 4 + 12 + 12) + ntiles * 16
+    bwd = gp * (4 + 48 + 36) + bp * (4 + 16 + 2 * 12) + npx * (4 + 4 + 12 + 12) + ntiles * 16
     return {"blend_fwd": fwd, "blend_bwd": bwd}
 
 
@@ -303,15 +304,16 @@ def path_bytes(counters, npx, ntiles, backward=True):
     must produce or consume counted once per essential read or write: per
     pixel the index map and (u, v) written and read, image, transmittance
     and stop index written, the backward's reads; per foreground pixel its
-    Gaussian written and read back by the parameter pass; per boundary pixel
-    its list entries, record and gradient; per Gaussian-tile pair the key
+    Gaussian written; per boundary pixel its list entries, record and
+    gradient (read back by the parameter pass); per Gaussian-tile pair the key
     emitted, sorted, the value and the record read in the forward and again
-    in the backward with the gradient read-modify-write; per boundary pair
-    the same with its 16-byte record; per tile its list ranges."""
+    in the backward, with its 36 bytes of sums written there and read by the
+    parameter pass; per boundary pair the same with its 16-byte record and a
+    12-byte gradient read-modify-write; per tile its list ranges."""
     gp, bp, fg, nb = counters[1], counters[2], counters[3], counters[4]
     fwd = npx * (12 + 12 + 20) + fg * 44 + nb * (4 + 4 + 16) + gp * (12 + 24 + 4 + 44) + bp * (12 + 24 + 4 + 16) \
         + ntiles * 24
-    bwd = npx * 24 + fg * 48 + nb * 24 + gp * (4 + 44 + 72) + bp * (4 + 16 + 24)
+    bwd = npx * 24 + nb * (24 + 12) + gp * (4 + 44 + 2 * 36) + bp * (4 + 16 + 24)
     return fwd + (bwd if backward else 0)
 
 

@@ -29,7 +29,8 @@ using namespace bgt;
 
 enum Field {
     F_COUNTERS, F_ZBUF, F_ITRI, F_IUV, F_PFLAGS, F_REC, F_GKEY, F_TFINAL, F_LAST, F_VERTS, F_GCOUNT, F_GSTART,
-    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_DGAUSS, F_BREC64, F_BIGTRI,
+    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_GSUM, F_DBOUND, F_TNLAST,
+    F_GINV, F_BREC64, F_BIGTRI,
     F_SCAN, F_END
 };
 static_assert(F_END + 1 == BGT_STATE_FIELDS, "state field count");
@@ -168,7 +169,10 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_GLIST, 4 * k.cap_g);
     put(F_BKEYS, 8 * k.cap_b);
     put(F_BLIST, 4 * k.cap_b);
-    put(F_DGAUSS, 48 * NR);
+    put(F_GSUM, 4 * kGsumWords * k.cap_g);
+    put(F_DBOUND, 12 * N);
+    put(F_TNLAST, 4 * NT);
+    put(F_GINV, 16 * NR);
     put(F_BREC64, 24 * N);
     put(F_BIGTRI, 4 * k.cap_big);
     {
@@ -205,7 +209,10 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.g_list = (uint32_t *)(b + sh.off[F_GLIST]);
     p.b_keys = (unsigned long long *)(b + sh.off[F_BKEYS]);
     p.b_list = (uint32_t *)(b + sh.off[F_BLIST]);
-    p.dgauss = (float *)(b + sh.off[F_DGAUSS]);
+    p.gsum = (float *)(b + sh.off[F_GSUM]);
+    p.dbound = (float *)(b + sh.off[F_DBOUND]);
+    p.t_nlast = (int32_t *)(b + sh.off[F_TNLAST]);
+    p.ginv = (int32_t *)(b + sh.off[F_GINV]);
     p.brec64 = (double *)(b + sh.off[F_BREC64]);
     p.big_tris = (int32_t *)(b + sh.off[F_BIGTRI]);
     p.scan_tmp = (int32_t *)(b + sh.off[F_SCAN]);
@@ -494,7 +501,7 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         (e = launch_fill_f32(gp.quat, 0.f, 4LL * k.T * k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.opacity, 0.f, k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(sp.dgauss, 0.f, 12 * sh.NR, st)) != hipSuccess)
+        (e = launch_fill_f32(sp.dbound, 0.f, 3 * sh.N, st)) != hipSuccess)
         return hip_fail(ctx, e, "fill");
     {
         StageTimer tm(ctx, 4, st);

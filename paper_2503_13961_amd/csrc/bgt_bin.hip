@@ -272,15 +272,20 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
         }
         return;
     }
-    const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
+    unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
     const int v = view_of_tile(vt, t);
     uint32_t *dst = which == 0 ? st.g_list : st.b_list;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the keys go back sorted too: the parameter pass finds a record's list
+    // positions in them by bisection
     if (cnt <= 64) {
         // short lists (most boundary lists, border tiles): one wave, one key per lane
         if (wave != 0) return;
         const unsigned long long x = wave_sort64(lane < cnt ? src[start + lane] : ~0ull, lane);
-        if (lane < cnt) dst[start + lane] = (uint32_t)record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
+        if (lane < cnt) {
+            src[start + lane] = x;
+            dst[start + lane] = (uint32_t)record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
+        }
         return;
     }
     // Runs of 64 keys sorted in registers, one wave per run (padded with
@@ -319,8 +324,10 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
             if (pos[q] >= 0) keys[pos[q]] = x[q];
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        src[start + i] = keys[i];
         dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+    }
 }
 
 // Segments longer than the LDS buffer: same network on global memory, one

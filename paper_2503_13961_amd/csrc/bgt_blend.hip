@@ -666,12 +666,11 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 //   dl/dc_i = T_i a_i dl/dC,  dl/da_i = dl/dC . (T_i c_i - S_i / (1 - a_i)),
 //   dl/dw = dl/da a / w (Supplementary Sec. C), G = exp(-d^T Q d / 2).
 // Per Gaussian the 9 gradient values are summed over each row with DPP and
-// over rows and waves in LDS, then added to global memory once per tile.  The
-// boundary terms accumulate per (run, pixel) and go to the minimising
+// over rows and waves in LDS, then stored once per tile at the entry's list
+// position (plain stores: the parameter pass sums a record's positions over
+// its tiles in a fixed order, so the result does not depend on scheduling).
+// The boundary terms accumulate per (run, pixel) and go to the minimising
 // boundary point at the end of the tile.
-// (the waves-per-EU hint keeps the register count at 96, five waves per
-// SIMD, without spills: the FP64 arg-min decision of the rare in-loop path
-// would otherwise push it to 104 and four waves)
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
@@ -699,7 +698,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     float *acc = U.loop.acc;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gc = st.g_count[t];
-    if (gc == 0) return;  // no Gaussian reaches the tile: nothing to differentiate
+    if (gc == 0) {  // no Gaussian reaches the tile: nothing to differentiate
+        if (tid == 0) st.t_nlast[t] = 0;
+        return;
+    }
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
     const int tl = t - vi.tile_off, tx = tl % vi.tiles_x, ty = tl / vi.tiles_x;
@@ -721,6 +723,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int ox = tx * TS, oy = ty * TS;
     const float qx = (float)(lx & 7), qy = (float)(ly & 7);
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
+    const int jpar = __builtin_amdgcn_readfirstlane((ty & 1) * 2 + (tx & 1));
 
     if (tid == 0) max_last = 0;
     for (int i = tid; i < K * 9; i += blockDim.x) acc[i] = 0.f;
@@ -738,6 +741,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 
     const int gs0 = st.g_start[t];
     const int nlast = max_last;
+    if (tid == 0) st.t_nlast[t] = nlast;  // the prefix of the list whose sums are written below
     // R = C - prefix: the colour still to come after the current entry
     float T = 1.0f, P0 = im0, P1 = im1, P2 = im2;
     const float amax = k.alpha_max;
@@ -828,12 +832,12 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                         const float d = bdist(ddx, ddy);
                         const float gb = gamma_fn(d, sg);  // gamma of the routed point
                         const float dd = dgm * LN2 / sg * gb;
-                        float *dst = st.dgauss + (int64_t)bpix * 12;
+                        float *dst = st.dbound + (int64_t)bpix * 3;
                         if (d > kDKink) {
-                            unsafeAtomicAdd(&dst[10], -dd * ddx / d);
-                            unsafeAtomicAdd(&dst[11], -dd * ddy / d);
+                            unsafeAtomicAdd(&dst[1], -dd * ddx / d);
+                            unsafeAtomicAdd(&dst[2], -dd * ddy / d);
                         }
-                        unsafeAtomicAdd(&dst[9], -dgm * LN2 * d / (sg * sg) * gb);
+                        unsafeAtomicAdd(&dst[0], -dgm * LN2 * d / (sg * sg) * gb);
                     }
                 }
                 // wave totals, scattered over the lanes of row 0 with bit 2 set,
@@ -851,16 +855,21 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();
-        if (tid < K && cur_gp >= 0) {  // each loader flushes its own slot, then stages the next batch
+        if (tid < K && cur_gp >= 0) {  // each loader stores its own slot's sums, then stages the next batch
+            const int p = gs0 + base + tid;
+            float2 *dst = (float2 *)(st.gsum + (int64_t)p * kGsumWords);
+            const float *a = acc + tid * 9;
+            dst[0] = make_float2(a[0], a[1]);
+            dst[1] = make_float2(a[2], a[3]);
+            dst[2] = make_float2(a[4], a[5]);
+            dst[3] = make_float2(a[6], a[7]);
+            dst[4] = make_float2(a[8], __int_as_float(cur_gp));  // with the entry's record
 #pragma unroll
-            for (int f = 0; f < 9; ++f) {
-                float *a = acc + tid * 9 + f;
-                const float val = a[0];
-                if (val != 0.f) {
-                    unsafeAtomicAdd(&st.dgauss[(int64_t)cur_gp * 12 + f], val);
-                    a[0] = 0.f;
-                }
-            }
+            for (int f = 0; f < 9; ++f) acc[tid * 9 + f] = 0.f;
+            // the position, under the tile's parity, for the parameter
+            // pass's lookup (unique within a range of at most 2 x 2 tiles;
+            // records reaching more tiles are found by bisection)
+            st.ginv[(int64_t)cur_gp * 4 + jpar] = p;
         }
         if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
     }
@@ -896,10 +905,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     for (int e = tid; e < B.nbl; e += blockDim.x) {
         const float a0 = bacc[e][0], a1 = bacc[e][1], a2 = bacc[e][2];
         if (a0 == 0.f && a1 == 0.f && a2 == 0.f) continue;
-        float *dst = st.dgauss + (int64_t)st.b_list[bs0 + e] * 12;
-        if (a0 != 0.f) unsafeAtomicAdd(&dst[10], a0);
-        if (a1 != 0.f) unsafeAtomicAdd(&dst[11], a1);
-        if (a2 != 0.f) unsafeAtomicAdd(&dst[9], a2);
+        float *dst = st.dbound + (int64_t)st.b_list[bs0 + e] * 3;
+        if (a0 != 0.f) unsafeAtomicAdd(&dst[1], a0);
+        if (a1 != 0.f) unsafeAtomicAdd(&dst[2], a1);
+        if (a2 != 0.f) unsafeAtomicAdd(&dst[0], a2);
     }
 }
 

@@ -169,6 +169,10 @@ struct VertRec {
 // A pixel's record is at its own pixel; a lattice Gaussian's at the pixel
 // (floor(mu_x), floor(mu_y)), clamped to +-30000.  The depth is kept in
 // the sort key array (gkey) only.
+// words per Gaussian-list entry of the backward's sums: the 9 sums of
+// k_blend_bwd, then the entry's record index (int bits)
+constexpr int kGsumWords = 10;
+
 struct StatePtrs {
     int64_t *counters;
     unsigned long long *zbuf;
@@ -186,7 +190,10 @@ struct StatePtrs {
     int32_t *b_count, *b_start, *b_cursor;
     unsigned long long *g_keys, *b_keys;
     uint32_t *g_list, *b_list;
-    float *dgauss;         // [records][12]
+    float *gsum;           // [cap_g][kGsumWords] blend-pass sums of each Gaussian-list entry and its record
+    float *dbound;         // [pixels][3] dl/dsigma_b, dl/dmu (x, y) of each boundary point
+    int32_t *t_nlast;      // [tiles] entries of the tile's list whose gsum the backward wrote
+    int32_t *ginv;         // [records][4] gsum position of the record in the tile of each parity (tx & 1, ty & 1)
     double *brec64;        // [pixels][3] boundary points in FP64: mu - pixel centre (x, y), sigma
     int32_t *big_tris;     // [cap_big] queue of raster items
     int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
