@@ -15,6 +15,8 @@
 // and each row walks its own mask, so the four rows of a wave composite four
 // (possibly different) Gaussians per step; a Gaussian that misses a
 // sub-block costs that sub-block nothing.
+#include <type_traits>
+
 #include "bgt_internal.h"
 #include "bgt_wave.h"
 
@@ -72,26 +74,30 @@ struct BoundaryLds {
     static constexpr int NMAP = RM;
     float bdx[CAP], bdy[CAP], bs[CAP];
     int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
-    int brun[CAP];
+    uint8_t brun[CAP];  // each point's run, 255 for runs from 255 on (only runs below NMAP are mapped)
     int run_prim[CAP], run_start[CAP + 1];
-    int wsum[33];
     int n_runs, nbl, max_rows;
     union {
-        int bp[CAP];                // each point's primitive, while the runs are found
+        struct {
+            int bp[CAP];            // each point's primitive, while the runs are found
+            int wsum[33];           // and the scans' wave sums
+        };
         unsigned map[RM][TS * TS];  // then gamma* bits per (run, pixel in thread order)
     };
-    static_assert(RM * TS * TS >= CAP, "the maps hold the staging ids");
+    static_assert(RM * TS * TS >= CAP + 33, "the maps hold the staging ids");
+    static_assert(RM < 255, "run indices of mapped runs fit brun");
 };
 
 // A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
 // the Gaussian's own pixel, w0 the origin of the wave's 8x8 block and delta
 // the mean's offset from g's centre: one rounding that does not depend on
 // the tile size.
-template <int TS, int K>
+// BOUND: the forward's layout, whose colour carries the sub-block bound
+template <int TS, int K, bool BOUND>
 struct BatchLds {
     float2 m[TS * TS / 64][K];  // per-wave mean offsets
     float4 e[K];                // conic in exponent form kE (a, 2b, c), opacity
-    float4 c[K];                // colour; w: exponent below which no pixel of a 4x4 sub-block is in the support
+    float4 c[K];                // colour; w (forward): exponent below which no pixel of a 4x4 sub-block is in the support
     int2 pr[K];                 // primitive id, run index
     int xr[K], yr[K];
 };
@@ -171,7 +177,7 @@ __device__ __forceinline__ void stage_boundary(BL &B, const StatePtrs &st, int b
         const int ex = block_scan_excl(f, tot, B.wsum);
         if (e < nbl) {
             if (f) { B.run_prim[nr0 + ex] = B.bp[e]; B.run_start[nr0 + ex] = e; }
-            B.brun[e] = nr0 + ex + f - 1;
+            B.brun[e] = (uint8_t)min(nr0 + ex + f - 1, 255);
         }
         __syncthreads();
         if (threadIdx.x == 0) B.n_runs = nr0 + tot;
@@ -421,7 +427,7 @@ __device__ __forceinline__ float sub_block_bound(float qa, float qb, float qc, f
 
 // BOUND: also store the sub-block bound (the forward's row masks use it)
 template <int TS, int K, bool BOUND>
-__device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetch &P, int kk, int ox, int oy,
+__device__ __forceinline__ void stage_slot(BatchLds<TS, K, BOUND> &S, const SlotPrefetch &P, int kk, int ox, int oy,
                                            const int *run_prim, int n_runs, bool slow_b, float kappa) {
     using G = TileGeom<TS>;
     // tile-relative pixel the Gaussian's mean is stored against
@@ -443,6 +449,16 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K> &S, const SlotPrefetc
     S.yr[kk] = __float_as_int(P.r3.y);
 }
 
+// the backward's staging of slot kk from record gp, read at once
+template <int TS, int K>
+__device__ __forceinline__ void load_stage(BatchLds<TS, K, false> &S, const StatePtrs &st, int gp, int kk, int ox, int oy,
+                                           const int *run_prim, int n_runs, bool slow_b) {
+    SlotPrefetch P;
+    const float4 *rp = st.rec + (int64_t)gp * 4;
+    P.r0 = rp[0]; P.r1 = rp[1]; P.r2 = rp[2]; P.r3 = rp[3];
+    stage_slot<TS, K, false>(S, P, kk, ox, oy, run_prim, n_runs, slow_b, 0.f);
+}
+
 // does the pixel range (packed int16 pairs) touch the 4x4 sub-block at (x0, y0)?
 __device__ __forceinline__ bool touches4(int xr, int yr, int x0, int y0) {
     return !(hi16(xr) < x0 || lo16(xr) > x0 + 3 || hi16(yr) < y0 || lo16(yr) > y0 + 3);
@@ -454,7 +470,7 @@ __device__ __forceinline__ bool touches4(int xr, int yr, int x0, int y0) {
 // sub-block's centre is within the conic bound of sub_block_bound (an entry
 // left out has no live pixel there, so the result does not change).
 template <int TS, int K>
-__device__ __forceinline__ void sub_block_masks(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
+__device__ __forceinline__ void sub_block_masks(const BatchLds<TS, K, true> &S, int wave, int c0, int n, int lane,
                                                 int wx0, int wy0, unsigned long long (&mb)[4]) {
     const int j = c0 + lane, jj = j < K ? j : K - 1;
     const bool in = j < n;
@@ -475,7 +491,7 @@ __device__ __forceinline__ void sub_block_masks(const BatchLds<TS, K> &S, int wa
 
 // ... this lane's row's mask (the forward's rows walk their own sub-block)
 template <int TS, int K>
-__device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K> &S, int wave, int c0, int n, int lane,
+__device__ __forceinline__ unsigned long long row_mask(const BatchLds<TS, K, true> &S, int wave, int c0, int n, int lane,
                                                        int wx0, int wy0) {
     unsigned long long mb[4];
     sub_block_masks<TS, K>(S, wave, c0, n, lane, wx0, wy0, mb);
@@ -542,7 +558,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     using BL = BoundaryLds<TS, RunMapsFwd<TS>::value>;
     constexpr int RM = BL::NMAP;
     __shared__ BL B;
-    __shared__ BatchLds<TS, K> S;
+    __shared__ BatchLds<TS, K, true> S;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int v = view_of_tile(vt, t);
     const ViewInfo vi = vt.v[v];
@@ -681,7 +697,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     // the batch stage and its gradient sums are dead once the list is done;
     // the per-point boundary sums reuse their space
     struct LoopLds {
-        BatchLds<TS, K> S;
+        BatchLds<TS, K, false> S;
         float acc[K * 9];  // gradient sums of the staged entries
     };
     union TailLds {
@@ -694,7 +710,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 #pragma unroll
     for (int i = 0; i < RD; ++i) dgr[i] = 0.f;
     __shared__ int max_last;
-    BatchLds<TS, K> &S = U.loop.S;
+    BatchLds<TS, K, false> &S = U.loop.S;
     float *acc = U.loop.acc;
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gc = st.g_count[t];
@@ -748,14 +764,12 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
     const float e_min = kE * k.kappa2;
     const float LN2 = 0.69314718055994531f;
-    SlotPrefetch pf;
-    pf.gp_next = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
-    pf.issue(st, gs0, nlast, 0, tid, K);
-    if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
+    // the loaders read their records at the end of the previous batch, not
+    // ahead of it: registers held across the replay would cost a wave per SIMD
+    int cur_gp = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
+    if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
-        const int cur_gp = pf.gp;
-        pf.issue(st, gs0, nlast, base + K, tid, K);  // next batch's records, in flight during the replay
         const int nkw = min(min(K, nlast - base), wave_last - base);  // entries this wave replays
         for (int c0 = 0; c0 < nkw; c0 += 64) {
             const int j = c0 + lane, jj = j < K ? j : K - 1;
@@ -871,7 +885,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             // records reaching more tiles are found by bisection)
             st.ginv[(int64_t)cur_gp * 4 + jpar] = p;
         }
-        if (pf.gp >= 0) stage_slot<TS, K, false>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, 0.f);
+        cur_gp = (tid < K && base + K + tid < nlast) ? (int)st.g_list[gs0 + base + K + tid] : -1;
+        if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (gamma_lds: the smallest
