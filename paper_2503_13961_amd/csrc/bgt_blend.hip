@@ -678,7 +678,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 
 // Front-to-back replay of the forward per pixel: T_i is recomputed exactly as
 // the forward did, the suffix S_i = sum_{j>i} T_j a_j c_j + T_n bg is the
-// forward colour minus the running prefix, and
+// forward colour minus the running prefix (carried as its dot product with
+// dl/dC), and
 //   dl/dc_i = T_i a_i dl/dC,  dl/da_i = dl/dC . (T_i c_i - S_i / (1 - a_i)),
 //   dl/dw = dl/da a / w (Supplementary Sec. C), G = exp(-d^T Q d / 2).
 // Per Gaussian the 9 gradient values are summed over each row with DPP and
@@ -758,8 +759,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int gs0 = st.g_start[t];
     const int nlast = max_last;
     if (tid == 0) st.t_nlast[t] = nlast;  // the prefix of the list whose sums are written below
-    // R = C - prefix: the colour still to come after the current entry
-    float T = 1.0f, P0 = im0, P1 = im1, P2 = im2;
+    // dl/dC . S: the suffix colour S = C - prefix enters dl/dalpha only through
+    // its dot product with dl/dC, so that product is carried instead of S
+    float T = 1.0f, GS = g0 * im0 + g1 * im1 + g2 * im2;
     const float amax = k.alpha_max;
     const bool nob = (k.flags & BGT_FLAG_NO_BOUNDARY) != 0;
     const float e_min = kE * k.kappa2;
@@ -810,9 +812,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 a = live ? a : 0.0f;
                 const float ta = T * a;
                 const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
-                P0 -= ta * c.x; P1 -= ta * c.y; P2 -= ta * c.z;
+                const float gc = g0 * c.x + g1 * c.y + g2 * c.z;  // dl/dC . c_i
+                GS -= ta * gc;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-                const float dalpha = g0 * (T * c.x - P0 * inv) + g1 * (T * c.y - P1 * inv) + g2 * (T * c.z - P2 * inv);
+                const float dalpha = T * gc - GS * inv;
                 T = T * (1.0f - a);
                 const bool smooth = live && !clamped;
                 const float d_o = smooth ? dalpha * w * Gv : 0.0f;
