@@ -172,7 +172,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_GSUM, 4 * kGsumWords * k.cap_g);
     put(F_DBOUND, 12 * N);
     put(F_TNLAST, 4 * NT);
-    put(F_GINV, 16 * NR);
+    put(F_GINV, 4 * kInvSlots * NR);
     put(F_BREC64, 24 * N);
     put(F_BIGTRI, 4 * k.cap_big);
     {
@@ -500,8 +500,7 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
         (e = launch_fill_f32(gp.log_scale, 0.f, 3LL * k.T * k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.quat, 0.f, 4LL * k.T * k.P, st)) != hipSuccess ||
         (e = launch_fill_f32(gp.opacity, 0.f, k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(sp.dbound, 0.f, 3 * sh.N, st)) != hipSuccess)
+        (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess)
         return hip_fail(ctx, e, "fill");
     {
         StageTimer tm(ctx, 4, st);

@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int ox = tx * TS, oy = ty * TS;
     const float qx = (float)(lx & 7), qy = (float)(ly & 7);
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
-    const int jpar = __builtin_amdgcn_readfirstlane((ty & 1) * 2 + (tx & 1));
+    const int jslot = __builtin_amdgcn_readfirstlane(ty % 3 * 3 + tx % 3);  // the tile's ginv slot
 
     if (tid == 0) max_last = 0;
     for (int i = tid; i < K * 9; i += blockDim.x) acc[i] = 0.f;
@@ -883,10 +883,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             dst[4] = make_float2(a[8], __int_as_float(cur_gp));  // with the entry's record
 #pragma unroll
             for (int f = 0; f < 9; ++f) acc[tid * 9 + f] = 0.f;
-            // the position, under the tile's parity, for the parameter
-            // pass's lookup (unique within a range of at most 2 x 2 tiles;
-            // records reaching more tiles are found by bisection)
-            st.ginv[(int64_t)cur_gp * 4 + jpar] = p;
+            // the position, under the tile's coordinates modulo 3, for the
+            // parameter pass's lookup (unique within a range of at most
+            // 3 x 3 tiles; records reaching more tiles are found by bisection)
+            st.ginv[(int64_t)cur_gp * kInvSlots + jslot] = p;
         }
         cur_gp = (tid < K && base + K + tid < nlast) ? (int)st.g_list[gs0 + base + K + tid] : -1;
         if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);

@@ -690,6 +690,10 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                     b64[0] = mux - (x + 0.5);
                     b64[1] = muy - (y + 0.5);
                     b64[2] = sg;
+                    // the point's gradient accumulator starts at zero (the
+                    // parameter pass clears it again after reading it)
+                    float *db = st.dbound + (int64_t)pix * 3;
+                    db[0] = 0.f; db[1] = 0.f; db[2] = 0.f;
                     centre_range(mux, sg, vi.W, bi0, bi1);
                     centre_range(muy, sg, vi.H, bj0, bj1);
                     flags |= PF_BOUNDARY;

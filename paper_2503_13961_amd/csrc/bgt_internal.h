@@ -172,6 +172,8 @@ struct VertRec {
 // words per Gaussian-list entry of the backward's sums: the 9 sums of
 // k_blend_bwd, then the entry's record index (int bits)
 constexpr int kGsumWords = 10;
+// slots per record of the backward's list positions: tiles (tx mod 3, ty mod 3)
+constexpr int kInvSlots = 9;
 
 struct StatePtrs {
     int64_t *counters;
@@ -191,9 +193,11 @@ struct StatePtrs {
     unsigned long long *g_keys, *b_keys;
     uint32_t *g_list, *b_list;
     float *gsum;           // [cap_g][kGsumWords] blend-pass sums of each Gaussian-list entry and its record
-    float *dbound;         // [pixels][3] dl/dsigma_b, dl/dmu (x, y) of each boundary point
+    float *dbound;         // [pixels][3] dl/dsigma_b, dl/dmu (x, y) of each boundary point (zeroed by the
+                           // generation, accumulated by the backward, read and zeroed by the parameter pass)
     int32_t *t_nlast;      // [tiles] entries of the tile's list whose gsum the backward wrote
-    int32_t *ginv;         // [records][4] gsum position of the record in the tile of each parity (tx & 1, ty & 1)
+    int32_t *ginv;         // [records][kInvSlots] gsum position of the record in the tile (tx, ty) of its range
+                           // at slot (ty mod 3) 3 + tx mod 3
     double *brec64;        // [pixels][3] boundary points in FP64: mu - pixel centre (x, y), sigma
     int32_t *big_tris;     // [cap_big] queue of raster items
     int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory

@@ -109,11 +109,11 @@ __device__ __forceinline__ int region_view(const ViewTable &vt, int reg, int &rx
 // tiles are taken in raster order, so the sum does not depend on scheduling.
 // Only positions in the tile's replayed prefix (t_nlast) were written: the
 // others were reached by no pixel and hold nothing.  A record reaching at
-// most 2 x 2 tiles has its positions in ginv, one per tile parity, written
-// by the backward with the sums: one that lies in the replayed prefix and
-// holds the record is this pass's (had the pass not replayed the record in
-// that tile, the record would sit in the tile's list past the prefix).
-// Other records are found by bisection on their key.
+// most 3 x 3 tiles has its positions in ginv, one per tile at the slot of its
+// coordinates modulo 3, written by the backward with the sums: one that lies
+// in the replayed prefix and holds the record is this pass's (had the pass
+// not replayed the record in that tile, the record would sit in the tile's
+// list past the prefix).  Other records are found by bisection on their key.
 __device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, const StatePtrs &st, int rid, int lr,
                                            float *g) {
     // (the positions are loaded with the range, and the position's sums and
@@ -121,21 +121,23 @@ __device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, 
     // that, and used only once it lies in the tile's prefix, where the record
     // word was written by this pass)
     const float4 r3 = st.rec[(int64_t)rid * 4 + 3];
-    const int4 pos = *(const int4 *)(st.ginv + (int64_t)rid * 4);
     const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
     if (!(lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy))) return;
     const int TSH = __builtin_ctz(k.tile);
     const int gt0 = lo16(gx) >> TSH, gu0 = lo16(gy) >> TSH;
     const int nx = (hi16(gx) >> TSH) - gt0 + 1, ny = (hi16(gy) >> TSH) - gu0 + 1;
-    if (nx <= 2 && ny <= 2) {
+    if (nx <= 3 && ny <= 3) {
         const int pmax = (int)min(k.cap_g, (int64_t)INT32_MAX) - 1;
+        const int *pos = st.ginv + (int64_t)rid * kInvSlots;
+        const int mx = gt0 % 3, my = gu0 % 3;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // (row, column) of the 2 x 2 range
-            const int tx = gt0 + (j & 1), ty = gu0 + (j >> 1);
-            if ((j & 1) >= nx || (j >> 1) >= ny) continue;
+        for (int j = 0; j < 9; ++j) {  // (row, column) of the 3 x 3 range
+            const int jx = j % 3, jy = j / 3;
+            if (jx >= nx || jy >= ny) continue;
+            const int tx = gt0 + jx, ty = gu0 + jy;
             const int t = vi.tile_off + ty * vi.tiles_x + tx;
-            const int par = (ty & 1) * 2 + (tx & 1);
-            const int p = par == 0 ? pos.x : par == 1 ? pos.y : par == 2 ? pos.z : pos.w;
+            const int sx = mx + jx >= 3 ? mx + jx - 3 : mx + jx, sy = my + jy >= 3 ? my + jy - 3 : my + jy;
+            const int p = pos[sy * 3 + sx];
             const int pc = min(max(p, 0), pmax);
             const float2 *qp = (const float2 *)(st.gsum + (int64_t)pc * kGsumWords);
             const float2 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3], q4 = qp[4];
@@ -256,9 +258,10 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             // record of the lattice variant has none), boundary radius and
             // position (a boundary point's)
             if (LAT || k.NL == 0) gauss_sums(k, vt.v[v0], st, pix, lr, g);
-            if (!LAT && (fl & PF_BOUNDARY)) {
-                const float *bp = st.dbound + (int64_t)pix * 3;
+            if (!LAT && (fl & PF_BOUNDARY)) {  // read and cleared for the next backward pass
+                float *bp = st.dbound + (int64_t)pix * 3;
                 g[9] = bp[0]; g[10] = bp[1]; g[11] = bp[2];
+                bp[0] = 0.f; bp[1] = 0.f; bp[2] = 0.f;
             }
             bool nz = false;
 #pragma unroll
