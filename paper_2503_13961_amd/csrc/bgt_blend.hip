@@ -75,7 +75,8 @@ struct BoundaryLds {
     float bdx[CAP], bdy[CAP], bs[CAP];
     int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
     uint8_t brun[CAP];  // each point's run, 255 for runs from 255 on (only runs below NMAP are mapped)
-    int run_prim[CAP], run_start[CAP + 1];
+    int run_prim[CAP];
+    uint16_t run_start[CAP + 1];  // first point of each run (CAP fits 16 bits)
     int n_runs, nbl, max_rows;
     union {
         struct {
@@ -86,6 +87,7 @@ struct BoundaryLds {
     };
     static_assert(RM * TS * TS >= CAP + 33, "the maps hold the staging ids");
     static_assert(RM < 255, "run indices of mapped runs fit brun");
+    static_assert(CAP < 65536, "point indices fit run_start");
 };
 
 // A staged Gaussian's mean is kept per wave as (g - w0) + delta, where g is
@@ -176,14 +178,14 @@ __device__ __forceinline__ void stage_boundary(BL &B, const StatePtrs &st, int b
         const int nr0 = B.n_runs;
         const int ex = block_scan_excl(f, tot, B.wsum);
         if (e < nbl) {
-            if (f) { B.run_prim[nr0 + ex] = B.bp[e]; B.run_start[nr0 + ex] = e; }
+            if (f) { B.run_prim[nr0 + ex] = B.bp[e]; B.run_start[nr0 + ex] = (uint16_t)e; }
             B.brun[e] = (uint8_t)min(nr0 + ex + f - 1, 255);
         }
         __syncthreads();
         if (threadIdx.x == 0) B.n_runs = nr0 + tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) { B.run_start[B.n_runs] = nbl; B.nbl = nbl; }
+    if (threadIdx.x == 0) { B.run_start[B.n_runs] = (uint16_t)nbl; B.nbl = nbl; }
     __syncthreads();
 }
 
@@ -697,9 +699,13 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     __shared__ BL B;
     // the batch stage and its gradient sums are dead once the list is done;
     // the per-point boundary sums reuse their space
+    // a 8x8 tile is one wave, whose totals are the tile's: they go straight
+    // to global memory, and the workgroup needs no LDS sums (its smaller
+    // footprint lets more workgroups share a CU)
+    constexpr bool ONE = TS == 8;
     struct LoopLds {
         BatchLds<TS, K, false> S;
-        float acc[K * 9];  // gradient sums of the staged entries
+        float acc[ONE ? 1 : K * 9];  // gradient sums of the staged entries
     };
     union TailLds {
         LoopLds loop;
@@ -743,7 +749,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int jslot = __builtin_amdgcn_readfirstlane(ty % 3 * 3 + tx % 3);  // the tile's ginv slot
 
     if (tid == 0) max_last = 0;
-    for (int i = tid; i < K * 9; i += blockDim.x) acc[i] = 0.f;
+    if (!ONE)
+        for (int i = tid; i < K * 9; i += blockDim.x) acc[i] = 0.f;
     __syncthreads();
     atomicMax(&max_last, mylast);
     int wave_last = mylast;  // last list entry any lane of this wave replays
@@ -772,6 +779,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
+        unsigned long long stored = 0ull;  // (one wave) entries whose sums went to memory
         const int nkw = min(min(K, nlast - base), wave_last - base);  // entries this wave replays
         for (int c0 = 0; c0 < nkw; c0 += 64) {
             const int j = c0 + lane, jj = j < K ? j : K - 1;
@@ -864,7 +872,14 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 row_reduce_scatter9(vals, lane);
                 vals[0] = cross_row_sum_bp(vals[0], lane);
                 vals[8] = cross_row_sum_bp(vals[8], lane);
-                if (lane < 16 && (lane & 4)) {
+                if constexpr (ONE) {
+                    if (lane < 16 && (lane & 4)) {
+                        float *dst = st.gsum + (int64_t)(gs0 + base + kk) * kGsumWords;
+                        dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)] = vals[0];
+                        if (lane == 4) dst[8] = vals[8];
+                    }
+                    stored |= 1ull << kk;
+                } else if (lane < 16 && (lane & 4)) {
                     float *dst = acc + kk * 9;
                     atomicAdd(&dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)], vals[0]);
                     if (lane == 4) atomicAdd(&dst[8], vals[8]);
@@ -875,14 +890,24 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         if (tid < K && cur_gp >= 0) {  // each loader stores its own slot's sums, then stages the next batch
             const int p = gs0 + base + tid;
             float2 *dst = (float2 *)(st.gsum + (int64_t)p * kGsumWords);
-            const float *a = acc + tid * 9;
-            dst[0] = make_float2(a[0], a[1]);
-            dst[1] = make_float2(a[2], a[3]);
-            dst[2] = make_float2(a[4], a[5]);
-            dst[3] = make_float2(a[6], a[7]);
-            dst[4] = make_float2(a[8], __int_as_float(cur_gp));  // with the entry's record
+            if constexpr (ONE) {
+                // the entry's record; zero sums for the entries the wave skipped
+                if ((stored >> tid) & 1ull) {
+                    ((int *)dst)[9] = cur_gp;
+                } else {
+                    dst[0] = dst[1] = dst[2] = dst[3] = make_float2(0.f, 0.f);
+                    dst[4] = make_float2(0.f, __int_as_float(cur_gp));
+                }
+            } else {
+                const float *a = acc + tid * 9;
+                dst[0] = make_float2(a[0], a[1]);
+                dst[1] = make_float2(a[2], a[3]);
+                dst[2] = make_float2(a[4], a[5]);
+                dst[3] = make_float2(a[6], a[7]);
+                dst[4] = make_float2(a[8], __int_as_float(cur_gp));  // with the entry's record
 #pragma unroll
-            for (int f = 0; f < 9; ++f) acc[tid * 9 + f] = 0.f;
+                for (int f = 0; f < 9; ++f) acc[tid * 9 + f] = 0.f;
+            }
             // the position, under the tile's coordinates modulo 3, for the
             // parameter pass's lookup (unique within a range of at most
             // 3 x 3 tiles; records reaching more tiles are found by bisection)
