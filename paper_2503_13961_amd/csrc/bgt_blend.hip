@@ -23,26 +23,30 @@
 namespace bgt {
 
 // Runs with an LDS gamma* map per tile (forward, backward) and boundary
-// points staged in LDS.  The budget keeps 5-6 workgroups per CU at 16 px; on
+// points staged in LDS.  The budget keeps 6 workgroups per CU at 16 px; on
 // the 2000-patch sphere at 16 px a tile has at most 13 runs (mean 4.4) and
 // 157 points (the 20,000-patch box: 24 and 251).  Runs and tiles beyond it
 // take the slower paths, never a wrong one.  A 32 px tile meets about four
 // times the runs; its workgroup of 16 waves is one per CU whatever its LDS
-// (registers bound it), so it maps 24.  The backward keeps a dl/dgamma* sum
-// per (run, pixel) in registers for the first kDgrRuns runs only; a mapped
-// run beyond those sends its boundary terms to the arg-min point at once.
-template <int TS>
+// (registers bound it), so it maps 24.  An 8 px workgroup is a single wave
+// whose LDS sets how many waves share a SIMD: with 32-entry batches it stages
+// 88 points and maps 8 runs (about 6 KB, six waves per SIMD), with 64-entry
+// batches 128 points and 12 runs (four), for scenes with more runs per tile.
+// The backward keeps a dl/dgamma* sum per (run, pixel) in registers for the
+// first kDgrRuns runs only; a mapped run beyond those sends its boundary
+// terms to the arg-min point at once.
+template <int TS, int K>
 struct RunMapsFwd {
-    static constexpr int value = TS >= 32 ? 24 : 12;
+    static constexpr int value = TS >= 32 ? 24 : (TS >= 16 || K > 32 ? 12 : 8);
 };
-template <int TS>
+template <int TS, int K>
 struct RunMapsBwd {
-    static constexpr int value = TS >= 32 ? 24 : 12;
+    static constexpr int value = RunMapsFwd<TS, K>::value;
 };
 constexpr int kDgrRuns = 12;
-template <int TS>
+template <int TS, int K>
 struct BoundaryCap {
-    static constexpr int value = TS >= 32 ? 512 : (TS >= 16 ? 256 : 128);
+    static constexpr int value = TS >= 32 ? 512 : (TS >= 16 ? 256 : (K > 32 ? 128 : 88));
 };
 
 // Thread layout: wave w owns the 8x8 block (w % SPR, w / SPR); lane l of it
@@ -68,9 +72,9 @@ struct TileGeom {
 // (bdx, bdy) of its projected position from that pixel's centre; distances
 // to pixel (x, y) are (x - bix) - bdx etc., an exact integer minus one float,
 // so every value depends only on the point and the pixel, never on the tile.
-template <int TS, int RM>
+template <int TS, int K, int RM>
 struct BoundaryLds {
-    static constexpr int CAP = BoundaryCap<TS>::value;
+    static constexpr int CAP = BoundaryCap<TS, K>::value;
     static constexpr int NMAP = RM;
     float bdx[CAP], bdy[CAP], bs[CAP];
     int bxy[CAP];  // tile-relative pixel x | y << 16 (int16 each)
@@ -557,7 +561,7 @@ __device__ __forceinline__ float cross_row_sum_bp(float x, int lane) {
 template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, StatePtrs st, float *image) {
     using G = TileGeom<TS>;
-    using BL = BoundaryLds<TS, RunMapsFwd<TS>::value>;
+    using BL = BoundaryLds<TS, K, RunMapsFwd<TS, K>::value>;
     constexpr int RM = BL::NMAP;
     __shared__ BL B;
     __shared__ BatchLds<TS, K, true> S;
@@ -580,7 +584,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
-    const bool slow_b = bc > BoundaryCap<TS>::value;
+    const bool slow_b = bc > BoundaryCap<TS, K>::value;
     if (slow_b && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_BIGBLIST], 1ull);
     if (st.g_count[t] == 0) {
         // no Gaussian reaches the tile (most of the background): T = 1
@@ -694,7 +698,7 @@ template <int TS, int K>
 __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
     using G = TileGeom<TS>;
-    using BL = BoundaryLds<TS, RunMapsBwd<TS>::value>;
+    using BL = BoundaryLds<TS, K, RunMapsBwd<TS, K>::value>;
     constexpr int RM = BL::NMAP;
     __shared__ BL B;
     // the batch stage and its gradient sums are dead once the list is done;
@@ -709,7 +713,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     };
     union TailLds {
         LoopLds loop;
-        float bacc[BoundaryCap<TS>::value][3];
+        float bacc[BoundaryCap<TS, K>::value][3];
     };
     __shared__ TailLds U;
     constexpr int RD = kDgrRuns < RM ? kDgrRuns : RM;
@@ -759,7 +763,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 
     const int bs0 = st.b_start[t], bc = st.b_count[t];
     stage_boundary(B, st, bs0, bc, ox, oy, vi);  // (syncs)
-    const bool slow_b = bc > BoundaryCap<TS>::value;
+    const bool slow_b = bc > BoundaryCap<TS, K>::value;
     const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     build_gamma_maps<TS>(B);
 
@@ -921,8 +925,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     // d/sigma, near-ties decided in FP64, the lowest raster index among
     // exactly equal ratios).
     __syncthreads();  // the loaders' last flush reads acc, which bacc overlays
-    float(&bacc)[BoundaryCap<TS>::value][3] = U.bacc;
-    for (int i = tid; i < BoundaryCap<TS>::value * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
+    constexpr int BCAP = BoundaryCap<TS, K>::value;
+    float(&bacc)[BCAP][3] = U.bacc;
+    for (int i = tid; i < BCAP * 3; i += blockDim.x) (&bacc[0][0])[i] = 0.f;
     __syncthreads();
     const int nmap = B.n_runs < RD ? B.n_runs : RD;
     for (int r = 0; r < nmap; ++r) {  // not unrolled: one copy of the arg-min search
