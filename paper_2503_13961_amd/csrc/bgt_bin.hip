@@ -117,12 +117,44 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int32_t *gc, int32_t
 
 // ------------------------------------------------------------ scatter
 
+// The pairs of the lanes whose tile rectangle lies within the 3x3 tiles
+// around (cx, cy), the tile of the wave's 8x8 block: one cursor atomic per
+// neighbouring tile for the whole wave, all issued by one instruction (lane
+// j takes tile j), so the wave waits for one round trip; a lane's slot in a
+// tile is the tile's base plus its rank among the lanes there.  The other
+// lanes' rectangles (in = false) are left to the caller.
+template <typename E>
+__device__ __forceinline__ void near_tiles(bool in, int tx0, int tx1, int ty0, int ty1, int cx, int cy,
+                                           const ViewInfo &vi, int32_t *cursor, int lane, E &&emit) {
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long m[9];
+    int cnt = 0, tl = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const int tx = cx + j % 3 - 1, ty = cy + j / 3 - 1;
+        m[j] = __ballot(in && tx >= tx0 && tx <= tx1 && ty >= ty0 && ty <= ty1);
+        if (lane == j) { cnt = __popcll(m[j]); tl = vi.tile_off + ty * vi.tiles_x + tx; }
+    }
+    int base = 0;
+    if (lane < 9 && cnt > 0) base = atomicAdd(&cursor[tl], cnt);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        if (m[j] == 0ull) continue;
+        const int b = __builtin_amdgcn_readlane(base, j);
+        const int t = vi.tile_off + (cy + j / 3 - 1) * vi.tiles_x + cx + j % 3 - 1;
+        if ((m[j] >> lane) & 1ull) emit(t, b + __popcll(m[j] & below));
+    }
+}
+
 __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePtrs st) {
     const int lane = threadIdx.x & 63;
     int v, x, y;
     const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
     const ViewInfo vi = vt.v[v];
     const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
+    // the tile of the wave's block (x - (lane & 7) is its left edge)
+    const int cx = __builtin_amdgcn_readfirstlane((x - (lane & 7)) >> TSH);
+    const int cy = __builtin_amdgcn_readfirstlane((y - (lane >> 3)) >> TSH);
     int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;
     unsigned long long gkey = 0ull, bkey = 0ull;
     if (act) {
@@ -146,9 +178,20 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
             }
         }
     }
-    // one cursor atomic per group of lanes at the same tile; each lane takes
-    // the slot of its rank within the group
+    // rectangles within the 3x3 tiles around the block's tile (nearly all):
+    // one round of cursor atomics per list; the rest one cursor atomic per
+    // group of lanes at the same tile, each lane taking the slot of its rank
+    const bool gnear = gt0 <= gt1 && gu0 <= gu1 && gt0 >= cx - 1 && gt1 <= cx + 1 && gu0 >= cy - 1 && gu1 <= cy + 1;
+    const bool bnear = bt0 <= bt1 && bu0 <= bu1 && bt0 >= cx - 1 && bt1 <= cx + 1 && bu0 >= cy - 1 && bu1 <= cy + 1;
+    near_tiles(gnear, gt0, gt1, gu0, gu1, cx, cy, vi, st.g_cursor, lane, [&](int t, int slot) {
+        if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = gkey;
+    });
+    near_tiles(bnear, bt0, bt1, bu0, bu1, cx, cy, vi, st.b_cursor, lane, [&](int t, int slot) {
+        if (slot < st.b_start[t] + st.b_count[t]) st.b_keys[slot] = bkey;
+    });
     const unsigned long long below = (1ull << lane) - 1ull;
+    if (gnear) { gt0 = 1; gt1 = 0; }
+    if (bnear) { bt0 = 1; bt1 = 0; }
     for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off,
                       [&](int t, unsigned long long gm, bool in, int leader) {
         int base = 0;
