@@ -515,37 +515,51 @@ def main():
         log(f"[bench] per-view: {ms_pv:.3f} ms/step; images equal {same}; grad diff {gdiff:.2e}")
         del pv, gpv
     if not args.no_variants:
+        # each variant with the (tile, batch) the autotuner picks for it (with
+        # --tile given, the main step's)
+        def variant_config(degree, vparams, **config):
+            if args.tile != "auto":
+                return tile, batch, None
+            from paper_2503_13961_amd.autotune import autotune
+            tv = autotune(degree, vparams, camt, wh, cache=False, **config)
+            return tv["tile"], tv["batch"], {k: round(v, 4) for k, v in tv["timings"].items()}
+
         # the ablation variant without blending coefficients (w = 1): same
         # scene and kernels, no boundary points, lists or gamma* maps
         from paper_2503_13961_amd import native as N
-        vs = Step(Renderer(0, tile=tile, batch=batch, flags=N.BGT_FLAG_NO_BOUNDARY), scene.degree, params, camt, wh,
+        vt, vb, vtune = variant_config(scene.degree, params, flags=N.BGT_FLAG_NO_BOUNDARY)
+        vs = Step(Renderer(0, tile=vt, batch=vb, flags=N.BGT_FLAG_NO_BOUNDARY), scene.degree, params, camt, wh,
                   target)
         gv = capture(vs)
         ms_v = time_replays(gv, args.steps, args.warmup)
         out["variants"] = {"no_boundary": {"ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+                                           "tile": vt, "batch": vb, "autotune_ms": vtune,
                                            "what": "w = 1 for every Gaussian (ablation w/o B)"}}
-        log(f"[bench] variant without blending coefficients: {ms_v:.3f} ms/step")
+        log(f"[bench] variant without blending coefficients: {ms_v:.3f} ms/step (tile {vt}, batch {vb})")
         del vs, gv
         # the paper's full model: resolution-3 rotation and scale maps, SH colour of degree 3
-        from paper_2503_13961_amd.render import scene_tensors
         full = S.with_attributes(scene, attr_res=3, sh_degree=3)
-        vs = Step(Renderer(0, tile=tile, batch=batch), full.degree, scene_tensors(full, dev), camt, wh, target)
+        fparams = scene_tensors(full, dev)
+        vt, vb, vtune = variant_config(full.degree, fparams)
+        vs = Step(Renderer(0, tile=vt, batch=vb), full.degree, fparams, camt, wh, target)
         gv = capture(vs)
         ms_v = time_replays(gv, args.steps, args.warmup)
         ast = stage_profile(vs)
         out["variants"]["attr_maps_r3_sh3"] = {
             "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+            "tile": vt, "batch": vb, "autotune_ms": vtune,
             "stage_ms": {k: round(v, 4) for k, v in ast.items()},
             "what": "resolution-3 rotation and scale maps and degree-3 SH colour (the paper's full model)"}
-        log(f"[bench] variant with resolution-3 maps and SH degree 3: {ms_v:.3f} ms/step")
+        log(f"[bench] variant with resolution-3 maps and SH degree 3: {ms_v:.3f} ms/step (tile {vt}, batch {vb})")
         del vs, gv
         # the lattice variant: m = 4 Gaussians per flat sub-triangle edge
         # (91 per patch and view) in place of the per-pixel Gaussians, sized
         # to the lattice spacing; the image of the last replay is checked on
         # sampled pixels of four views
         lat = S.lattice_scaled(scene, m=4, L=4)
-        vs = Step(Renderer(0, tile=tile, batch=batch, lattice=4), lat.degree, scene_tensors(lat, dev), camt, wh,
-                  target)
+        lparams = scene_tensors(lat, dev)
+        vt, vb, vtune = variant_config(lat.degree, lparams, lattice=4)
+        vs = Step(Renderer(0, tile=vt, batch=vb, lattice=4), lat.degree, lparams, camt, wh, target)
         gv = capture(vs)
         ms_v = time_replays(gv, args.steps, args.warmup)
         _, lc = vs.r.query(vs.state)
@@ -556,11 +570,13 @@ def main():
                                 views=range(0, cams.n_views, max(1, cams.n_views // 4)), lattice=4)
         out["variants"]["lattice_m4"] = {
             "ms_per_step": round(ms_v, 4), "value": round(npx / (ms_v * 1e-3) / 1e6, 2),
+            "tile": vt, "batch": vb, "autotune_ms": vtune,
             "gaussians": int(cams.n_views * scene.num_prims * 91), "gauss_pairs": int(lc[1]),
             "image_max_abs_err_sampled": lerr, "stage_ms": {k: round(v, 4) for k, v in lst.items()},
             "what": "4 Gaussians per flat sub-triangle edge (91 per patch and view) instead of one per pixel, "
                     "log-scales set to 0.6 x the lattice spacing"}
-        log(f"[bench] lattice variant: {ms_v:.3f} ms/step, {lc[1]} pairs, sampled image err {lerr}")
+        log(f"[bench] lattice variant: {ms_v:.3f} ms/step (tile {vt}, batch {vb}), {lc[1]} pairs, "
+            f"sampled image err {lerr}")
         del vs, gv
     if not args.no_train_step:
         # one optimisation iteration of Sec. 3.3 on the same views: forward,

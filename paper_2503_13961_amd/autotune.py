@@ -85,6 +85,8 @@ def autotune(degree, params, cams, wh, device=0, candidates=CANDIDATES, reps=5, 
     wh = np.ascontiguousarray(wh, dtype=np.int32).reshape(-1, 2)
     P = int(params["opacity"].shape[0])
     key = shape_key(degree, P, wh, device)
+    if config:  # the renderer's variant (lattice, flags, ...) changes the best choice
+        key += "|" + ",".join(f"{k}={config[k]}" for k in sorted(config))
     path = cache_path or default_cache_path()
     if cache:
         hit = _load(path).get(key)
