@@ -716,7 +716,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
         float bacc[BoundaryCap<TS, K>::value][3];
     };
     __shared__ TailLds U;
-    constexpr int RD = kDgrRuns < RM ? kDgrRuns : RM;
+    // (kept at kDgrRuns even where fewer runs are mapped: below about ten
+    // entries the compiler indexes the array by select chains, not registers)
+    constexpr int RD = kDgrRuns;
     float dgr[RD];  // sums of dl/dgamma* per tracked run at this pixel (uniform index: indexed registers)
 #pragma unroll
     for (int i = 0; i < RD; ++i) dgr[i] = 0.f;
