@@ -179,10 +179,11 @@ bgt_status bgt_state_size(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
  * inspection and tests.  Order: counters, zbuf(u64), I_tri(i32), I_uv(f32x2),
  * pflags(u8), rec(f32x16), gkey(u64), T_final(f32), last(i32), verts,
  * g_count, g_start, g_cursor, b_count, b_start, b_cursor, g_keys(u64),
- * g_list(u32), b_keys(u64), b_list(u32), gsum(f32x10 per Gaussian-list
- * entry), dbound(f32x3 per pixel), t_nlast(i32 per tile), ginv(i32x9 per
- * record), brec64(f64x3), big_tris, scan, end. */
-#define BGT_STATE_FIELDS 28
+ * g_list(u32), b_keys(u64), b_list(u32), gslot(f32x9 per record and tile
+ * slot), gpos(i32 per record and tile slot), t_nlast(i32 per tile),
+ * gwide(f32x9 per record), dbound(f32x3 per pixel), brec64(f64x3), big_tris,
+ * scan, end. */
+#define BGT_STATE_FIELDS 29
 bgt_status bgt_state_layout(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views *views,
                             int64_t *offsets);
 

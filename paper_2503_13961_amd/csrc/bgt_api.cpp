@@ -29,8 +29,8 @@ using namespace bgt;
 
 enum Field {
     F_COUNTERS, F_ZBUF, F_ITRI, F_IUV, F_PFLAGS, F_REC, F_GKEY, F_TFINAL, F_LAST, F_VERTS, F_GCOUNT, F_GSTART,
-    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_GSUM, F_DBOUND, F_TNLAST,
-    F_GINV, F_BREC64, F_BIGTRI,
+    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_GSLOT, F_GPOS, F_TNLAST,
+    F_GWIDE, F_DBOUND, F_BREC64, F_BIGTRI,
     F_SCAN, F_END
 };
 static_assert(F_END + 1 == BGT_STATE_FIELDS, "state field count");
@@ -169,10 +169,11 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_GLIST, 4 * k.cap_g);
     put(F_BKEYS, 8 * k.cap_b);
     put(F_BLIST, 4 * k.cap_b);
-    put(F_GSUM, 4 * kGsumWords * k.cap_g);
-    put(F_DBOUND, 12 * N);
+    put(F_GSLOT, 4 * kSlotTiles * kSums * NR);
+    put(F_GPOS, 4 * kSlotTiles * NR);
     put(F_TNLAST, 4 * NT);
-    put(F_GINV, 4 * kInvSlots * NR);
+    put(F_GWIDE, 4 * kSums * NR);
+    put(F_DBOUND, 12 * N);
     put(F_BREC64, 24 * N);
     put(F_BIGTRI, 4 * k.cap_big);
     {
@@ -209,10 +210,12 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.g_list = (uint32_t *)(b + sh.off[F_GLIST]);
     p.b_keys = (unsigned long long *)(b + sh.off[F_BKEYS]);
     p.b_list = (uint32_t *)(b + sh.off[F_BLIST]);
-    p.gsum = (float *)(b + sh.off[F_GSUM]);
-    p.dbound = (float *)(b + sh.off[F_DBOUND]);
+    p.n_rec = sh.NR;
+    p.gslot = (float *)(b + sh.off[F_GSLOT]);
+    p.gpos = (int32_t *)(b + sh.off[F_GPOS]);
     p.t_nlast = (int32_t *)(b + sh.off[F_TNLAST]);
-    p.ginv = (int32_t *)(b + sh.off[F_GINV]);
+    p.gwide = (float *)(b + sh.off[F_GWIDE]);
+    p.dbound = (float *)(b + sh.off[F_DBOUND]);
     p.brec64 = (double *)(b + sh.off[F_BREC64]);
     p.big_tris = (int32_t *)(b + sh.off[F_BIGTRI]);
     p.scan_tmp = (int32_t *)(b + sh.off[F_SCAN]);

@@ -301,6 +301,13 @@ __device__ __forceinline__ int rank_in(const unsigned long long *a, int n, unsig
     return lo;
 }
 
+// The list positions of tile t (of view v) under its slot: gpos[rec] is
+// the position of record rec in the tile's list.
+__device__ __forceinline__ int32_t *list_positions(const ViewTable &vt, const StatePtrs &st, int v, int t) {
+    const int tl = t - vt.v[v].tile_off, tx = tl % vt.v[v].tiles_x, ty = tl / vt.v[v].tiles_x;
+    return st.gpos + (int64_t)tile_slot(tx, ty) * st.n_rec;
+}
+
 __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, int lat_per_view) {
     __shared__ unsigned long long keys[kSortLds];
     const int t = blockIdx.x, which = blockIdx.y;
@@ -315,19 +322,21 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
         }
         return;
     }
-    unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
+    const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
     const int v = view_of_tile(vt, t);
     uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+    // a Gaussian list also records each entry's position under its record's
+    // tile slot, for the parameter pass
+    int32_t *gpos = which == 0 ? list_positions(vt, st, v, t) : nullptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // the keys go back sorted too: the parameter pass finds a record's list
-    // positions in them by bisection
     if (cnt <= 64) {
         // short lists (most boundary lists, border tiles): one wave, one key per lane
         if (wave != 0) return;
         const unsigned long long x = wave_sort64(lane < cnt ? src[start + lane] : ~0ull, lane);
         if (lane < cnt) {
-            src[start + lane] = x;
-            dst[start + lane] = (uint32_t)record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
+            const int rec = record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
+            dst[start + lane] = (uint32_t)rec;
+            if (gpos) gpos[rec] = start + lane;
         }
         return;
     }
@@ -368,8 +377,9 @@ __global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, 
         __syncthreads();
     }
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        src[start + i] = keys[i];
-        dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+        const int rec = record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+        dst[start + i] = (uint32_t)rec;
+        if (gpos) gpos[rec] = start + i;
     }
 }
 
@@ -392,8 +402,12 @@ __global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st, in
         });
         const int v = view_of_tile(vt, t);
         uint32_t *dst = which == 0 ? st.g_list : st.b_list;
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-            dst[start + i] = (uint32_t)record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+        int32_t *gpos = which == 0 ? list_positions(vt, st, v, t) : nullptr;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int rec = record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
+            dst[start + i] = (uint32_t)rec;
+            if (gpos) gpos[rec] = start + i;
+        }
         __syncthreads();
     }
 }

@@ -457,12 +457,14 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K, BOUND> &S, const Slot
 
 // the backward's staging of slot kk from record gp, read at once
 template <int TS, int K>
-__device__ __forceinline__ void load_stage(BatchLds<TS, K, false> &S, const StatePtrs &st, int gp, int kk, int ox, int oy,
+__device__ __forceinline__ bool load_stage(BatchLds<TS, K, false> &S, const StatePtrs &st, int gp, int kk, int ox, int oy,
                                            const int *run_prim, int n_runs, bool slow_b) {
     SlotPrefetch P;
     const float4 *rp = st.rec + (int64_t)gp * 4;
     P.r0 = rp[0]; P.r1 = rp[1]; P.r2 = rp[2]; P.r3 = rp[3];
     stage_slot<TS, K, false>(S, P, kk, ox, oy, run_prim, n_runs, slow_b, 0.f);
+    // is the record wide (more than 3 x 3 tiles)?
+    return !narrow_range(__float_as_int(P.r3.x), __float_as_int(P.r3.y), TS == 8 ? 3 : (TS == 16 ? 4 : 5));
 }
 
 // does the pixel range (packed int16 pairs) touch the 4x4 sub-block at (x0, y0)?
@@ -689,9 +691,11 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 //   dl/dc_i = T_i a_i dl/dC,  dl/da_i = dl/dC . (T_i c_i - S_i / (1 - a_i)),
 //   dl/dw = dl/da a / w (Supplementary Sec. C), G = exp(-d^T Q d / 2).
 // Per Gaussian the 9 gradient values are summed over each row with DPP and
-// over rows and waves in LDS, then stored once per tile at the entry's list
-// position (plain stores: the parameter pass sums a record's positions over
-// its tiles in a fixed order, so the result does not depend on scheduling).
+// over rows and waves in LDS (an 8x8 tile is one wave: no LDS), then stored
+// once per tile in the record's slot for the tile (plain stores: the
+// parameter pass sums a record's slots over its tiles in a fixed order, so
+// the result does not depend on scheduling; a record reaching more than
+// 3 x 3 tiles adds into sums of its own by float atomics instead).
 // The boundary terms accumulate per (run, pixel) and go to the minimising
 // boundary point at the end of the tile.
 template <int TS, int K>
@@ -752,7 +756,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int ox = tx * TS, oy = ty * TS;
     const float qx = (float)(lx & 7), qy = (float)(ly & 7);
     const int wx0 = tx * TS + (wave % G::SPR) * 8, wy0 = ty * TS + (wave / G::SPR) * 8;
-    const int jslot = __builtin_amdgcn_readfirstlane(ty % 3 * 3 + tx % 3);  // the tile's ginv slot
+    // this tile's slot of the narrow records' sums
+    float *const gs_tile = st.gslot + (int64_t)tile_slot(tx, ty) * st.n_rec * kSums;
 
     if (tid == 0) max_last = 0;
     if (!ONE)
@@ -782,7 +787,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     // the loaders read their records at the end of the previous batch, not
     // ahead of it: registers held across the replay would cost a wave per SIMD
     int cur_gp = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
-    if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+    bool wide = false;
+    if (cur_gp >= 0) wide = load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+    unsigned long long wide_b = __ballot(wide);  // the wave's loaders of wide records
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
         unsigned long long stored = 0ull;  // (one wave) entries whose sums went to memory
@@ -879,10 +886,18 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 vals[0] = cross_row_sum_bp(vals[0], lane);
                 vals[8] = cross_row_sum_bp(vals[8], lane);
                 if constexpr (ONE) {
+                    const int rec = __builtin_amdgcn_readlane(cur_gp, kk);  // the entry's loader holds it
                     if (lane < 16 && (lane & 4)) {
-                        float *dst = st.gsum + (int64_t)(gs0 + base + kk) * kGsumWords;
-                        dst[((lane >> 1) & 4) | (lane & 2) | (lane & 1)] = vals[0];
-                        if (lane == 4) dst[8] = vals[8];
+                        const int f = ((lane >> 1) & 4) | (lane & 2) | (lane & 1);
+                        if ((wide_b >> kk) & 1ull) {
+                            float *dst = st.gwide + (int64_t)rec * kSums;
+                            unsafeAtomicAdd(&dst[f], vals[0]);
+                            if (lane == 4) unsafeAtomicAdd(&dst[8], vals[8]);
+                        } else {
+                            float *dst = gs_tile + (int64_t)rec * kSums;
+                            dst[f] = vals[0];
+                            if (lane == 4) dst[8] = vals[8];
+                        }
                     }
                     stored |= 1ull << kk;
                 } else if (lane < 16 && (lane & 4)) {
@@ -893,34 +908,31 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();
-        if (tid < K && cur_gp >= 0) {  // each loader stores its own slot's sums, then stages the next batch
-            const int p = gs0 + base + tid;
-            float2 *dst = (float2 *)(st.gsum + (int64_t)p * kGsumWords);
+        if (tid < K && cur_gp >= 0) {  // each loader stores its own entry's sums, then stages the next batch
+            const bool wide_me = (wide_b >> lane) & 1ull;
             if constexpr (ONE) {
-                // the entry's record; zero sums for the entries the wave skipped
-                if ((stored >> tid) & 1ull) {
-                    ((int *)dst)[9] = cur_gp;
-                } else {
-                    dst[0] = dst[1] = dst[2] = dst[3] = make_float2(0.f, 0.f);
-                    dst[4] = make_float2(0.f, __int_as_float(cur_gp));
-                }
+                // zero sums for the entries the wave skipped
+                if (!wide_me && !((stored >> tid) & 1ull)) zero_sums(gs_tile + (int64_t)cur_gp * kSums);
             } else {
-                const float *a = acc + tid * 9;
-                dst[0] = make_float2(a[0], a[1]);
-                dst[1] = make_float2(a[2], a[3]);
-                dst[2] = make_float2(a[4], a[5]);
-                dst[3] = make_float2(a[6], a[7]);
-                dst[4] = make_float2(a[8], __int_as_float(cur_gp));  // with the entry's record
+                float *a = acc + tid * 9;
+                if (wide_me) {
+                    float *dst = st.gwide + (int64_t)cur_gp * kSums;
 #pragma unroll
-                for (int f = 0; f < 9; ++f) acc[tid * 9 + f] = 0.f;
+                    for (int f = 0; f < 9; ++f)
+                        if (a[f] != 0.f) unsafeAtomicAdd(&dst[f], a[f]);
+                } else {
+                    float *dst = gs_tile + (int64_t)cur_gp * kSums;
+#pragma unroll
+                    for (int f = 0; f < 9; ++f) dst[f] = a[f];
+                }
+#pragma unroll
+                for (int f = 0; f < 9; ++f) a[f] = 0.f;
             }
-            // the position, under the tile's coordinates modulo 3, for the
-            // parameter pass's lookup (unique within a range of at most
-            // 3 x 3 tiles; records reaching more tiles are found by bisection)
-            st.ginv[(int64_t)cur_gp * kInvSlots + jslot] = p;
         }
         cur_gp = (tid < K && base + K + tid < nlast) ? (int)st.g_list[gs0 + base + K + tid] : -1;
-        if (cur_gp >= 0) load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+        wide = false;
+        if (cur_gp >= 0) wide = load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+        wide_b = __ballot(wide);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (gamma_lds: the smallest

@@ -712,6 +712,9 @@ __global__ void __launch_bounds__(256) k_gen(Consts k, ViewTable vt, PrimPtrs pr
                 // (in the lattice variant the pixel records are boundary points only)
                 if (gi0 <= gi1 && gj0 <= gj1 && k.NL == 0) {
                     gt0 = gi0 >> TSH; gt1 = gi1 >> TSH; gu0 = gj0 >> TSH; gu1 = gj1 >> TSH;
+                    // a wide record's sums start at zero (the parameter pass
+                    // clears them again after reading them)
+                    if (!narrow_range(pack16(gi0, gi1), pack16(gj0, gj1), TSH)) zero_sums(st.gwide + (int64_t)pix * kSums);
                 }
                 if (bi0 <= bi1 && bj0 <= bj1) { bt0 = bi0 >> TSH; bt1 = bi1 >> TSH; bu0 = bj0 >> TSH; bu1 = bj1 >> TSH; }
             }
@@ -839,7 +842,11 @@ __global__ void __launch_bounds__(256) k_gen_lattice(Consts k, ViewTable vt, con
                                  __int_as_float(pack16(1, 0)), __int_as_float(pack16(1, 0)));
             st.gkey[vt.total_px + i] = ((unsigned long long)__double_as_longlong(e.tz)) >> 24;
             const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
-            if (gi0 <= gi1 && gj0 <= gj1) { gt0 = gi0 >> TSH; gt1 = gi1 >> TSH; gu0 = gj0 >> TSH; gu1 = gj1 >> TSH; }
+            if (gi0 <= gi1 && gj0 <= gj1) {
+                gt0 = gi0 >> TSH; gt1 = gi1 >> TSH; gu0 = gj0 >> TSH; gu1 = gj1 >> TSH;
+                if (!narrow_range(pack16(gi0, gi1), pack16(gj0, gj1), TSH))
+                    zero_sums(st.gwide + ((int64_t)vt.total_px + i) * kSums);
+            }
         } else {
             // behind z_near: empty ranges, never listed
             rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -169,11 +169,16 @@ struct VertRec {
 // A pixel's record is at its own pixel; a lattice Gaussian's at the pixel
 // (floor(mu_x), floor(mu_y)), clamped to +-30000.  The depth is kept in
 // the sort key array (gkey) only.
-// words per Gaussian-list entry of the backward's sums: the 9 sums of
-// k_blend_bwd, then the entry's record index (int bits)
-constexpr int kGsumWords = 10;
-// slots per record of the backward's list positions: tiles (tx mod 3, ty mod 3)
-constexpr int kInvSlots = 9;
+// The backward's 9 sums of a Gaussian record in one tile of its range go to
+// slot (ty mod 3) 3 + tx mod 3 of the record, and the sort writes the
+// record's position in that tile's list to the same slot: within a range of
+// at most 3 x 3 tiles ("narrow") no two tiles share a slot.  Slot-major
+// arrays ([slot][record]), so that consecutive records are consecutive in
+// memory for the parameter pass, which reads them in pixel order.  A record
+// reaching more tiles ("wide") adds its sums into kSums floats of its own
+// instead (float atomics).
+constexpr int kSums = 9;
+constexpr int kSlotTiles = 9;
 
 struct StatePtrs {
     int64_t *counters;
@@ -192,12 +197,15 @@ struct StatePtrs {
     int32_t *b_count, *b_start, *b_cursor;
     unsigned long long *g_keys, *b_keys;
     uint32_t *g_list, *b_list;
-    float *gsum;           // [cap_g][kGsumWords] blend-pass sums of each Gaussian-list entry and its record
+    int64_t n_rec;         // Gaussian records
+    float *gslot;          // [kSlotTiles][records][kSums] the backward's sums of narrow records per tile slot,
+                           // written for the tile's replayed prefix (zeros for entries no pixel reached)
+    int32_t *gpos;         // [kSlotTiles][records] the record's position in the tile's sorted list (the sort)
+    int32_t *t_nlast;      // [tiles] entries of the tile's list whose sums the backward wrote
+    float *gwide;          // [records][kSums] the sums of wide records (zeroed by the generation, added by
+                           // the backward, read and zeroed by the parameter pass)
     float *dbound;         // [pixels][3] dl/dsigma_b, dl/dmu (x, y) of each boundary point (zeroed by the
                            // generation, accumulated by the backward, read and zeroed by the parameter pass)
-    int32_t *t_nlast;      // [tiles] entries of the tile's list whose gsum the backward wrote
-    int32_t *ginv;         // [records][kInvSlots] gsum position of the record in the tile (tx, ty) of its range
-                           // at slot (ty mod 3) 3 + tx mod 3
     double *brec64;        // [pixels][3] boundary points in FP64: mu - pixel centre (x, y), sigma
     int32_t *big_tris;     // [cap_big] queue of raster items
     int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
@@ -216,6 +224,17 @@ __device__ __forceinline__ int record_of(const ViewTable &vt, int v, int lr, int
 }
 __device__ __forceinline__ int lo16(int v) { return (int)(int16_t)(v & 0xFFFF); }
 __device__ __forceinline__ int hi16(int v) { return v >> 16; }
+
+__device__ __forceinline__ int tile_slot(int tx, int ty) { return ty % 3 * 3 + tx % 3; }
+// does the tile range of the packed pixel ranges gx, gy (lo | hi << 16, not
+// empty) hold at most 3 x 3 tiles of side 1 << tsh?
+__device__ __forceinline__ bool narrow_range(int gx, int gy, int tsh) {
+    return (hi16(gx) >> tsh) - (lo16(gx) >> tsh) < 3 && (hi16(gy) >> tsh) - (lo16(gy) >> tsh) < 3;
+}
+__device__ __forceinline__ void zero_sums(float *g) {
+#pragma unroll
+    for (int f = 0; f < kSums; ++f) g[f] = 0.f;
+}
 
 // ---------------------------------------------------------------- training step
 

@@ -103,70 +103,50 @@ __device__ __forceinline__ int region_view(const ViewTable &vt, int reg, int &rx
     return -1;
 }
 
-// The blend pass's sums g[0..8] of record `rid` (index `lr` within its view
-// vi): one per tile its Gaussian was binned to (the tile range of the
-// binning pass), stored at the record's position in the tile's sorted list;
-// tiles are taken in raster order, so the sum does not depend on scheduling.
-// Only positions in the tile's replayed prefix (t_nlast) were written: the
-// others were reached by no pixel and hold nothing.  A record reaching at
-// most 3 x 3 tiles has its positions in ginv, one per tile at the slot of its
-// coordinates modulo 3, written by the backward with the sums: one that lies
-// in the replayed prefix and holds the record is this pass's (had the pass
-// not replayed the record in that tile, the record would sit in the tile's
-// list past the prefix).  Other records are found by bisection on their key.
-__device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, const StatePtrs &st, int rid, int lr,
+// The blend pass's sums g[0..8] of record `rid` of view vi: one per tile its
+// Gaussian was binned to (the tile range of the binning pass), added in
+// raster order, so the result does not depend on scheduling.  A narrow
+// record (at most 3 x 3 tiles) has them at its slot of each tile, valid where
+// its position in the tile's list (which the sort wrote to the same slot)
+// lies in the tile's replayed prefix: the backward writes every entry of that
+// prefix and no other.  All loads of a tile are independent of each other.
+// A wide record's sums were added into its own floats, which are read and
+// cleared for the next backward pass.
+__device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, const StatePtrs &st, int rid,
                                            float *g) {
-    // (the positions are loaded with the range, and the position's sums and
-    // record with the tile's bounds: a position is clamped into the array for
-    // that, and used only once it lies in the tile's prefix, where the record
-    // word was written by this pass)
     const float4 r3 = st.rec[(int64_t)rid * 4 + 3];
     const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
     if (!(lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy))) return;
     const int TSH = __builtin_ctz(k.tile);
-    const int gt0 = lo16(gx) >> TSH, gu0 = lo16(gy) >> TSH;
-    const int nx = (hi16(gx) >> TSH) - gt0 + 1, ny = (hi16(gy) >> TSH) - gu0 + 1;
-    if (nx <= 3 && ny <= 3) {
-        const int pmax = (int)min(k.cap_g, (int64_t)INT32_MAX) - 1;
-        const int *pos = st.ginv + (int64_t)rid * kInvSlots;
-        const int mx = gt0 % 3, my = gu0 % 3;
+    if (!narrow_range(gx, gy, TSH)) {
+        float *w = st.gwide + (int64_t)rid * kSums;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {  // (row, column) of the 3 x 3 range
-            const int jx = j % 3, jy = j / 3;
-            if (jx >= nx || jy >= ny) continue;
-            const int tx = gt0 + jx, ty = gu0 + jy;
-            const int t = vi.tile_off + ty * vi.tiles_x + tx;
-            const int sx = mx + jx >= 3 ? mx + jx - 3 : mx + jx, sy = my + jy >= 3 ? my + jy - 3 : my + jy;
-            const int p = pos[sy * 3 + sx];
-            const int pc = min(max(p, 0), pmax);
-            const float2 *qp = (const float2 *)(st.gsum + (int64_t)pc * kGsumWords);
-            const float2 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3], q4 = qp[4];
-            const int s0 = st.g_start[t], n = min(st.t_nlast[t], st.g_count[t]);
-            if (p >= s0 && p < s0 + n && __float_as_int(q4.y) == rid) {
-                g[0] += q0.x; g[1] += q0.y; g[2] += q1.x; g[3] += q1.y; g[4] += q2.x;
-                g[5] += q2.y; g[6] += q3.x; g[7] += q3.y; g[8] += q4.x;
-            }
-        }
+        for (int f = 0; f < kSums; ++f) { g[f] = w[f]; w[f] = 0.f; }
         return;
     }
-    const unsigned long long key = (st.gkey[rid] << 24) | (unsigned long long)lr;
-    for (int ty = gu0; ty <= hi16(gy) >> TSH; ++ty)
-        for (int tx = gt0; tx <= hi16(gx) >> TSH; ++tx) {
-            const int t = vi.tile_off + ty * vi.tiles_x + tx;
-            const int s0 = st.g_start[t], n = min(st.t_nlast[t], st.g_count[t]);
-            const unsigned long long *keys = st.g_keys + s0;
-            int lo = 0, hi = n;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (keys[mid] < key) lo = mid + 1;
-                else hi = mid;
-            }
-            if (lo < n && keys[lo] == key) {
-                const float *q = st.gsum + (int64_t)(s0 + lo) * kGsumWords;
+    // lists that overflowed their capacity lack entries, whose slots hold
+    // no position of this pass: no sums are taken then
+    if (st.counters[C_OVERFLOW] & 1) return;
+    const int gt0 = lo16(gx) >> TSH, gu0 = lo16(gy) >> TSH;
+    const int nx = (hi16(gx) >> TSH) - gt0 + 1, ny = (hi16(gy) >> TSH) - gu0 + 1;
 #pragma unroll
-                for (int f = 0; f < 9; ++f) g[f] += q[f];
-            }
+    for (int j = 0; j < 9; ++j) {  // (row, column) of the 3 x 3 range
+        const int jx = j % 3, jy = j / 3;
+        if (jx >= nx || jy >= ny) continue;
+        const int tx = gt0 + jx, ty = gu0 + jy;
+        const int t = vi.tile_off + ty * vi.tiles_x + tx;
+        const int64_t si = (int64_t)tile_slot(tx, ty) * st.n_rec + rid;
+        const int p = st.gpos[si];
+        const float *q = st.gslot + si * kSums;
+        float qv[kSums];
+#pragma unroll
+        for (int f = 0; f < kSums; ++f) qv[f] = q[f];
+        const int s0 = st.g_start[t], n = min(st.t_nlast[t], st.g_count[t]);
+        if ((unsigned)(p - s0) < (unsigned)n) {
+#pragma unroll
+            for (int f = 0; f < kSums; ++f) g[f] += qv[f];
         }
+    }
 }
 
 template <int DEG, bool EXT, bool LAT>
@@ -225,7 +205,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
     float g[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) g[i] = 0.f;
-    int v0 = 0, lr = 0;  // view and index within the view of the lane's record
+    int v0 = 0;  // view of the lane's record
     float2 uv = make_float2(0.f, 0.f);
     if constexpr (LAT) {
         // record total_px + i: view i / (P NL), patch, node (a, b) at (a, b) / M
@@ -239,7 +219,6 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             while (node > k.lat_level - a) { node -= k.lat_level - a + 1; ++a; }
             uv = make_float2((float)a / (float)k.lat_level, (float)node / (float)k.lat_level);
             pix = vt.total_px + (int)i;
-            lr = vt.v[v0].W * vt.v[v0].H + (int)r;
             prim = p;
         }
     } else if (rv >= 0) {
@@ -247,7 +226,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
         const int b = wave + 4 * pass;
         const int x0 = rx0 + (b & 3) * 8 + (lane & 7), y0 = ry0 + (b >> 2) * 8 + (lane >> 3);
         v0 = rv;
-        lr = y0 * vt.v[rv].W + x0;
+        const int lr = y0 * vt.v[rv].W + x0;
         if (x0 < vt.v[rv].W && y0 < vt.v[rv].H) pix = vt.v[rv].px_off + lr;
     }
     {
@@ -257,7 +236,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             // of dl/dG G, colour, opacity (the record's Gaussian; a pixel
             // record of the lattice variant has none), boundary radius and
             // position (a boundary point's)
-            if (LAT || k.NL == 0) gauss_sums(k, vt.v[v0], st, pix, lr, g);
+            if (LAT || k.NL == 0) gauss_sums(k, vt.v[v0], st, pix, g);
             if (!LAT && (fl & PF_BOUNDARY)) {  // read and cleared for the next backward pass
                 float *bp = st.dbound + (int64_t)pix * 3;
                 g[9] = bp[0]; g[10] = bp[1]; g[11] = bp[2];

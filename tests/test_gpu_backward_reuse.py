@@ -1,14 +1,14 @@
 """Backward passes repeated on one forward pass's state.
 
-The blend backward stores each tile-list entry's sums at the entry's list
-position, for the tile's replayed prefix only (the entries up to the largest
-stop index of the tile's pixels with a non-zero cotangent), and records per
-Gaussian record its position in each tile; the parameter pass takes a
-recorded position only when it lies in that tile's prefix and holds the
-record.  A second backward with a cotangent that vanishes on the pixels that
-composite deepest shortens those prefixes, so the positions and sums the first
-pass wrote past them are still in the state: the second pass's gradients
-must be those of its own cotangent, against the oracle."""
+The blend backward stores each tile-list entry's sums in its record's slot
+for the tile, for the tile's replayed prefix only (the entries up to the
+largest stop index of the tile's pixels with a non-zero cotangent); the sort
+writes each entry's list position to the same slot, and the parameter pass
+takes a slot's sums only when that position lies in the tile's prefix.  A
+second backward with a cotangent that vanishes on the pixels that composite
+deepest shortens those prefixes, so sums the first pass wrote past them are
+still in the state: the second pass's gradients must be those of its own
+cotangent, against the oracle."""
 import numpy as np
 import pytest
 
