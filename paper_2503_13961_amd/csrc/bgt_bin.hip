@@ -4,8 +4,9 @@
 // id.  The sort is a two-level radix split: a counting pass on the tile id
 // (the high key digit) places each pair in its tile's segment, then each
 // segment is sorted on the low digits (depth, record index) or (primitive,
-// record index): runs of 64 keys sorted in registers by one wave each, then
-// merged pairwise by rank in LDS (segments beyond the LDS buffer: a bitonic
+// record index): by one wave in registers (a bitonic network over up to 512
+// keys), longer segments by a workgroup (runs of 64 keys sorted in registers,
+// merged pairwise by rank in LDS; segments beyond the LDS buffer: a bitonic
 // network in global memory).  The low digits make every key unique, so the
 // result does not depend on the order of the atomics that filled the segment.
 #include "bgt_internal.h"
@@ -308,107 +309,169 @@ __device__ __forceinline__ int32_t *list_positions(const ViewTable &vt, const St
     return st.gpos + (int64_t)tile_slot(tx, ty) * st.n_rec;
 }
 
-__global__ void __launch_bounds__(256) k_sort_tiles(ViewTable vt, StatePtrs st, int lat_per_view) {
-    __shared__ unsigned long long keys[kSortLds];
-    const int t = blockIdx.x, which = blockIdx.y;
-    const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
-    if (cnt == 0) return;
-    const int start = which == 0 ? st.g_start[t] : st.b_start[t];
-    if (cnt > kSortLds) {
-        if (threadIdx.x == 0) {
-            const long long q = atomicAdd((unsigned long long *)&st.counters[C_BIGSORT_Q + which], 1ull);
-            st.bigsort_q[(int64_t)which * vt.total_tiles + q] = t;
-            atomicAdd((unsigned long long *)&st.counters[C_BIGSORT], 1ull);
-        }
-        return;
-    }
-    const unsigned long long *src = which == 0 ? st.g_keys : st.b_keys;
-    const int v = view_of_tile(vt, t);
-    uint32_t *dst = which == 0 ? st.g_list : st.b_list;
-    // a Gaussian list also records each entry's position under its record's
-    // tile slot, for the parameter pass
-    int32_t *gpos = which == 0 ? list_positions(vt, st, v, t) : nullptr;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (cnt <= 64) {
-        // short lists (most boundary lists, border tiles): one wave, one key per lane
-        if (wave != 0) return;
-        const unsigned long long x = wave_sort64(lane < cnt ? src[start + lane] : ~0ull, lane);
-        if (lane < cnt) {
-            const int rec = record_of(vt, v, (int)(x & 0xFFFFFFull), lat_per_view);
-            dst[start + lane] = (uint32_t)rec;
-            if (gpos) gpos[rec] = start + lane;
-        }
-        return;
-    }
-    // Runs of 64 keys sorted in registers, one wave per run (padded with
-    // ~0, above every key), then merged pairwise by rank: a key's place in
-    // the merged run is its place in its own run plus the number of keys of
-    // the other run before it (keys of the first run go before equal keys of
-    // the second; only the padding repeats).  In place: every thread ranks its
-    // keys (at most kSortLds / 256) first and all write after a barrier, so
-    // the block needs one buffer (16 KB) and twice as many blocks fit a CU.
-    constexpr int PER = kSortLds / 256;
-    const int n64 = (cnt + 63) & ~63, nruns = n64 >> 6;
-    for (int run = wave; run < nruns; run += blockDim.x >> 6) {
-        const int i = run * 64 + lane;
-        keys[i] = wave_sort64(i < cnt ? src[start + i] : ~0ull, lane);
-    }
-    __syncthreads();
-    for (int L = 64; L < n64; L <<= 1) {
-        unsigned long long x[PER];
-        int pos[PER];
+// Ascending bitonic sort of the 64 R keys x[r] of lane l (key l R + r)
+// across the wave: partners fewer than R apart are in the same lane, the
+// others (fewer steps) are exchanged between lanes.  Padding keys (~0) sort
+// last.
+template <int R>
+__device__ __forceinline__ void wave_sort_regs(unsigned long long (&x)[R], int lane) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + q * 256;
-            pos[q] = -1;
-            x[q] = 0ull;
-            if (i < n64) {
-                const int p0 = i & ~(2 * L - 1);
-                const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
-                x[q] = keys[i];
-                pos[q] = i < mid ? i + rank_in<false>(keys + mid, end - mid, x[q])
-                                 : p0 + (i - mid) + rank_in<true>(keys + p0, mid - p0, x[q]);
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            if (j < R) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int r2 = r ^ j;
+                    if (r2 < r) continue;
+                    // ascending where bit k of the key index l R + r is clear
+                    const bool up = (((lane * R) | r) & k) == 0;
+                    const unsigned long long a = x[r], b = x[r2];
+                    const bool sw = (b < a) == up;  // (equal keys: either)
+                    x[r] = sw ? b : a;
+                    x[r2] = sw ? a : b;
+                }
+            } else {
+                const int m = j / R;  // partner lane l ^ m
+                // the lower lane of a pair keeps the smaller key in ascending
+                // runs: it takes the partner's key when that is smaller, the
+                // upper lane when it is larger (equal keys: either)
+                const bool keep_min = ((lane & m) == 0) == (((lane * R) & k) == 0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const unsigned long long y = __shfl_xor(x[r], m, 64);
+                    x[r] = (y < x[r]) == keep_min ? y : x[r];
+                }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q)
-            if (pos[q] >= 0) keys[pos[q]] = x[q];
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int rec = record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
-        dst[start + i] = (uint32_t)rec;
-        if (gpos) gpos[rec] = start + i;
     }
 }
 
-// Segments longer than the LDS buffer: same network on global memory, one
-// block per segment (rare; correctness path).
-__global__ void __launch_bounds__(256) k_sort_big(ViewTable vt, StatePtrs st, int lat_per_view) {
+// Lists up to this length are sorted by one wave in registers; longer ones
+// are queued for a workgroup each.
+constexpr int kWaveSort = 512;
+
+template <int R, typename Emit>
+__device__ __forceinline__ void wave_sort_list(const unsigned long long *src, int cnt, int lane, Emit &&emit) {
+    unsigned long long x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane * R + r;
+        x[r] = i < cnt ? src[i] : ~0ull;
+    }
+    wave_sort_regs<R>(x, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane * R + r;
+        if (i < cnt) emit(i, x[r]);
+    }
+}
+
+// One wave per list: list L < n_tiles is the Gaussian list of tile L, the
+// others the boundary lists.  Empty lists cost a wave a few instructions.
+__global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, int lat_per_view) {
+    const int lane = threadIdx.x & 63;
+    const int L = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (L >= 2 * vt.total_tiles) return;
+    const int which = L < vt.total_tiles ? 0 : 1, t = which == 0 ? L : L - vt.total_tiles;
+    const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
+    if (cnt == 0) return;
+    if (cnt > kWaveSort) {
+        if (lane == 0) {
+            const long long q = atomicAdd((unsigned long long *)&st.counters[C_BIGSORT_Q + which], 1ull);
+            st.bigsort_q[(int64_t)which * vt.total_tiles + q] = t;
+        }
+        return;
+    }
+    const int start = which == 0 ? st.g_start[t] : st.b_start[t];
+    const unsigned long long *src = (which == 0 ? st.g_keys : st.b_keys) + start;
+    const int v = view_of_tile(vt, t);
+    uint32_t *dst = (which == 0 ? st.g_list : st.b_list) + start;
+    // a Gaussian list also records each entry's position under its record's
+    // tile slot, for the parameter pass
+    int32_t *gpos = which == 0 ? list_positions(vt, st, v, t) : nullptr;
+    auto emit = [&](int i, unsigned long long key) {
+        const int rec = record_of(vt, v, (int)(key & 0xFFFFFFull), lat_per_view);
+        dst[i] = (uint32_t)rec;
+        if (gpos) gpos[rec] = start + i;
+    };
+    if (cnt <= 64) wave_sort_list<1>(src, cnt, lane, emit);
+    else if (cnt <= 128) wave_sort_list<2>(src, cnt, lane, emit);
+    else if (cnt <= 256) wave_sort_list<4>(src, cnt, lane, emit);
+    else wave_sort_list<8>(src, cnt, lane, emit);
+}
+
+// Lists longer than a wave sorts, one workgroup per queued list.  Up to
+// kSortLds keys: runs of 64 keys sorted in registers, one wave per run
+// (padded with ~0, above every key), then merged pairwise by rank: a key's
+// place in the merged run is its place in its own run plus the number of keys
+// of the other run before it (keys of the first run go before equal keys of
+// the second; only the padding repeats).  In place: every thread ranks its
+// keys (at most kSortLds / 256) first and all write after a barrier, so the
+// block needs one buffer (16 KB).  Longer lists (rare; a correctness path):
+// the bitonic network on global memory.
+__global__ void __launch_bounds__(256) k_sort_long(ViewTable vt, StatePtrs st, int lat_per_view) {
+    __shared__ unsigned long long keys[kSortLds];
     const int which = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t nq = st.counters[C_BIGSORT_Q + which];
     for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int t = st.bigsort_q[(int64_t)which * vt.total_tiles + qi];
         const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
         const int start = which == 0 ? st.g_start[t] : st.b_start[t];
-        unsigned long long *keys = (which == 0 ? st.g_keys : st.b_keys) + start;
-        int n2 = 1;
-        while (n2 < cnt) n2 <<= 1;
-        bitonic_steps<NoGet>(n2, [&](int a, int b) {
-            if (b >= cnt) return;
-            const unsigned long long x = keys[a], y = keys[b];
-            if (y < x) { keys[a] = y; keys[b] = x; }
-        });
+        unsigned long long *src = (which == 0 ? st.g_keys : st.b_keys) + start;
         const int v = view_of_tile(vt, t);
-        uint32_t *dst = which == 0 ? st.g_list : st.b_list;
+        uint32_t *dst = (which == 0 ? st.g_list : st.b_list) + start;
         int32_t *gpos = which == 0 ? list_positions(vt, st, v, t) : nullptr;
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-            const int rec = record_of(vt, v, (int)(keys[i] & 0xFFFFFFull), lat_per_view);
-            dst[start + i] = (uint32_t)rec;
+        auto emit = [&](int i, unsigned long long key) {
+            const int rec = record_of(vt, v, (int)(key & 0xFFFFFFull), lat_per_view);
+            dst[i] = (uint32_t)rec;
             if (gpos) gpos[rec] = start + i;
+        };
+        if (cnt > kSortLds) {
+            if (threadIdx.x == 0) atomicAdd((unsigned long long *)&st.counters[C_BIGSORT], 1ull);
+            int n2 = 1;
+            while (n2 < cnt) n2 <<= 1;
+            bitonic_steps<NoGet>(n2, [&](int a, int b) {
+                if (b >= cnt) return;
+                const unsigned long long x = src[a], y = src[b];
+                if (y < x) { src[a] = y; src[b] = x; }
+            });
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) emit(i, src[i]);
+            __syncthreads();
+            continue;
+        }
+        constexpr int PER = kSortLds / 256;
+        const int n64 = (cnt + 63) & ~63, nruns = n64 >> 6;
+        for (int run = wave; run < nruns; run += blockDim.x >> 6) {
+            const int i = run * 64 + lane;
+            keys[i] = wave_sort64(i < cnt ? src[i] : ~0ull, lane);
         }
         __syncthreads();
+        for (int L = 64; L < n64; L <<= 1) {
+            unsigned long long x[PER];
+            int pos[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = threadIdx.x + q * 256;
+                pos[q] = -1;
+                x[q] = 0ull;
+                if (i < n64) {
+                    const int p0 = i & ~(2 * L - 1);
+                    const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
+                    x[q] = keys[i];
+                    pos[q] = i < mid ? i + rank_in<false>(keys + mid, end - mid, x[q])
+                                     : p0 + (i - mid) + rank_in<true>(keys + p0, mid - p0, x[q]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (pos[q] >= 0) keys[pos[q]] = x[q];
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) emit(i, keys[i]);
+        __syncthreads();  // the next list reuses the buffer
     }
 }
 
@@ -443,8 +506,9 @@ hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs 
         const int64_t nl = (int64_t)vt.n * lat_per_view;
         hipLaunchKernelGGL(k_scatter_lattice, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, k, vt, st);
     }
-    hipLaunchKernelGGL(k_sort_tiles, dim3(n, 2), dim3(256), 0, s, vt, st, lat_per_view);
-    hipLaunchKernelGGL(k_sort_big, dim3(64, 2), dim3(256), 0, s, vt, st, lat_per_view);
+    hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)((2 * (int64_t)n + 3) / 4)), dim3(256), 0, s, vt, st,
+                       lat_per_view);
+    hipLaunchKernelGGL(k_sort_long, dim3(512, 2), dim3(256), 0, s, vt, st, lat_per_view);
     return hipGetLastError();
 }
 
