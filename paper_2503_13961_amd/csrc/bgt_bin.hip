@@ -309,6 +309,22 @@ __device__ __forceinline__ int32_t *list_positions(const ViewTable &vt, const St
     return st.gpos + (int64_t)tile_slot(tx, ty) * st.n_rec;
 }
 
+// The key of lane l ^ m (m a power of two below 64): DPP within quads
+// (plain VALU moves), an LDS swizzle within 32-lane halves, a permute across
+// them.
+__device__ __forceinline__ int xor_lane(int v, int m) {
+    if (m == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+    if (m == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+    if (m == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);               // bit mode: and 31, xor 4
+    if (m == 8) return __builtin_amdgcn_ds_swizzle(v, 0x201F);
+    if (m == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    return __shfl_xor(v, m, 64);
+}
+__device__ __forceinline__ unsigned long long xor_lane(unsigned long long v, int m) {
+    const int lo = xor_lane((int)(unsigned)v, m), hi = xor_lane((int)(unsigned)(v >> 32), m);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
 // Ascending bitonic sort of the 64 R keys x[r] of lane l (key l R + r)
 // across the wave: partners fewer than R apart are in the same lane, the
 // others (fewer steps) are exchanged between lanes.  Padding keys (~0) sort
@@ -339,7 +355,7 @@ __device__ __forceinline__ void wave_sort_regs(unsigned long long (&x)[R], int l
                 const bool keep_min = ((lane & m) == 0) == (((lane * R) & k) == 0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const unsigned long long y = __shfl_xor(x[r], m, 64);
+                    const unsigned long long y = xor_lane(x[r], m);
                     x[r] = (y < x[r]) == keep_min ? y : x[r];
                 }
             }
