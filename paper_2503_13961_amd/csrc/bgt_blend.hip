@@ -729,7 +729,9 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     __shared__ int max_last;
     BatchLds<TS, K, false> &S = U.loop.S;
     float *acc = U.loop.acc;
-    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // runs of 64 neighbouring tiles per XCD: the sums of a record's tiles
+    // then mostly meet in one L2
+    const int t = xcd_runs<64>(blockIdx.x, gridDim.x), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gc = st.g_count[t];
     if (gc == 0) {  // no Gaussian reaches the tile: nothing to differentiate
         if (tid == 0) st.t_nlast[t] = 0;

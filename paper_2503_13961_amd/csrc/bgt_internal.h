@@ -111,6 +111,19 @@ __device__ __forceinline__ void for_tiles_grouped(int tx0, int tx1, int ty0, int
     }
 }
 
+// Workgroups go to the chip's 8 XCDs in turn (workgroup i to XCD i mod 8),
+// each XCD with an L2 of its own.  This maps launch index i to a work item
+// so that each XCD takes runs of C consecutive items (neighbouring tiles read
+// many of the same records); indices past the last whole round of 8 C map to
+// themselves.  A bijection of [0, n).
+template <int C>
+__device__ __forceinline__ int xcd_runs(int i, int n) {
+    const int full = n / (8 * C) * (8 * C);
+    if (i >= full) return i;
+    const int x = i & 7, k = i >> 3;
+    return ((k / C) * 8 + x) * C + k % C;
+}
+
 // ---------------------------------------------------------------- constants
 
 struct Consts {
