@@ -118,82 +118,113 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int32_t *gc, int32_t
 
 // ------------------------------------------------------------ scatter
 
-// The pairs of the lanes whose tile rectangle lies within the 3x3 tiles
-// around (cx, cy), the tile of the wave's 8x8 block: one cursor atomic per
-// neighbouring tile for the whole wave, all issued by one instruction (lane
-// j takes tile j), so the wave waits for one round trip; a lane's slot in a
-// tile is the tile's base plus its rank among the lanes there.  The other
-// lanes' rectangles (in = false) are left to the caller.
-template <typename E>
-__device__ __forceinline__ void near_tiles(bool in, int tx0, int tx1, int ty0, int ty1, int cx, int cy,
-                                           const ViewInfo &vi, int32_t *cursor, int lane, E &&emit) {
+// A lane's tile rectangle [x0, x1] x [y0, y1] (empty: x0 > x1).
+struct TileRect {
+    int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+    __device__ bool has(int tx, int ty) const { return tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1; }
+};
+
+// The pairs of the lanes whose rectangles lie within the 3x3 tiles around
+// (cx, cy), the tile of the wave's 8x8 block, for both lists: one cursor
+// atomic per (list, neighbouring tile) for the whole wave, all issued by one
+// instruction (lane j takes the Gaussian list of tile j, lane 9 + j its
+// boundary list) together with the loads of the segments' ends, so the wave
+// waits for one round trip; a lane's slot in a tile is the tile's base plus
+// its rank among the lanes there (slots past the segment's end, after a
+// capacity overflow, are dropped).  Every base and end goes to scalar
+// registers before the first key is stored: reading them between the stores
+// would make each store wait for the previous one.  Lanes whose rectangle
+// reaches further (gin, bin false) are left to the caller.
+template <typename EG, typename EB>
+__device__ __forceinline__ void near_tiles(bool gin, const TileRect &g, bool bin, const TileRect &b, int cx, int cy,
+                                           const ViewInfo &vi, const StatePtrs &st, int lane, EG &&emit_g,
+                                           EB &&emit_b) {
     const unsigned long long below = (1ull << lane) - 1ull;
-    unsigned long long m[9];
-    int cnt = 0, tl = 0;
+    int cnt = 0;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         const int tx = cx + j % 3 - 1, ty = cy + j / 3 - 1;
-        m[j] = __ballot(in && tx >= tx0 && tx <= tx1 && ty >= ty0 && ty <= ty1);
-        if (lane == j) { cnt = __popcll(m[j]); tl = vi.tile_off + ty * vi.tiles_x + tx; }
+        const unsigned long long mg = __ballot(gin && g.has(tx, ty));
+        const unsigned long long mb = __ballot(bin && b.has(tx, ty));
+        if (lane == j) cnt = __popcll(mg);
+        if (lane == 9 + j) cnt = __popcll(mb);
     }
-    int base = 0;
-    if (lane < 9 && cnt > 0) base = atomicAdd(&cursor[tl], cnt);
+    int base = 0, s0 = 0, c0 = 0;
+    if (cnt > 0) {
+        const bool isg = lane < 9;
+        const int j = isg ? lane : lane - 9;
+        const int tl = vi.tile_off + (cy + j / 3 - 1) * vi.tiles_x + cx + j % 3 - 1;
+        s0 = (isg ? st.g_start : st.b_start)[tl];
+        c0 = (isg ? st.g_count : st.b_count)[tl];
+        base = atomicAdd((isg ? st.g_cursor : st.b_cursor) + tl, cnt);
+    }
+    const int end = s0 + c0;
+    int bs[18], es[18];
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+        bs[j] = __builtin_amdgcn_readlane(base, j);
+        es[j] = __builtin_amdgcn_readlane(end, j);
+    }
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-        if (m[j] == 0ull) continue;
-        const int b = __builtin_amdgcn_readlane(base, j);
-        const int t = vi.tile_off + (cy + j / 3 - 1) * vi.tiles_x + cx + j % 3 - 1;
-        if ((m[j] >> lane) & 1ull) emit(t, b + __popcll(m[j] & below));
+        const int tx = cx + j % 3 - 1, ty = cy + j / 3 - 1;
+        const bool ig = gin && g.has(tx, ty), ib = bin && b.has(tx, ty);
+        const unsigned long long mg = __ballot(ig), mb = __ballot(ib);
+        const int sg = bs[j] + __popcll(mg & below), sb = bs[9 + j] + __popcll(mb & below);
+        if (ig && sg < es[j]) emit_g(sg);
+        if (ib && sb < es[9 + j]) emit_b(sb);
     }
 }
 
 __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePtrs st) {
     const int lane = threadIdx.x & 63;
     int v, x, y;
-    const bool act = block8_pixel(vt, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane, v, x, y);
+    const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const bool act = block8_pixel(vt, blk, lane, v, x, y);
     const ViewInfo vi = vt.v[v];
     const int TSH = __builtin_ctz(k.tile);  // tile side 8, 16 or 32: pixel ranges (>= 0) shift to tiles
     // the tile of the wave's block (x - (lane & 7) is its left edge)
     const int cx = __builtin_amdgcn_readfirstlane((x - (lane & 7)) >> TSH);
     const int cy = __builtin_amdgcn_readfirstlane((y - (lane >> 3)) >> TSH);
-    int gt0 = 1, gt1 = 0, gu0 = 1, gu1 = 0, bt0 = 1, bt1 = 0, bu0 = 1, bu1 = 0;
+    TileRect g, b;
     unsigned long long gkey = 0ull, bkey = 0ull;
     if (act) {
         const int lp = y * vi.W + x, pix = vi.px_off + lp;
         const uint8_t fl = st.pflags[pix];
         if (fl & PF_VALID) {
+            // (the three loads in one round trip: the primitive is read for
+            // every record, used for boundary points)
             const float4 r3 = st.rec[(int64_t)pix * 4 + 3];
+            const unsigned long long depth = st.gkey[pix];
+            const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
             const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
             // (in the lattice variant a pixel record is a boundary point only)
             if (k.NL == 0 && lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy)) {
-                gt0 = lo16(gx) >> TSH; gt1 = hi16(gx) >> TSH; gu0 = lo16(gy) >> TSH; gu1 = hi16(gy) >> TSH;
+                g.x0 = lo16(gx) >> TSH; g.x1 = hi16(gx) >> TSH; g.y0 = lo16(gy) >> TSH; g.y1 = hi16(gy) >> TSH;
             }
-            gkey = (st.gkey[pix] << 24) | (unsigned long long)lp;
+            gkey = (depth << 24) | (unsigned long long)lp;
             if (fl & PF_BOUNDARY) {
                 const int bx = __float_as_int(r3.z), by = __float_as_int(r3.w);
                 if (lo16(bx) <= hi16(bx) && lo16(by) <= hi16(by)) {
-                    bt0 = lo16(bx) >> TSH; bt1 = hi16(bx) >> TSH; bu0 = lo16(by) >> TSH; bu1 = hi16(by) >> TSH;
+                    b.x0 = lo16(bx) >> TSH; b.x1 = hi16(bx) >> TSH; b.y0 = lo16(by) >> TSH; b.y1 = hi16(by) >> TSH;
                 }
-                const int prim = __float_as_int(st.rec[(int64_t)pix * 4 + 2].y);
                 bkey = ((unsigned long long)prim << 24) | (unsigned long long)lp;
             }
         }
     }
     // rectangles within the 3x3 tiles around the block's tile (nearly all):
-    // one round of cursor atomics per list; the rest one cursor atomic per
-    // group of lanes at the same tile, each lane taking the slot of its rank
-    const bool gnear = gt0 <= gt1 && gu0 <= gu1 && gt0 >= cx - 1 && gt1 <= cx + 1 && gu0 >= cy - 1 && gu1 <= cy + 1;
-    const bool bnear = bt0 <= bt1 && bu0 <= bu1 && bt0 >= cx - 1 && bt1 <= cx + 1 && bu0 >= cy - 1 && bu1 <= cy + 1;
-    near_tiles(gnear, gt0, gt1, gu0, gu1, cx, cy, vi, st.g_cursor, lane, [&](int t, int slot) {
-        if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = gkey;
-    });
-    near_tiles(bnear, bt0, bt1, bu0, bu1, cx, cy, vi, st.b_cursor, lane, [&](int t, int slot) {
-        if (slot < st.b_start[t] + st.b_count[t]) st.b_keys[slot] = bkey;
-    });
+    // one round of cursor atomics for both lists; the rest one cursor atomic
+    // per group of lanes at the same tile, each lane taking the slot of its rank
+    const bool gnear = g.x0 <= g.x1 && g.y0 <= g.y1 && g.x0 >= cx - 1 && g.x1 <= cx + 1 && g.y0 >= cy - 1 &&
+                       g.y1 <= cy + 1;
+    const bool bnear = b.x0 <= b.x1 && b.y0 <= b.y1 && b.x0 >= cx - 1 && b.x1 <= cx + 1 && b.y0 >= cy - 1 &&
+                       b.y1 <= cy + 1;
+    near_tiles(gnear, g, bnear, b, cx, cy, vi, st, lane, [&](int slot) { st.g_keys[slot] = gkey; },
+               [&](int slot) { st.b_keys[slot] = bkey; });
     const unsigned long long below = (1ull << lane) - 1ull;
-    if (gnear) { gt0 = 1; gt1 = 0; }
-    if (bnear) { bt0 = 1; bt1 = 0; }
-    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off,
+    if (gnear) g = TileRect();
+    if (bnear) b = TileRect();
+    for_tiles_grouped(g.x0, g.x1, g.y0, g.y1, vi.tiles_x, vi.tile_off,
                       [&](int t, unsigned long long gm, bool in, int leader) {
         int base = 0;
         if (lane == leader) base = atomicAdd(&st.g_cursor[t], __popcll(gm));
@@ -203,7 +234,7 @@ __global__ void __launch_bounds__(256) k_scatter(Consts k, ViewTable vt, StatePt
             if (slot < st.g_start[t] + st.g_count[t]) st.g_keys[slot] = gkey;
         }
     });
-    for_tiles_grouped(bt0, bt1, bu0, bu1, vi.tiles_x, vi.tile_off,
+    for_tiles_grouped(b.x0, b.x1, b.y0, b.y1, vi.tiles_x, vi.tile_off,
                       [&](int t, unsigned long long gm, bool in, int leader) {
         int base = 0;
         if (lane == leader) base = atomicAdd(&st.b_cursor[t], __popcll(gm));
@@ -367,25 +398,54 @@ __device__ __forceinline__ void wave_sort_regs(unsigned long long (&x)[R], int l
 // are queued for a workgroup each.
 constexpr int kWaveSort = 512;
 
+// LDS slot of key i of a wave's staging buffer: 8 bytes of padding after
+// every 8 keys, so that lanes reading 8 consecutive keys each hit distinct
+// banks
+__device__ __forceinline__ int stage_slot(int i) { return i + (i >> 3); }
+constexpr int kStageKeys = kWaveSort + kWaveSort / 8;
+
+// Sorts one list of cnt <= 64 R keys.  Multi-key lanes load and store
+// through the wave's LDS buffer sb, so that global memory is read and written
+// in 64-lane runs while each lane sorts consecutive keys.
 template <int R, typename Emit>
-__device__ __forceinline__ void wave_sort_list(const unsigned long long *src, int cnt, int lane, Emit &&emit) {
+__device__ __forceinline__ void wave_sort_list(const unsigned long long *src, int cnt, int lane, unsigned long long *sb,
+                                               Emit &&emit) {
     unsigned long long x[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = lane * R + r;
-        x[r] = i < cnt ? src[i] : ~0ull;
+    if constexpr (R == 1) {
+        x[0] = lane < cnt ? src[lane] : ~0ull;
+        wave_sort_regs<1>(x, lane);
+        if (lane < cnt) emit(lane, x[0]);
+        return;
     }
-    wave_sort_regs<R>(x, lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane * R + r;
-        if (i < cnt) emit(i, x[r]);
+        const int i = r * 64 + lane;
+        sb[stage_slot(i)] = i < cnt ? src[i] : ~0ull;
+    }
+    // (one wave's LDS accesses complete in order: the fence keeps the
+    // compiler from moving them across each other)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = sb[stage_slot(lane * R + r)];
+    wave_sort_regs<R>(x, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r) sb[stage_slot(lane * R + r)] = x[r];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * 64 + lane;
+        if (i < cnt) emit(i, sb[stage_slot(i)]);
     }
 }
 
 // One wave per list: list L < n_tiles is the Gaussian list of tile L, the
 // others the boundary lists.  Empty lists cost a wave a few instructions.
 __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, int lat_per_view) {
+    __shared__ unsigned long long stage[4][kStageKeys];
     const int lane = threadIdx.x & 63;
     const int L = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (L >= 2 * vt.total_tiles) return;
@@ -411,10 +471,11 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
         dst[i] = (uint32_t)rec;
         if (gpos) gpos[rec] = start + i;
     };
-    if (cnt <= 64) wave_sort_list<1>(src, cnt, lane, emit);
-    else if (cnt <= 128) wave_sort_list<2>(src, cnt, lane, emit);
-    else if (cnt <= 256) wave_sort_list<4>(src, cnt, lane, emit);
-    else wave_sort_list<8>(src, cnt, lane, emit);
+    unsigned long long *sb = stage[threadIdx.x >> 6];
+    if (cnt <= 64) wave_sort_list<1>(src, cnt, lane, sb, emit);
+    else if (cnt <= 128) wave_sort_list<2>(src, cnt, lane, sb, emit);
+    else if (cnt <= 256) wave_sort_list<4>(src, cnt, lane, sb, emit);
+    else wave_sort_list<8>(src, cnt, lane, sb, emit);
 }
 
 // Lists longer than a wave sorts, one workgroup per queued list.  Up to
