@@ -910,7 +910,13 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
             }
         }
         __syncthreads();
-        if (tid < K && cur_gp >= 0) {  // each loader stores its own entry's sums, then stages the next batch
+        // the next batch is staged before this batch's sums are stored: a
+        // load issued after the stores would wait for them too (acc is not
+        // part of the stage)
+        const int next_gp = (tid < K && base + K + tid < nlast) ? (int)st.g_list[gs0 + base + K + tid] : -1;
+        bool next_wide = false;
+        if (next_gp >= 0) next_wide = load_stage<TS, K>(S, st, next_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+        if (tid < K && cur_gp >= 0) {  // each loader stores its own entry's sums
             const bool wide_me = (wide_b >> lane) & 1ull;
             if constexpr (ONE) {
                 // zero sums for the entries the wave skipped
@@ -931,10 +937,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
                 for (int f = 0; f < 9; ++f) a[f] = 0.f;
             }
         }
-        cur_gp = (tid < K && base + K + tid < nlast) ? (int)st.g_list[gs0 + base + K + tid] : -1;
-        wide = false;
-        if (cur_gp >= 0) wide = load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
-        wide_b = __ballot(wide);
+        cur_gp = next_gp;
+        wide_b = __ballot(next_wide);
     }
     // boundary points at the arg-min of each (run, pixel): d gamma / d b, d sigma.
     // The arg-min is searched again over the run (gamma_lds: the smallest
