@@ -180,7 +180,7 @@ bgt_status bgt_state_size(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
  * pflags(u8), rec(f32x16), gkey(u64), T_final(f32), last(i32), verts,
  * g_count, g_start, g_cursor, b_count, b_start, b_cursor, g_keys(u64),
  * g_list(u32), b_keys(u64), b_list(u32), gslot(f32x9 per record and tile
- * slot), gpos(i32 per record and tile slot), t_nlast(i32 per tile),
+ * slot), gpos(i32 per record and tile slot), t_end(i32 per tile),
  * gwide(f32x9 per record), dbound(f32x3 per pixel), brec64(f64x3), big_tris,
  * scan, end. */
 #define BGT_STATE_FIELDS 29

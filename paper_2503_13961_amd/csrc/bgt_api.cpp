@@ -29,7 +29,7 @@ using namespace bgt;
 
 enum Field {
     F_COUNTERS, F_ZBUF, F_ITRI, F_IUV, F_PFLAGS, F_REC, F_GKEY, F_TFINAL, F_LAST, F_VERTS, F_GCOUNT, F_GSTART,
-    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_GSLOT, F_GPOS, F_TNLAST,
+    F_GCURSOR, F_BCOUNT, F_BSTART, F_BCURSOR, F_GKEYS, F_GLIST, F_BKEYS, F_BLIST, F_GSLOT, F_GPOS, F_TEND,
     F_GWIDE, F_DBOUND, F_BREC64, F_BIGTRI,
     F_SCAN, F_END
 };
@@ -171,7 +171,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_BLIST, 4 * k.cap_b);
     put(F_GSLOT, 4 * kSlotTiles * kSums * NR);
     put(F_GPOS, 4 * kSlotTiles * NR);
-    put(F_TNLAST, 4 * NT);
+    put(F_TEND, 4 * NT);
     put(F_GWIDE, 4 * kSums * NR);
     put(F_DBOUND, 12 * N);
     put(F_BREC64, 24 * N);
@@ -213,7 +213,7 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.n_rec = sh.NR;
     p.gslot = (float *)(b + sh.off[F_GSLOT]);
     p.gpos = (int32_t *)(b + sh.off[F_GPOS]);
-    p.t_nlast = (int32_t *)(b + sh.off[F_TNLAST]);
+    p.t_end = (int32_t *)(b + sh.off[F_TEND]);
     p.gwide = (float *)(b + sh.off[F_GWIDE]);
     p.dbound = (float *)(b + sh.off[F_DBOUND]);
     p.brec64 = (double *)(b + sh.off[F_BREC64]);

@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
     const int t = xcd_runs<64>(blockIdx.x, gridDim.x), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gc = st.g_count[t];
     if (gc == 0) {  // no Gaussian reaches the tile: nothing to differentiate
-        if (tid == 0) st.t_nlast[t] = 0;
+        if (tid == 0) st.t_end[t] = 0;
         return;
     }
     const int v = view_of_tile(vt, t);
@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, St
 
     const int gs0 = st.g_start[t];
     const int nlast = max_last;
-    if (tid == 0) st.t_nlast[t] = nlast;  // the prefix of the list whose sums are written below
+    if (tid == 0) st.t_end[t] = gs0 + nlast;  // the prefix of the list whose sums are written below
     // dl/dC . S: the suffix colour S = C - prefix enters dl/dalpha only through
     // its dot product with dl/dC, so that product is carried instead of S
     float T = 1.0f, GS = g0 * im0 + g1 * im1 + g2 * im2;

@@ -214,7 +214,7 @@ struct StatePtrs {
     float *gslot;          // [kSlotTiles][records][kSums] the backward's sums of narrow records per tile slot,
                            // written for the tile's replayed prefix (zeros for entries no pixel reached)
     int32_t *gpos;         // [kSlotTiles][records] the record's position in the tile's sorted list (the sort)
-    int32_t *t_nlast;      // [tiles] entries of the tile's list whose sums the backward wrote
+    int32_t *t_end;        // [tiles] list position past the tile's replayed prefix, whose sums the backward wrote
     float *gwide;          // [records][kSums] the sums of wide records (zeroed by the generation, added by
                            // the backward, read and zeroed by the parameter pass)
     float *dbound;         // [pixels][3] dl/dsigma_b, dl/dmu (x, y) of each boundary point (zeroed by the

@@ -108,15 +108,19 @@ __device__ __forceinline__ int region_view(const ViewTable &vt, int reg, int &rx
 // raster order, so the result does not depend on scheduling.  A narrow
 // record (at most 3 x 3 tiles) has them at its slot of each tile, valid where
 // its position in the tile's list (which the sort wrote to the same slot)
-// lies in the tile's replayed prefix: the backward writes every entry of that
-// prefix and no other.  All loads of a tile are independent of each other.
-// A wide record's sums were added into its own floats, which are read and
-// cleared for the next backward pass.
+// lies before the end of the tile's replayed prefix: the backward writes
+// every entry of that prefix and no other.  The tiles are taken three at a
+// time with every load issued before any is used (a slot past the prefix is
+// loaded and not added), so a record of up to three tiles waits for one
+// round trip.  A wide record's sums were added into its own floats, which are
+// read and cleared for the next backward pass.  `ovf`: lists overflowed their
+// capacity and lack entries, whose slots hold no position of this pass; no
+// sums are taken then.
 __device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, const StatePtrs &st, int rid,
-                                           float *g) {
-    const float4 r3 = st.rec[(int64_t)rid * 4 + 3];
-    const int gx = __float_as_int(r3.x), gy = __float_as_int(r3.y);
-    if (!(lo16(gx) <= hi16(gx) && lo16(gy) <= hi16(gy))) return;
+                                           bool ovf, float *g) {
+    const int4 r3 = *(const int4 *)(st.rec + (int64_t)rid * 4 + 3);
+    const int gx = r3.x, gy = r3.y;
+    if (!((lo16(gx) <= hi16(gx)) & (lo16(gy) <= hi16(gy)))) return;
     const int TSH = __builtin_ctz(k.tile);
     if (!narrow_range(gx, gy, TSH)) {
         float *w = st.gwide + (int64_t)rid * kSums;
@@ -124,27 +128,27 @@ __device__ __forceinline__ void gauss_sums(const Consts &k, const ViewInfo &vi, 
         for (int f = 0; f < kSums; ++f) { g[f] = w[f]; w[f] = 0.f; }
         return;
     }
-    // lists that overflowed their capacity lack entries, whose slots hold
-    // no position of this pass: no sums are taken then
-    if (st.counters[C_OVERFLOW] & 1) return;
+    if (ovf) return;
     const int gt0 = lo16(gx) >> TSH, gu0 = lo16(gy) >> TSH;
-    const int nx = (hi16(gx) >> TSH) - gt0 + 1, ny = (hi16(gy) >> TSH) - gu0 + 1;
+    const int nx = (hi16(gx) >> TSH) - gt0 + 1, nt = nx * ((hi16(gy) >> TSH) - gu0 + 1);
+    for (int j0 = 0; j0 < nt; j0 += 3) {
+        int p[3], e[3];
+        float q[3][kSums];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {  // (row, column) of the 3 x 3 range
-        const int jx = j % 3, jy = j / 3;
-        if (jx >= nx || jy >= ny) continue;
-        const int tx = gt0 + jx, ty = gu0 + jy;
-        const int t = vi.tile_off + ty * vi.tiles_x + tx;
-        const int64_t si = (int64_t)tile_slot(tx, ty) * st.n_rec + rid;
-        const int p = st.gpos[si];
-        const float *q = st.gslot + si * kSums;
-        float qv[kSums];
+        for (int c = 0; c < 3; ++c) {
+            const int j = min(j0 + c, nt - 1);  // (past the range: the last tile again, not added)
+            const int tx = gt0 + j % nx, ty = gu0 + j / nx;
+            const int64_t si = (int64_t)tile_slot(tx, ty) * st.n_rec + rid;
+            p[c] = st.gpos[si];
+            e[c] = st.t_end[vi.tile_off + ty * vi.tiles_x + tx];
 #pragma unroll
-        for (int f = 0; f < kSums; ++f) qv[f] = q[f];
-        const int s0 = st.g_start[t], n = min(st.t_nlast[t], st.g_count[t]);
-        if ((unsigned)(p - s0) < (unsigned)n) {
+            for (int f = 0; f < kSums; ++f) q[c][f] = st.gslot[si * kSums + f];
+        }
 #pragma unroll
-            for (int f = 0; f < kSums; ++f) g[f] += qv[f];
+        for (int c = 0; c < 3; ++c) {
+            const bool ok = j0 + c < nt && p[c] < e[c];
+#pragma unroll
+            for (int f = 0; f < kSums; ++f) g[f] += ok ? q[c][f] : 0.f;
         }
     }
 }
@@ -164,6 +168,7 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
     __shared__ int slot_prim[SLOTS];
     __shared__ float table[SLOTS * NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool ovf = (st.counters[C_OVERFLOW] & 1) != 0;  // the Gaussian lists overflowed
     for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) slot_prim[i] = -1;
     for (int i = threadIdx.x; i < SLOTS * NV; i += blockDim.x) table[i] = 0.f;
     int rx0 = 0, ry0 = 0, rv = 0;
@@ -236,7 +241,15 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             // of dl/dG G, colour, opacity (the record's Gaussian; a pixel
             // record of the lattice variant has none), boundary radius and
             // position (a boundary point's)
-            if (LAT || k.NL == 0) gauss_sums(k, vt.v[v0], st, pix, g);
+            // (the pixel's triangle and uv are read before the cleared words
+            // are written: a load issued after a store waits for it too)
+            int tri = 0;
+            float2 uvp = make_float2(0.f, 0.f);
+            if constexpr (!LAT) {
+                tri = st.I_tri[pix];
+                uvp = st.I_uv[pix];
+            }
+            if (LAT || k.NL == 0) gauss_sums(k, vt.v[v0], st, pix, ovf, g);
             if (!LAT && (fl & PF_BOUNDARY)) {  // read and cleared for the next backward pass
                 float *bp = st.dbound + (int64_t)pix * 3;
                 g[9] = bp[0]; g[10] = bp[1]; g[11] = bp[2];
@@ -248,8 +261,8 @@ __global__ void __launch_bounds__(256) k_param_bwd(Consts k, ViewTable vt, PrimP
             if (nz) {
                 act = true;
                 if constexpr (!LAT) {
-                    prim = st.I_tri[pix] / k.L2;
-                    uv = st.I_uv[pix];
+                    prim = tri / k.L2;
+                    uv = uvp;
                 }
             }
         }

@@ -18,7 +18,7 @@ BGT_FLAG_NO_BOUNDARY = 1  # bgt_config.flags: the variant without blending coeff
 BGT_STATE_FIELDS = 29
 STATE_FIELD_NAMES = ["counters", "zbuf", "I_tri", "I_uv", "pflags", "rec", "gkey", "T_final", "last",
                      "verts", "g_count", "g_start", "g_cursor", "b_count", "b_start", "b_cursor",
-                     "g_keys", "g_list", "b_keys", "b_list", "gslot", "gpos", "t_nlast", "gwide", "dbound", "brec64",
+                     "g_keys", "g_list", "b_keys", "b_list", "gslot", "gpos", "t_end", "gwide", "dbound", "brec64",
                      "big_tris", "scan", "end"]
 EXPORTS = ["bgt_default_config", "bgt_validate_config", "bgt_validate_prims", "bgt_validate_views",
            "bgt_create", "bgt_destroy", "bgt_last_error", "bgt_tessellate", "bgt_state_size",
