@@ -289,14 +289,23 @@ __device__ __forceinline__ bool tri_setup(const Consts &k, const ViewInfo &vi, c
                                           TriSetup &ts) {
     int m[3];
     subtri_corners(k.L, s, m);
+    // (the three corners are loaded before any is tested, so the lane waits
+    // for one round trip)
+    int32_t X[3], Y[3];
+    double iz[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {  // (iz, X, Y: the record's last 16 bytes, one load)
+        const int4 w = *(const int4 *)((const char *)(vv + (int64_t)m[c] * k.P + p) + offsetof(VertRec, iz));
+        iz[c] = __hiloint2double(w.y, w.x);
+        X[c] = w.z;
+        Y[c] = w.w;
+    }
+    const bool culled = (X[0] == INT32_MIN) | (X[1] == INT32_MIN) | (X[2] == INT32_MIN);  // near-plane cull
     VertRec r[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        r[c] = vv[(int64_t)m[c] * k.P + p];
-        if (r[c].X == INT32_MIN) return false;  // near-plane cull
-    }
+    for (int c = 0; c < 3; ++c) { r[c].X = X[c]; r[c].Y = Y[c]; r[c].iz = iz[c]; }
     int64_t A = edge_fn(r[0].X, r[0].Y, r[1].X, r[1].Y, r[2].X, r[2].Y);
-    if (A == 0) return false;
+    if (culled | (A == 0)) return false;
     int o1 = 1, o2 = 2;
     if (A < 0) { o1 = 2; o2 = 1; A = -A; }
     const int ord[3] = {0, o1, o2};
