@@ -41,7 +41,7 @@ struct Shape {
     int64_t N, NT;
     int64_t NR;  // Gaussian records: the N pixel records, then the lattice Gaussians of every view
     int64_t off[BGT_STATE_FIELDS];
-    int64_t wverts_off, patch_off, bigsort_off;
+    int64_t wverts_off, patch_off;
 };
 
 bgt_status fail(bgt_ctx *ctx, bgt_status st, const char *msg) {
@@ -178,8 +178,7 @@ bgt_status make_shape(bgt_ctx *ctx, const bgt_prims *pr, const bgt_views *vw, Sh
     put(F_BIGTRI, 4 * k.cap_big);
     {
         sh.off[F_SCAN] = o;
-        sh.bigsort_off = align256(o + 16 * nb_scan);
-        o = align256(sh.bigsort_off + 8 * NT);
+        o = align256(o + 16 * nb_scan);
     }
     sh.off[F_END] = o;
     return BGT_OK;
@@ -219,7 +218,6 @@ StatePtrs state_ptrs(const Shape &sh, void *state) {
     p.brec64 = (double *)(b + sh.off[F_BREC64]);
     p.big_tris = (int32_t *)(b + sh.off[F_BIGTRI]);
     p.scan_tmp = (int32_t *)(b + sh.off[F_SCAN]);
-    p.bigsort_q = (int32_t *)(b + sh.bigsort_off);
     return p;
 }
 

@@ -451,14 +451,7 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
     if (L >= 2 * vt.total_tiles) return;
     const int which = L < vt.total_tiles ? 0 : 1, t = which == 0 ? L : L - vt.total_tiles;
     const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
-    if (cnt == 0) return;
-    if (cnt > kWaveSort) {
-        if (lane == 0) {
-            const long long q = atomicAdd((unsigned long long *)&st.counters[C_BIGSORT_Q + which], 1ull);
-            st.bigsort_q[(int64_t)which * vt.total_tiles + q] = t;
-        }
-        return;
-    }
+    if (cnt == 0 || cnt > kWaveSort) return;  // (longer lists: k_sort_long)
     const int start = which == 0 ? st.g_start[t] : st.b_start[t];
     const unsigned long long *src = (which == 0 ? st.g_keys : st.b_keys) + start;
     const int v = view_of_tile(vt, t);
@@ -478,7 +471,12 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
     else wave_sort_list<8>(src, cnt, lane, sb, emit);
 }
 
-// Lists longer than a wave sorts, one workgroup per queued list.  Up to
+// Lists longer than a wave sorts, one workgroup per list: workgroup b takes
+// the long lists among kLongChunk tiles, whose counts its threads read at
+// once (no queue, no global atomic).  Tile i of the launch is tile
+// i (2^31 - 1) mod n, a permutation (2^31 - 1 is a prime above n) that
+// spreads the long lists, which cluster in neighbouring tiles and at the
+// same place in similar views, over the workgroups.  Up to
 // kSortLds keys: runs of 64 keys sorted in registers, one wave per run
 // (padded with ~0, above every key), then merged pairwise by rank: a key's
 // place in the merged run is its place in its own run plus the number of keys
@@ -487,13 +485,25 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
 // keys (at most kSortLds / 256) first and all write after a barrier, so the
 // block needs one buffer (16 KB).  Longer lists (rare; a correctness path):
 // the bitonic network on global memory.
+constexpr int kLongChunk = 16;
+
 __global__ void __launch_bounds__(256) k_sort_long(ViewTable vt, StatePtrs st, int lat_per_view) {
     __shared__ unsigned long long keys[kSortLds];
+    __shared__ int long_tiles[kLongChunk], n_long;
     const int which = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nq = st.counters[C_BIGSORT_Q + which];
-    for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
-        const int t = st.bigsort_q[(int64_t)which * vt.total_tiles + qi];
+    if (threadIdx.x == 0) n_long = 0;
+    __syncthreads();
+    if (threadIdx.x < kLongChunk) {
+        const int i = blockIdx.x * kLongChunk + threadIdx.x;
+        if (i < vt.total_tiles) {
+            const int t = (int)((int64_t)i * 2147483647ll % vt.total_tiles);
+            if ((which == 0 ? st.g_count[t] : st.b_count[t]) > kWaveSort) long_tiles[atomicAdd(&n_long, 1)] = t;
+        }
+    }
+    __syncthreads();
+    for (int li = 0; li < n_long; ++li) {
+        const int t = long_tiles[li];
         const int cnt = which == 0 ? st.g_count[t] : st.b_count[t];
         const int start = which == 0 ? st.g_start[t] : st.b_start[t];
         unsigned long long *src = (which == 0 ? st.g_keys : st.b_keys) + start;
@@ -585,7 +595,8 @@ hipError_t launch_binning(const Consts &k, const ViewTable &vt, const StatePtrs 
     }
     hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)((2 * (int64_t)n + 3) / 4)), dim3(256), 0, s, vt, st,
                        lat_per_view);
-    hipLaunchKernelGGL(k_sort_long, dim3(512, 2), dim3(256), 0, s, vt, st, lat_per_view);
+    hipLaunchKernelGGL(k_sort_long, dim3((unsigned)((n + kLongChunk - 1) / kLongChunk), 2), dim3(256), 0, s, vt, st,
+                       lat_per_view);
     return hipGetLastError();
 }
 

@@ -25,8 +25,8 @@ enum Counter {
     C_BIGTRI = 5,
     C_BIGSORT = 6,
     C_BIGBLIST = 7,
-    C_BIGSORT_Q = 8,  // queue length for the global-memory sort (g in low, b via C_BIGSORT_QB)
-    C_BIGSORT_QB = 9,
+    C_UNUSED8 = 8,
+    C_UNUSED9 = 9,
     C_MANYRUNS = 10,  // tiles with more boundary runs than the forward's gamma* maps
     C_NUM = 16
 };
@@ -221,7 +221,6 @@ struct StatePtrs {
                            // generation, accumulated by the backward, read and zeroed by the parameter pass)
     double *brec64;        // [pixels][3] boundary points in FP64: mu - pixel centre (x, y), sigma
     int32_t *big_tris;     // [cap_big] queue of raster items
-    int32_t *bigsort_q;    // [2][n_tiles] queue of tiles sorted in global memory
     int32_t *scan_tmp;     // block sums
 };
 
