@@ -698,8 +698,17 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
 // 3 x 3 tiles adds into sums of its own by float atomics instead).
 // The boundary terms accumulate per (run, pixel) and go to the minimising
 // boundary point at the end of the tile.
+// Waves per SIMD the backward's registers must allow: at 16 px the LDS of
+// up to 64-entry batches lets six workgroups share a CU, which 80 registers
+// per lane keep (the compiler otherwise takes 82 and five); elsewhere no bound.
 template <int TS, int K>
-__global__ void __launch_bounds__(TS *TS) k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
+struct BwdWaves {
+    static constexpr int value = TS == 16 && K <= 64 ? 6 : 1;
+};
+
+template <int TS, int K>
+__global__ void __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(BwdWaves<TS, K>::value)))
+k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                                                      const float *grad_image) {
     using G = TileGeom<TS>;
     using BL = BoundaryLds<TS, K, RunMapsBwd<TS, K>::value>;
