@@ -455,16 +455,25 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K, BOUND> &S, const Slot
     S.yr[kk] = __float_as_int(P.r3.y);
 }
 
-// the backward's staging of slot kk from record gp, read at once
+// the backward's staging of slot kk from record gp's words P; returns
+// whether the record is wide (more than 3 x 3 tiles)
+template <int TS, int K>
+__device__ __forceinline__ bool stage_rec(BatchLds<TS, K, false> &S, const SlotPrefetch &P, int kk, int ox, int oy,
+                                          const int *run_prim, int n_runs, bool slow_b) {
+    stage_slot<TS, K, false>(S, P, kk, ox, oy, run_prim, n_runs, slow_b, 0.f);
+    return !narrow_range(__float_as_int(P.r3.x), __float_as_int(P.r3.y), TS == 8 ? 3 : (TS == 16 ? 4 : 5));
+}
+__device__ __forceinline__ void load_rec(const StatePtrs &st, int gp, SlotPrefetch &P) {
+    const float4 *rp = st.rec + (int64_t)gp * 4;
+    P.r0 = rp[0]; P.r1 = rp[1]; P.r2 = rp[2]; P.r3 = rp[3];
+}
+// ... read at once
 template <int TS, int K>
 __device__ __forceinline__ bool load_stage(BatchLds<TS, K, false> &S, const StatePtrs &st, int gp, int kk, int ox, int oy,
                                            const int *run_prim, int n_runs, bool slow_b) {
     SlotPrefetch P;
-    const float4 *rp = st.rec + (int64_t)gp * 4;
-    P.r0 = rp[0]; P.r1 = rp[1]; P.r2 = rp[2]; P.r3 = rp[3];
-    stage_slot<TS, K, false>(S, P, kk, ox, oy, run_prim, n_runs, slow_b, 0.f);
-    // is the record wide (more than 3 x 3 tiles)?
-    return !narrow_range(__float_as_int(P.r3.x), __float_as_int(P.r3.y), TS == 8 ? 3 : (TS == 16 ? 4 : 5));
+    load_rec(st, gp, P);
+    return stage_rec<TS, K>(S, P, kk, ox, oy, run_prim, n_runs, slow_b);
 }
 
 // does the pixel range (packed int16 pairs) touch the 4x4 sub-block at (x0, y0)?
@@ -599,12 +608,17 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
         }
         return;
     }
+    // the first batch's records are read before the boundary points are
+    // staged, so that the two waits overlap
+    const int gs0 = st.g_start[t], gc = st.g_count[t];
+    SlotPrefetch pf;
+    pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
+    pf.issue(st, gs0, gc, 0, tid, K);
     stage_boundary(B, st, bs0, bc, ox, oy, vi);
     const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     if (B.n_runs > RM && tid == 0) atomicAdd((unsigned long long *)&st.counters[C_MANYRUNS], 1ull);
     build_gamma_maps<TS>(B);
 
-    const int gs0 = st.g_start[t], gc = st.g_count[t];
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     bool done = !inside;
     int last = gc;
@@ -616,9 +630,6 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     // support test d^T Q d <= 2 ln(1/g_min) as a base-2 exponent: G = 2^e, e >= log2(g_min)
     const float e_min = kE * k.kappa2;
     const float kappa = sqrtf(k.kappa2);
-    SlotPrefetch pf;
-    pf.gp_next = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
-    pf.issue(st, gs0, gc, 0, tid, K);
     if (pf.gp >= 0) stage_slot<TS, K, true>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, kappa);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
@@ -779,13 +790,19 @@ k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
+    // the first batch's records are read before the boundary points are
+    // staged, so that the two waits overlap (entries past the replayed
+    // prefix, known once the stop indices are combined, are dropped then)
+    const int gs0 = st.g_start[t];
+    const int gp0 = (tid < K && tid < gc) ? (int)st.g_list[gs0 + tid] : -1;
+    SlotPrefetch P0;
+    if (gp0 >= 0) load_rec(st, gp0, P0);
     const int bs0 = st.b_start[t], bc = st.b_count[t];
     stage_boundary(B, st, bs0, bc, ox, oy, vi);  // (syncs)
     const bool slow_b = bc > BoundaryCap<TS, K>::value;
     const int n_full = slow_b ? B.n_runs - 1 : B.n_runs;  // runs staged in full
     build_gamma_maps<TS>(B);
 
-    const int gs0 = st.g_start[t];
     const int nlast = max_last;
     if (tid == 0) st.t_end[t] = gs0 + nlast;  // the prefix of the list whose sums are written below
     // dl/dC . S: the suffix colour S = C - prefix enters dl/dalpha only through
@@ -797,9 +814,9 @@ k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
     const float LN2 = 0.69314718055994531f;
     // the loaders read their records at the end of the previous batch, not
     // ahead of it: registers held across the replay would cost a wave per SIMD
-    int cur_gp = (tid < K && tid < nlast) ? (int)st.g_list[gs0 + tid] : -1;
+    int cur_gp = tid < nlast ? gp0 : -1;
     bool wide = false;
-    if (cur_gp >= 0) wide = load_stage<TS, K>(S, st, cur_gp, tid, ox, oy, B.run_prim, n_full, slow_b);
+    if (cur_gp >= 0) wide = stage_rec<TS, K>(S, P0, tid, ox, oy, B.run_prim, n_full, slow_b);
     unsigned long long wide_b = __ballot(wide);  // the wave's loaders of wide records
     for (int base = 0; base < nlast; base += K) {
         __syncthreads();  // publishes the staged batch
