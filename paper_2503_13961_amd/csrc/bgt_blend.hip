@@ -839,6 +839,11 @@ k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                 const float dx = qx - m.x, dy = qy - m.y;
                 const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);  // as in the forward
                 bool live = base + kk < mylast && (own || r != -1) && e >= e_min;
+                // at 16 and 32 px an entry that no lane's support reaches
+                // leaves before the gamma* lookups (common where the
+                // Gaussians are small against the 8x8 blocks; at 8 px the
+                // branch costs more than it saves)
+                if (TS >= 16 && !__any(live)) continue;
                 const bool mapped = r >= 0 && r < RM;
                 const bool tracked = r >= 0 && r < RD;  // (uniform) dgr holds its dl/dgamma*
                 float gam = 1.0f;
