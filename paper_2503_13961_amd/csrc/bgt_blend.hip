@@ -659,6 +659,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         const float e = fmaf(dx, fmaf(ex.x, dx, ex.y * dy), ex.z * dy * dy);
                         // w = 0 without a boundary point of g near this tile, or outside the support
                         bool live = act && !done && (own || r != -1) && e >= e_min;
+                        // (at 16 and 32 px a step in which no lane's support
+                        // is reached leaves before the gamma* lookups, as in
+                        // the backward; T and C would not change)
+                        if (TS >= 16 && !__any(live)) continue;
                         const bool mapped = r >= 0 && r < RM;
                         float gam = __uint_as_float(B.map[min(max(r, 0), RM - 1)][tid]);
                         gam = mapped ? gam : 1.0f;
