@@ -268,8 +268,25 @@ __global__ void __launch_bounds__(256) k_scatter_lattice(Consts k, ViewTable vt,
         const int lr = vi.W * vi.H + (int)(i - v * per_view);
         gkey = (st.gkey[rid] << 24) | (unsigned long long)lr;
     }
+    // rectangles within the 3x3 tiles around the middle of the wave's first
+    // rectangle (the wave's records are neighbouring nodes of one or two
+    // patches), in that rectangle's view: one round of cursor atomics; the
+    // rest one cursor atomic per group of lanes at the same tile
+    TileRect g;
+    g.x0 = gt0; g.x1 = gt1; g.y0 = gu0; g.y1 = gu1;
+    const unsigned long long has = __ballot(gt0 <= gt1);
+    if (has) {
+        const int f = __ffsll((long long)has) - 1;
+        const int cx = __builtin_amdgcn_readlane((gt0 + gt1) >> 1, f);
+        const int cy = __builtin_amdgcn_readlane((gu0 + gu1) >> 1, f);
+        const int vw = __builtin_amdgcn_readlane(v, f);
+        const bool near = gt0 <= gt1 && v == vw && gt0 >= cx - 1 && gt1 <= cx + 1 && gu0 >= cy - 1 && gu1 <= cy + 1;
+        near_tiles(near, g, false, TileRect(), cx, cy, vt.v[vw], st, lane, [&](int slot) { st.g_keys[slot] = gkey; },
+                   [&](int) {});
+        if (near) g = TileRect();
+    }
     const unsigned long long below = (1ull << lane) - 1ull;
-    for_tiles_grouped(gt0, gt1, gu0, gu1, vi.tiles_x, vi.tile_off,
+    for_tiles_grouped(g.x0, g.x1, g.y0, g.y1, vi.tiles_x, vi.tile_off,
                       [&](int t, unsigned long long gm, bool in, int leader) {
         int base = 0;
         if (lane == leader) base = atomicAdd(&st.g_cursor[t], __popcll(gm));
