@@ -493,19 +493,22 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
 // once (no queue, no global atomic).  Tile i of the launch is tile
 // i (2^31 - 1) mod n, a permutation (2^31 - 1 is a prime above n) that
 // spreads the long lists, which cluster in neighbouring tiles and at the
-// same place in similar views, over the workgroups.  Up to
-// kSortLds keys: runs of 64 keys sorted in registers, one wave per run
-// (padded with ~0, above every key), then merged pairwise by rank: a key's
-// place in the merged run is its place in its own run plus the number of keys
-// of the other run before it (keys of the first run go before equal keys of
-// the second; only the padding repeats).  In place: every thread ranks its
-// keys (at most kSortLds / 256) first and all write after a barrier, so the
-// block needs one buffer (16 KB).  Longer lists (rare; a correctness path):
+// same place in similar views, over the workgroups.  Up to kSortLds keys:
+// runs of kWaveSort keys sorted in registers, one wave per run (padded with
+// ~0, above every key), then merged pairwise, level by level.  A thread
+// writes `per` consecutive outputs of a level (a power of two, at most
+// kSortLds / 256): a binary search along the merge path finds how many of
+// them come from the pair's first run, then one comparison per output walks
+// both runs (keys of the first run go before equal keys of the second).  In
+// place: every thread merges its outputs into registers first and all write
+// after a barrier, so the block needs one buffer (18 KB); the last level's
+// outputs go to the list at once.  Longer lists (rare; a correctness path):
 // the bitonic network on global memory.
 constexpr int kLongChunk = 16;
+static_assert(kSortLds == 4 * kWaveSort, "the four waves of a workgroup sort one run each");
 
 __global__ void __launch_bounds__(256) k_sort_long(ViewTable vt, StatePtrs st, int lat_per_view) {
-    __shared__ unsigned long long keys[kSortLds];
+    __shared__ unsigned long long keys[kSortLds + kSortLds / 8 + 1];
     __shared__ int long_tiles[kLongChunk], n_long;
     const int which = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -545,36 +548,70 @@ __global__ void __launch_bounds__(256) k_sort_long(ViewTable vt, StatePtrs st, i
             __syncthreads();
             continue;
         }
-        constexpr int PER = kSortLds / 256;
-        const int n64 = (cnt + 63) & ~63, nruns = n64 >> 6;
-        for (int run = wave; run < nruns; run += blockDim.x >> 6) {
-            const int i = run * 64 + lane;
-            keys[i] = wave_sort64(i < cnt ? src[i] : ~0ull, lane);
+        // runs of 512 keys, one wave each: loaded into the buffer in 64-lane
+        // runs, read by each lane as 8 consecutive keys, sorted in registers
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) keys[stage_slot(i)] = src[i];
+        __syncthreads();
+        if (wave * kWaveSort < cnt) {
+            unsigned long long x[8];
+            const int b0 = wave * kWaveSort + lane * 8;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = b0 + r < cnt ? keys[stage_slot(b0 + r)] : ~0ull;
+            wave_sort_regs<8>(x, lane);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (b0 + r < cnt) keys[stage_slot(b0 + r)] = x[r];
         }
         __syncthreads();
-        for (int L = 64; L < n64; L <<= 1) {
-            unsigned long long x[PER];
-            int pos[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int i = threadIdx.x + q * 256;
-                pos[q] = -1;
-                x[q] = 0ull;
-                if (i < n64) {
-                    const int p0 = i & ~(2 * L - 1);
-                    const int mid = min(p0 + L, n64), end = min(p0 + 2 * L, n64);
-                    x[q] = keys[i];
-                    pos[q] = i < mid ? i + rank_in<false>(keys + mid, end - mid, x[q])
-                                     : p0 + (i - mid) + rank_in<true>(keys + p0, mid - p0, x[q]);
+        // outputs per thread: a power of two, so that no thread's outputs
+        // straddle two pairs of runs
+        int per = 1;
+        while (per * 256 < cnt) per <<= 1;
+        for (int L = kWaveSort; L < cnt; L <<= 1) {
+            unsigned long long x[kSortLds / 256];
+            const int d0 = threadIdx.x * per;
+            int m = 0;
+            if (d0 < cnt) {
+                const int p0 = d0 & ~(2 * L - 1);
+                const int mid = min(p0 + L, cnt), end = min(p0 + 2 * L, cnt);
+                const int la = mid - p0, lb = end - mid, d = d0 - p0;
+                // how many of the pair's first d outputs come from the first
+                // run (the first run's keys go before equal keys of the second)
+                int lo = max(0, d - lb), hi = min(d, la);
+                while (lo < hi) {
+                    const int c = (lo + hi) >> 1;
+                    if (keys[stage_slot(p0 + c)] <= keys[stage_slot(mid + d - 1 - c)]) lo = c + 1;
+                    else hi = c;
                 }
-            }
-            __syncthreads();
+                int i = lo, j = d - lo;
+                // (reads one past a run's end stay in the buffer, which has a
+                // slot past the last key; their values are never taken)
+                unsigned long long ka = keys[stage_slot(p0 + i)], kb = keys[stage_slot(mid + j)];
+                m = min(per, end - d0);
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (pos[q] >= 0) keys[pos[q]] = x[q];
-            __syncthreads();
+                for (int k = 0; k < kSortLds / 256; ++k)
+                    if (k < m) {
+                        const bool take_a = i < la && (j >= lb || ka <= kb);
+                        x[k] = take_a ? ka : kb;
+                        i += take_a;
+                        j += !take_a;
+                        const unsigned long long nx = keys[stage_slot(take_a ? p0 + i : mid + j)];
+                        ka = take_a ? nx : ka;
+                        kb = take_a ? kb : nx;
+                    }
+            }
+            if (2 * L >= cnt) {  // the last level: its outputs are the list
+#pragma unroll
+                for (int k = 0; k < kSortLds / 256; ++k)
+                    if (k < m) emit(d0 + k, x[k]);
+            } else {  // in place: all read, then all write
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kSortLds / 256; ++k)
+                    if (k < m) keys[stage_slot(d0 + k)] = x[k];
+                __syncthreads();
+            }
         }
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) emit(i, keys[i]);
         __syncthreads();  // the next list reuses the buffer
     }
 }
