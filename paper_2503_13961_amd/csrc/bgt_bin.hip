@@ -459,6 +459,65 @@ __device__ __forceinline__ void wave_sort_list(const unsigned long long *src, in
     }
 }
 
+// Sorts one list of 256 < cnt <= 256 + 64 RB keys without sorting padding up
+// to 512: the first 256 keys (4 per lane) and the rest (RB per lane) are
+// sorted in registers as two runs, then merged along the merge path, each
+// lane writing per = ceil(cnt / 64) consecutive outputs: a binary search
+// finds how many of them come from the first run, then one comparison per
+// output walks both runs (keys of the first run go before equal keys of the
+// second).
+template <int RB, typename Emit>
+__device__ __forceinline__ void wave_sort_split(const unsigned long long *src, int cnt, int lane,
+                                                unsigned long long *sb, Emit &&emit) {
+    constexpr int RA = 4, NA = 64 * RA;
+    unsigned long long x[RA], y[RB];
+#pragma unroll
+    for (int r = 0; r < RA + RB; ++r) {
+        const int i = r * 64 + lane;
+        sb[stage_slot(i)] = i < cnt ? src[i] : ~0ull;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < RA; ++r) x[r] = sb[stage_slot(lane * RA + r)];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) y[r] = sb[stage_slot(NA + lane * RB + r)];
+    wave_sort_regs<RA>(x, lane);
+    wave_sort_regs<RB>(y, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < RA; ++r) sb[stage_slot(lane * RA + r)] = x[r];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) sb[stage_slot(NA + lane * RB + r)] = y[r];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int lb = cnt - NA, per = (cnt + 63) >> 6, d = lane * per;
+    if (d >= cnt) return;
+    int lo = max(0, d - lb), hi = min(d, NA);
+    while (lo < hi) {
+        const int c = (lo + hi) >> 1;
+        if (sb[stage_slot(c)] <= sb[stage_slot(NA + d - 1 - c)]) lo = c + 1;
+        else hi = c;
+    }
+    int i = lo, j = d - lo;
+    // (a read one past the first run is the second run's first key, one past
+    // the second a padding slot; neither is taken)
+    unsigned long long ka = sb[stage_slot(i)], kb = sb[stage_slot(NA + j)];
+    const int m = min(per, cnt - d);
+#pragma unroll
+    for (int k = 0; k < RA + RB; ++k)
+        if (k < m) {
+            const bool take_a = i < NA && (j >= lb || ka <= kb);
+            emit(d + k, take_a ? ka : kb);
+            i += take_a;
+            j += !take_a;
+            const unsigned long long nx = sb[stage_slot(take_a ? i : NA + j)];
+            ka = take_a ? nx : ka;
+            kb = take_a ? kb : nx;
+        }
+}
+
 // One wave per list: list L < n_tiles is the Gaussian list of tile L, the
 // others the boundary lists.  Empty lists cost a wave a few instructions.
 __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, int lat_per_view) {
@@ -485,6 +544,8 @@ __global__ void __launch_bounds__(256) k_sort_lists(ViewTable vt, StatePtrs st, 
     if (cnt <= 64) wave_sort_list<1>(src, cnt, lane, sb, emit);
     else if (cnt <= 128) wave_sort_list<2>(src, cnt, lane, sb, emit);
     else if (cnt <= 256) wave_sort_list<4>(src, cnt, lane, sb, emit);
+    else if (cnt <= 320) wave_sort_split<1>(src, cnt, lane, sb, emit);
+    else if (cnt <= 384) wave_sort_split<2>(src, cnt, lane, sb, emit);
     else wave_sort_list<8>(src, cnt, lane, sb, emit);
 }
 

@@ -348,32 +348,69 @@ __device__ __forceinline__ unsigned long long raster_pixel(const TriSetup &ts, i
     return ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - tri);
 }
 
+// Triangles whose corners lie within this many 1/256 px of each other on
+// both axes have edge functions that FP64 holds exactly at every pixel centre
+// of their bounding box: each product is an integer below 2^50 and their
+// difference one below 2^51.  Wider ones (rare: a small box clipped from a
+// huge triangle) go to the int64 path of k_raster_big.
+constexpr int64_t kExactExtent = 1ll << 25;
+
+// Edge function of the directed edge a -> b at p, as raster_pixel's int64
+// edge_fn, in FP64: exact for coordinates within kExactExtent of each other
+// (the int32 differences cannot overflow: coordinates are below 2^28).
+__device__ __forceinline__ double edge_f64(int ax, int ay, int bx, int by, int px, int py) {
+    return fma((double)(bx - ax), (double)(py - ay), -((double)(by - ay) * (double)(px - ax)));
+}
+
+// Inclusive max-scan of x over the wave's lanes (lane l gets the largest x of
+// lanes 0..l): shifts by 1, 2, 4 and 8 within each row of 16 lanes, then row
+// 15's and row 31's last lanes carried into the rows after them.  A lane
+// reads only lanes below it.
+__device__ __forceinline__ int wave_max_scan(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x111, 0xF, 0xF, false));  // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x112, 0xF, 0xF, false));  // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x114, 0xF, 0xF, false));  // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x118, 0xF, 0xF, false));  // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return x;
+}
+
 // Set-ups of a wave's 64 triangles, for the lanes that rasterize their pixels.
+// (5 KB: eight waves' worth fit a CU's LDS four workgroups at a time)
 struct RasterWaveLds {
     int32_t start[64];      // first pixel of the triangle in the wave's pixel sequence
     int32_t X[3][64], Y[3][64];
     double iz[3][64];
-    int64_t A[64];
-    int32_t own[64];        // top-left ownership bits of the three edges
-    int32_t i0[64], j0[64], bw[64];
-    int32_t px_off[64], W[64];
+    double A[64];           // twice the area, in 1/256^2 px^2 (an integer below 2^51)
+    int32_t ij0[64];        // box corner: i0 | j0 << 16
+    int32_t bwo[64];        // box width | top-left ownership bits of the edges << 9 | image width << 12
+    int32_t px_off[64];
+    int32_t mark[64];       // per chunk of 64 pixels: the last triangle starting at each pixel
     uint32_t tri[64];
 };
+static_assert(sizeof(RasterWaveLds) == 5120, "four waves' set-ups in 20 KB");
 
 // One lane per (view, sub-triangle) sets the triangle up; then the wave
 // rasterizes the bounding boxes of its 64 triangles together, one pixel per
 // lane over the concatenated boxes, so that lanes are not held by the
 // largest box of the wave.  Coverage and the z-buffer word are those of
-// raster_pixel (exact int64 edge functions, FP64 1/z plane).
+// raster_pixel (exact edge functions, here in FP64; FP64 1/z plane).
 __global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const VertRec *verts,
                                                 unsigned long long *zbuf, int32_t *big, int64_t *counters) {
     __shared__ RasterWaveLds R[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     RasterWaveLds &Rw = R[wave];
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t per_view = (int64_t)k.L2 * k.P;
+    const int64_t per_view = (int64_t)k.L2 * k.P, n_tri = per_view * vt.n;
+    // lane l of the launch takes triangle group (l / 8) (2^31 - 1) mod
+    // n_groups, member l mod 8 (a permutation: 2^31 - 1 is a prime above the
+    // group count): a wave's eight groups come from all over the views, so
+    // that the waves' pixel counts vary less than those of 64 neighbouring
+    // patches, while each group's corner loads stay contiguous
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, ng = (n_tri + 7) >> 3;
+    const int64_t idx = (gi >> 3) < ng ? ((gi >> 3) * 2147483647ll % ng) * 8 + (gi & 7) : n_tri;
     int area = 0;
-    if (idx < per_view * vt.n) {
+    if (idx < n_tri) {
         const int v = (int)(idx / per_view);
         const int64_t sp = idx % per_view;
         const int s = (int)(sp / k.P), p = (int)(sp % k.P);
@@ -381,7 +418,9 @@ __global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const Ve
         TriSetup ts;
         if (tri_setup(k, vi, verts + (int64_t)v * k.VL * k.P, s, p, ts)) {
             const int64_t a = (int64_t)(ts.i1 - ts.i0 + 1) * (ts.j1 - ts.j0 + 1);
-            if (a > kBigTriPixels) {
+            const int64_t ext = max(max(ts.X[0], max(ts.X[1], ts.X[2])) - min(ts.X[0], min(ts.X[1], ts.X[2])),
+                                    max(ts.Y[0], max(ts.Y[1], ts.Y[2])) - min(ts.Y[0], min(ts.Y[1], ts.Y[2])));
+            if (a > kBigTriPixels || ext >= kExactExtent) {
                 const long long slot = atomicAdd((unsigned long long *)&counters[C_BIGTRI], 1ull);
                 if (slot < k.cap_big) big[slot] = (int32_t)idx;
                 else atomicOr((unsigned long long *)&counters[C_OVERFLOW], 4ull);
@@ -393,13 +432,12 @@ __global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const Ve
                     Rw.Y[c][lane] = (int32_t)ts.Y[c];
                     Rw.iz[c][lane] = ts.iz[c];
                 }
-                Rw.A[lane] = ts.A;
-                Rw.own[lane] = (ts.own[0] ? 1 : 0) | (ts.own[1] ? 2 : 0) | (ts.own[2] ? 4 : 0);
-                Rw.i0[lane] = ts.i0;
-                Rw.j0[lane] = ts.j0;
-                Rw.bw[lane] = ts.i1 - ts.i0 + 1;
+                Rw.A[lane] = (double)ts.A;
+                Rw.ij0[lane] = ts.i0 | ts.j0 << 16;  // (images are at most 16384 px a side)
+                // (box width at most 256, image width at most 16384)
+                Rw.bwo[lane] = (ts.i1 - ts.i0 + 1) | ((ts.own[0] ? 1 : 0) | (ts.own[1] ? 2 : 0) | (ts.own[2] ? 4 : 0)) << 9 |
+                               vi.W << 12;
                 Rw.px_off[lane] = vi.px_off;
-                Rw.W[lane] = vi.W;
                 Rw.tri[lane] = (uint32_t)(p * k.L2 + s);
             }
         }
@@ -410,34 +448,49 @@ __global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const Ve
         const int y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
     }
-    Rw.start[lane] = incl - area;
+    const int my_start = incl - area;
+    Rw.start[lane] = my_start;
     const int total = __shfl(incl, 63, 64);
     __syncthreads();
     for (int base = 0; base < total; base += 64) {
+        // the triangle holding pixel e = base + lane: the last one starting
+        // at or before it (a triangle with an empty box starts where the next
+        // one does).  Each triangle marks its start within the chunk (those
+        // before it mark pixel 0) with its index, the largest index winning;
+        // a max-scan of the marks over the lanes then gives every pixel's.
+        // (LDS operations of one wave complete in order: the fences keep the
+        // compiler from moving them across each other)
+        Rw.mark[lane] = -1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (my_start - base < 64) atomicMax(&Rw.mark[max(my_start - base, 0)], lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int q = wave_max_scan(Rw.mark[lane]);  // (pixel 0's mark is set: triangle 0 starts at 0)
         const int e = base + lane;
-        if (e >= total) break;
-        // the triangle holding pixel e: the last one starting at or before it
-        // (a triangle with an empty box starts where the next one does)
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (Rw.start[mid] <= e) lo = mid;
-            else hi = mid - 1;
+        if (e >= total) continue;  // (the last chunk's tail; the scan above needed every lane)
+        const int r = e - Rw.start[q], bwo = Rw.bwo[q], bw = bwo & 0x1FF, ij0 = Rw.ij0[q];
+        // row of pixel r of the box: (r + 1/2) / bw lies at least 1/512 from
+        // an integer (r < 256), far beyond the reciprocal's error
+        const int dy = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)bw));
+        const int i = (ij0 & 0xFFFF) + (r - dy * bw), j = (ij0 >> 16) + dy;
+        // raster_pixel's coverage and z-buffer word, with the edge functions
+        // in FP64 (exact here: the triangle is narrower than kExactExtent)
+        const int px = 256 * i + 128, py = 256 * j + 128;
+        const int X0 = Rw.X[0][q], X1 = Rw.X[1][q], X2 = Rw.X[2][q];
+        const int Y0 = Rw.Y[0][q], Y1 = Rw.Y[1][q], Y2 = Rw.Y[2][q];
+        const double E0 = edge_f64(X1, Y1, X2, Y2, px, py);
+        const double E1 = edge_f64(X2, Y2, X0, Y0, px, py);
+        const double E2 = edge_f64(X0, Y0, X1, Y1, px, py);
+        const int own = (bwo >> 9) & 7;
+        const bool in = (E0 > 0.0 || (E0 == 0.0 && (own & 1))) && (E1 > 0.0 || (E1 == 0.0 && (own & 2))) &&
+                        (E2 > 0.0 || (E2 == 0.0 && (own & 4)));
+        if (in) {
+            const double key = fma(E2, Rw.iz[2][q], fma(E1, Rw.iz[1][q], E0 * Rw.iz[0][q])) / Rw.A[q];
+            const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
+            const unsigned long long c = ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - Rw.tri[q]);
+            atomicMax(&zbuf[Rw.px_off[q] + (int64_t)j * (bwo >> 12) + i], c);
         }
-        const int q = lo, r = e - Rw.start[q], bw = Rw.bw[q];
-        const int dy = (int)(((float)r + 0.5f) / (float)bw);  // exact: r < 256, never within 1/512 of an integer
-        const int i = Rw.i0[q] + (r - dy * bw), j = Rw.j0[q] + dy;
-        TriSetup ts;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            ts.X[c] = Rw.X[c][q];
-            ts.Y[c] = Rw.Y[c][q];
-            ts.iz[c] = Rw.iz[c][q];
-            ts.own[c] = (Rw.own[q] >> c) & 1;
-        }
-        ts.A = Rw.A[q];
-        const unsigned long long c = raster_pixel(ts, i, j, Rw.tri[q]);
-        if (c) atomicMax(&zbuf[Rw.px_off[q] + (int64_t)j * Rw.W[q] + i], c);
     }
 }
 
