@@ -203,7 +203,8 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
  * triangle queue) of this state's last forward pass together with those of
  * every forward pass on the context not yet reported, [1] Gaussian pairs,
  * [2] boundary pairs, [3] foreground pixels, [4] boundary pixels, [5] big
- * triangles, [6] tiles needing the global sort, [7] tiles whose boundary
+ * triangles (a bounding box over 256 pixels, or corners 2^17 pixels or more
+ * apart on an axis), [6] tiles needing the global sort, [7] tiles whose boundary
  * list exceeded LDS, [8] tiles with more boundary runs (primitives) than
  * the forward's gamma* maps hold (their other runs are searched per pixel),
  * [9] reserved (0).  Returns BGT_E_OVERFLOW when any overflow flag is set

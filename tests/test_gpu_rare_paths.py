@@ -1,6 +1,6 @@
 """Rare paths of the HIP path against the oracle: tile lists longer than the
-LDS sort holds (the global-memory sort), and patches with NaN or infinite
-control points."""
+LDS sort holds (the global-memory sort), patches with NaN or infinite
+control points, and thin sub-triangles reaching far outside the view."""
 import numpy as np
 import pytest
 
@@ -92,3 +92,37 @@ def test_nonfinite_control_points():
         assert np.isfinite(v).all(), k
         assert not v.reshape(ref[k].shape)[..., bad_nan + bad_inf].any(), k
     G.check_grads(g["grads"], ref)
+
+
+def test_far_reaching_slivers():
+    """Sub-triangles with a small box in the image whose corners lie more
+    than 2^17 px apart (thin bands across the view from corners 600000 px
+    outside it) are rasterized by the int64 path, not the per-wave FP64 one,
+    whose edge functions are exact only for narrower triangles: the library
+    counts them as big triangles (27 of the three bands' sub-triangles have a
+    box in the view, each under 256 px), and the index map is bit-exact
+    against the oracle's."""
+    from tests import helpers as H
+    G.log("[rare] far-reaching slivers")
+    W, Hh = 64, 48
+    cam = H.axis_camera(W, Hh, 40.0)
+    pts = lambda cs, z: [H.pixel_ray_point(cam, x, y, z) for x, y in cs]
+    sc = S.concat([H.flat_patch_scene(pts(c, z), color=col) for c, z, col in (
+        ([(-600000.0, 10.0), (600000.0, 10.0), (30.3, 13.5)], 2.0, (1, 0, 0)),
+        ([(20.2, -600000.0), (20.2, 600000.0), (23.9, 24.6)], 2.5, (0, 1, 0)),
+        ([(-600000.0, 30.1), (600000.0, 33.2), (41.7, 36.6)], 1.5, (0, 0, 1)),
+        ([(-5.0, -5.0), (70.0, -3.0), (20.0, 60.0)], 4.0, (1, 1, 1)),  # an ordinary patch behind them
+    )])
+    cams = S.Cameras(cam[None, :].copy(), np.array([[W, Hh]], np.int32), [(0.0, 0.0, 0.0)])
+    cfg = G.oracle_config(tile=16)
+    img_ref, frames = oracle.render_views(sc, cams, cfg)
+    g = G.run_gpu(sc, cams, tile=16)
+    assert g["status"] == 0 and g["counters"][0] == 0, g["counters"]
+    G.log(f"    {g['counters'][5]} big triangles")
+    assert g["counters"][5] >= 27
+    it = frames[0].raster()[0]
+    assert set(range(4)) <= set((it[it >= 0] // 16).tolist())  # every band wins pixels
+    np.testing.assert_array_equal(g["I_tri"], it)
+    err = np.abs(g["images"] - img_ref).max()
+    G.log(f"    image max abs err {err:.3e}")
+    assert err <= IMG_TOL
