@@ -489,7 +489,10 @@ __global__ void __launch_bounds__(256) k_raster(Consts k, ViewTable vt, const Ve
             const double key = fma(E2, Rw.iz[2][q], fma(E1, Rw.iz[1][q], E0 * Rw.iz[0][q])) / Rw.A[q];
             const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
             const unsigned long long c = ((kb >> 24) << 24) | (unsigned long long)(0xFFFFFFu - Rw.tri[q]);
-            atomicMax(&zbuf[Rw.px_off[q] + (int64_t)j * (bwo >> 12) + i], c);
+            // the z-buffer only grows: a word already at or above c (however
+            // stale the read) means the atomic would change nothing
+            unsigned long long *z = &zbuf[Rw.px_off[q] + (int64_t)j * (bwo >> 12) + i];
+            if (__hip_atomic_load(z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c) atomicMax(z, c);
         }
     }
 }
