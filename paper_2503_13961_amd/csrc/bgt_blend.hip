@@ -673,7 +673,10 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         // w = 0 (gamma* = 1 for another patch's Gaussian) gives
                         // a = 0 with no test: T and C stay as they are
                         const float w = own ? gam : 1.0f - gam;
-                        float a = fminf(ex.w * w * support_exp2(e), amax);
+                        // min(raw, alpha_max) as integers: the same as fminf for
+                        // every non-NaN raw, alpha_max being positive (one
+                        // instruction; fminf also canonicalizes alpha_max)
+                        float a = __int_as_float(min(__float_as_int(ex.w * w * support_exp2(e)), __float_as_int(amax)));
                         a = live ? a : 0.0f;
                         const float ta = T * a;
                         C0 += ta * c.x;
@@ -866,7 +869,9 @@ k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
                 const float Gv = support_exp2(e);
                 const float raw = o * w * Gv;
                 const bool clamped = raw > amax;
-                float a = clamped ? amax : raw;
+                // min(raw, alpha_max) as integers, as in the forward (the same
+                // as the clamp for every non-NaN raw, alpha_max being positive)
+                float a = __int_as_float(min(__float_as_int(raw), __float_as_int(amax)));
                 a = live ? a : 0.0f;
                 const float ta = T * a;
                 const float d_c0 = ta * g0, d_c1 = ta * g1, d_c2 = ta * g2;
