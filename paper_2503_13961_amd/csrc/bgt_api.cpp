@@ -440,11 +440,14 @@ bgt_status bgt_render_fwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     const StatePtrs sp = state_ptrs(sh, state);
     const PrimPtrs pp = prim_ptrs(prims);
     hipError_t e;
-    if ((e = launch_fill_u64((unsigned long long *)sp.counters, 0ull, kCounterWords, st)) != hipSuccess)
-        return hip_fail(ctx, e, "fill");
-    if ((e = launch_fill_u64(sp.zbuf, 0ull, sh.N, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
-    if ((e = launch_fill_i32(sp.g_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
-    if ((e = launch_fill_i32(sp.b_count, 0, sh.NT, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
+    {  // counters, z-buffer and tile counts start at zero
+        ZeroTable z;
+        z.add(sp.counters, 2 * (int64_t)kCounterWords);
+        z.add(sp.zbuf, 2 * (int64_t)sh.N);
+        z.add(sp.g_count, sh.NT);
+        z.add(sp.b_count, sh.NT);
+        if ((e = launch_zero(z, st)) != hipSuccess) return hip_fail(ctx, e, "clear");
+    }
     {
         StageTimer tm(ctx, 0, st);
         if ((e = launch_raster(sh.k, sh.vt, pp, views->cams, sp, st)) != hipSuccess) return hip_fail(ctx, e, "raster");
@@ -495,14 +498,17 @@ bgt_status bgt_render_bwd(bgt_ctx *ctx, const bgt_prims *prims, const bgt_views 
     if (k.K > 0 && !gp.sh) return fail(ctx, BGT_E_INVALID, "null SH gradient array");
     hipError_t e = hipSuccess;
     const int64_t nc = 3LL * k.ncp * k.P;
-    if (k.K > 0 && (e = launch_fill_f32(gp.sh, 0.f, 3LL * k.K * k.P, st)) != hipSuccess) return hip_fail(ctx, e, "fill");
-    if ((e = launch_fill_f32(gp.ctrl, 0.f, nc, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.color, 0.f, nc, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.log_scale, 0.f, 3LL * k.T * k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.quat, 0.f, 4LL * k.T * k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.opacity, 0.f, k.P, st)) != hipSuccess ||
-        (e = launch_fill_f32(gp.sharp, 0.f, k.P, st)) != hipSuccess)
-        return hip_fail(ctx, e, "fill");
+    {  // the gradient arrays are sums: they start at zero
+        ZeroTable z;
+        if (k.K > 0) z.add(gp.sh, 3LL * k.K * k.P);
+        z.add(gp.ctrl, nc);
+        z.add(gp.color, nc);
+        z.add(gp.log_scale, 3LL * k.T * k.P);
+        z.add(gp.quat, 4LL * k.T * k.P);
+        z.add(gp.opacity, k.P);
+        z.add(gp.sharp, k.P);
+        if ((e = launch_zero(z, st)) != hipSuccess) return hip_fail(ctx, e, "clear");
+    }
     {
         StageTimer tm(ctx, 4, st);
         if ((e = launch_blend_bwd(k, sh.vt, sp, images, grad_images, st)) != hipSuccess) return hip_fail(ctx, e, "blend_bwd");

@@ -12,40 +12,37 @@
 
 namespace bgt {
 
-// ------------------------------------------------------------ fill kernels
+// ------------------------------------------------------------ clearing
 
-__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-__global__ void k_fill_f32(float *p, float v, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+// Clears the table's segments laid end to end in 16-byte chunks, each
+// segment's chunks starting at its own base: one store per chunk, or word by
+// word for a segment's last chunk and for a base that is not 16-byte aligned.
+__global__ void k_zero(ZeroTable t, int64_t total_chunks) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int s = 0;
+        int64_t first = 0;  // first chunk of segment s
+        while (s + 1 < t.n && c >= first + ((t.words[s] + 3) >> 2)) {
+            first += (t.words[s] + 3) >> 2;
+            ++s;
+        }
+        const int64_t w = (c - first) * 4, n = t.words[s];
+        uint32_t *q = t.p[s] + w;
+        if (w + 4 <= n && ((uintptr_t)t.p[s] & 15) == 0) {
+            *(uint4 *)q = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int i = 0; i < 4 && w + i < n; ++i) q[i] = 0u;
+        }
+    }
 }
 
-static int fill_grid(int64_t n) {
-    int64_t b = (n + 255) / 256;
+hipError_t launch_zero(const ZeroTable &t, hipStream_t s) {
+    int64_t chunks = 0;
+    for (int i = 0; i < t.n; ++i) chunks += (t.words[i] + 3) >> 2;
+    if (chunks == 0) return hipSuccess;
+    int64_t b = (chunks + 255) / 256;
     if (b > 4096) b = 4096;
-    return (int)(b < 1 ? 1 : b);
-}
-
-hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
-    return hipGetLastError();
-}
-hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
-    return hipGetLastError();
-}
-hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_f32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)b), dim3(256), 0, s, t, chunks);
     return hipGetLastError();
 }
 

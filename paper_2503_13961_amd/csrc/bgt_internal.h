@@ -313,9 +313,19 @@ hipError_t launch_blend_bwd(const Consts &k, const ViewTable &vt, const StatePtr
                             const float *image, const float *grad_image, hipStream_t s);
 hipError_t launch_param_bwd(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                             const StatePtrs &st, const GradPtrs &gr, hipStream_t s);
-hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
-hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+// Arrays cleared by one launch, as 4-byte words (a segment with no words is
+// left out): the pass's counters, z-buffer and tile counts, or a backward
+// pass's gradient arrays
+constexpr int kZeroSegs = 8;
+struct ZeroTable {
+    uint32_t *p[kZeroSegs];
+    int64_t words[kZeroSegs];
+    int n = 0;
+    void add(void *ptr, int64_t w) {
+        if (w > 0 && n < kZeroSegs) { p[n] = (uint32_t *)ptr; words[n] = w; ++n; }
+    }
+};
+hipError_t launch_zero(const ZeroTable &t, hipStream_t s);
 void loss_tiles(int W, int H, int *tiles_x, int *tiles);
 hipError_t launch_loss(const LossTable &lt, const float *x, const float *y, float *loss, float *grad, float *maps,
                        double *partial, hipStream_t s);
