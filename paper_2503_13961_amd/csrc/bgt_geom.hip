@@ -160,55 +160,63 @@ hipError_t launch_tessellate(const Consts &k, const PrimPtrs &pr, double *wverts
 // map, one rotation and scale per patch: R(q/|q|) diag(exp(log_scale)) and
 // r_b^2 = (r_ref / sharpness)^2 in FP64.
 __global__ void k_prim_setup(Consts k, PrimPtrs pr, float *patch) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= k.P) return;
-    const int ncp = k.ncp;
+    // one thread per word of a patch record, the patch index fastest (the
+    // parameter arrays are read in runs of consecutive patches); the thread
+    // of M's first word computes the rotation-scale setup and writes all 20
+    // of its words
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)k.P * k.pdw) return;
+    const int p = (int)(idx % k.P), i = (int)(idx / k.P);
+    const int ncp = k.ncp, mo = patch_m_off(ncp), qo = patch_q_off(ncp);
+    const int xo = patch_x_off(ncp), so = patch_sh_off(ncp, k.T);
+    const bool ext = k.T > 1 || k.K > 0;  // the texels and SH coefficients are stored
     float *o = patch + (int64_t)p * k.pdw;
-    for (int c = 0; c < ncp; ++c)
-        for (int d = 0; d < 3; ++d) {
-            o[3 * c + d] = pr.ctrl[((int64_t)d * ncp + c) * k.P + p];
-            o[3 * ncp + 3 * c + d] = pr.color[((int64_t)d * ncp + c) * k.P + p];
-        }
-    o[6 * ncp] = pr.opacity[p];
-    o[6 * ncp + 1] = 0.f;
-    double q[4], qn = 0.0;
+    if (i < 6 * ncp) {
+        const float *src = i < 3 * ncp ? pr.ctrl : pr.color;
+        const int j = i < 3 * ncp ? i : i - 3 * ncp, c = j / 3, d = j % 3;
+        o[i] = src[((int64_t)d * ncp + c) * k.P + p];
+    } else if (i == 6 * ncp) {
+        o[i] = pr.opacity[p];
+    } else if (i == 6 * ncp + 1) {
+        o[i] = 0.f;
+    } else if (i == mo) {
+        double q[4], qn = 0.0;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
-    qn = sqrt(qn);
+        for (int d = 0; d < 4; ++d) { q[d] = pr.quat[(int64_t)d * k.T * k.P + p]; qn += q[d] * q[d]; }
+        qn = sqrt(qn);
 #pragma unroll
-    for (int d = 0; d < 4; ++d) q[d] /= qn;
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                          2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-    double sc[3];
+        for (int d = 0; d < 4; ++d) q[d] /= qn;
+        const double w = q[0], x = q[1], y = q[2], z = q[3];
+        const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                              2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                              2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        double sc[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) sc[d] = exp((double)pr.log_scale[(int64_t)d * k.T * k.P + p]);
-    double *m = (double *)(o + patch_m_off(ncp));
+        for (int d = 0; d < 3; ++d) sc[d] = exp((double)pr.log_scale[(int64_t)d * k.T * k.P + p]);
+        double *m = (double *)(o + mo);
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m[3 * r + c] = Rq[3 * r + c] * sc[c];
-    const double rb = (double)k.r_ref / (double)pr.sharp[p];
-    m[9] = rb * rb;
-    float *raw = o + patch_q_off(ncp);
-    for (int d = 0; d < 4; ++d) raw[d] = pr.quat[(int64_t)d * k.T * k.P + p];
-    for (int d = 0; d < 3; ++d) raw[4 + d] = pr.log_scale[(int64_t)d * k.T * k.P + p];
-    raw[7] = pr.sharp[p];
-    int end = patch_q_off(ncp) + 8;
-    if (k.T > 1 || k.K > 0) {
-        // every texel of the rotation and scale maps, then the SH coefficients
-        float *tx = o + patch_x_off(ncp);
-        for (int t = 0; t < k.T; ++t) {
-            for (int d = 0; d < 4; ++d) tx[7 * t + d] = pr.quat[((int64_t)d * k.T + t) * k.P + p];
-            for (int d = 0; d < 3; ++d) tx[7 * t + 4 + d] = pr.log_scale[((int64_t)d * k.T + t) * k.P + p];
-        }
-        float *shc = o + patch_sh_off(ncp, k.T);
-        for (int j = 0; j < k.K; ++j)
-            for (int c = 0; c < 3; ++c) shc[3 * j + c] = pr.sh[((int64_t)c * k.K + j) * k.P + p];
-        end = patch_sh_off(ncp, k.T) + 3 * k.K;
+            for (int c = 0; c < 3; ++c) m[3 * r + c] = Rq[3 * r + c] * sc[c];
+        const double rb = (double)k.r_ref / (double)pr.sharp[p];
+        m[9] = rb * rb;
+    } else if (i < qo) {
+        // (M's other words)
+    } else if (i < qo + 4) {  // the raw quaternion, log-scales and sharpness
+        o[i] = pr.quat[(int64_t)(i - qo) * k.T * k.P + p];
+    } else if (i < qo + 7) {
+        o[i] = pr.log_scale[(int64_t)(i - qo - 4) * k.T * k.P + p];
+    } else if (i == qo + 7) {
+        o[i] = pr.sharp[p];
+    } else if (ext && i < xo + 7 * k.T) {  // every texel of the rotation and scale maps
+        const int t = (i - xo) / 7, e = (i - xo) % 7;
+        o[i] = e < 4 ? pr.quat[((int64_t)e * k.T + t) * k.P + p] : pr.log_scale[((int64_t)(e - 4) * k.T + t) * k.P + p];
+    } else if (ext && i < so + 3 * k.K) {  // then the SH coefficients
+        const int j = (i - so) / 3, c = (i - so) % 3;
+        o[i] = pr.sh[((int64_t)c * k.K + j) * k.P + p];
+    } else {
+        o[i] = 0.f;
     }
-    for (int i = end; i < k.pdw; ++i) o[i] = 0.f;
 }
 
 // ------------------------------------------------------------ projection
@@ -945,7 +953,8 @@ hipError_t launch_raster(const Consts &k, const ViewTable &vt, const PrimPtrs &p
 
 hipError_t launch_gen(const Consts &k, const ViewTable &vt, const PrimPtrs &pr, const float *cams,
                       const StatePtrs &st, hipStream_t s) {
-    hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)((k.P + 255) / 256)), dim3(256), 0, s, k, pr, st.patch);
+    hipLaunchKernelGGL(k_prim_setup, dim3((unsigned)(((int64_t)k.P * k.pdw + 255) / 256)), dim3(256), 0, s, k, pr,
+                       st.patch);
     const bool ext = k.T > 1 || k.K > 0;  // resolution-3 maps or SH colour
     {
         dim3 grid((unsigned)((vt.total_b8 + 3) / 4)), block(256);  // one wave per 8x8 block
