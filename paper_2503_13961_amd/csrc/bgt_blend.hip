@@ -633,6 +633,7 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
     if (pf.gp >= 0) stage_slot<TS, K, true>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, kappa);
     for (int base = 0; base < gc; base += K) {
         if (__syncthreads_and(done ? 1 : 0)) break;  // also publishes the staged batch
+        int stop_kk = -1;  // batch index of the entry at which this pixel stops in this batch
         pf.issue(st, gs0, gc, base + K, tid, K);     // next batch's records, in flight during compositing
         const int nk = min(K, gc - base);
         if (!__all(done)) {
@@ -683,11 +684,16 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         C1 += ta * c.y;
                         C2 += ta * c.z;
                         T = T * (1.0f - a);
-                        if (live && T < tmin) { done = true; last = base + kk + 1; }
+                        // (the stopping entry's batch index; the list index is
+                        // formed once per batch below)
+                        const bool stop = live && T < tmin;
+                        done = done || stop;
+                        stop_kk = stop ? kk : stop_kk;
                     } while (__any(mm != 0u));
                 }
             }
         }
+        if (stop_kk >= 0) last = base + stop_kk + 1;
         __syncthreads();  // everyone is done with this batch
         if (pf.gp >= 0) stage_slot<TS, K, true>(S, pf, tid, ox, oy, B.run_prim, n_full, slow_b, kappa);
     }
