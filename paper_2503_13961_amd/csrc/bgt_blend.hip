@@ -101,11 +101,43 @@ struct BoundaryLds {
 // BOUND: the forward's layout, whose colour carries the sub-block bound
 template <int TS, int K, bool BOUND>
 struct BatchLds {
-    float2 m[TS * TS / 64][K];  // per-wave mean offsets
+    // per-wave mean offsets and (primitive id, run index); in the forward at
+    // 8 px (one wave) side by side in 16-byte records like e and c, so that
+    // one address serves every per-entry read (the backward, whose entry is
+    // wave-uniform, keeps them apart: packed, its compiler moved the means to
+    // scalar registers at two more instructions per entry)
+    static constexpr bool PACK = TS == 8 && BOUND;
+    struct MP {
+        float2 m;
+        int2 pr;
+    };
+    struct Packed {
+        MP mp[K];
+    };
+    struct Apart {
+        float2 m[TS * TS / 64][K];
+        int2 pr[K];
+    };
+    typename std::conditional<PACK, Packed, Apart>::type mpr;
     float4 e[K];                // conic in exponent form kE (a, 2b, c), opacity
     float4 c[K];                // colour; w (forward): exponent below which no pixel of a 4x4 sub-block is in the support
-    int2 pr[K];                 // primitive id, run index
     int xr[K], yr[K];
+    __device__ __forceinline__ float2 &m(int w, int kk) {
+        if constexpr (PACK) return mpr.mp[kk].m;
+        else return mpr.m[w][kk];
+    }
+    __device__ __forceinline__ int2 &pr(int kk) {
+        if constexpr (PACK) return mpr.mp[kk].pr;
+        else return mpr.pr[kk];
+    }
+    __device__ __forceinline__ const float2 &m(int w, int kk) const {
+        if constexpr (PACK) return mpr.mp[kk].m;
+        else return mpr.m[w][kk];
+    }
+    __device__ __forceinline__ const int2 &pr(int kk) const {
+        if constexpr (PACK) return mpr.mp[kk].pr;
+        else return mpr.pr[kk];
+    }
 };
 
 // |q - b| has its cone point at d = 0, where the subgradient taken is 0; a
@@ -441,7 +473,7 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K, BOUND> &S, const Slot
     const int x = lo16(a) - ox, y = hi16(a) - oy;
 #pragma unroll
     for (int w = 0; w < G::NT / 64; ++w)
-        S.m[w][kk] = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
+        S.m(w, kk) = make_float2((float)(x - (w % G::SPR) * 8) + P.r0.x, (float)(y - (w / G::SPR) * 8) + P.r0.y);
     S.e[kk] = make_float4(kE * P.r0.z, 2.0f * kE * P.r0.w, kE * P.r1.x, P.r2.x);
     S.c[kk] = make_float4(P.r1.y, P.r1.z, P.r1.w, BOUND ? sub_block_bound(P.r0.z, P.r0.w, P.r1.x, kappa) : 0.f);
     const int g = __float_as_int(P.r2.y);
@@ -450,7 +482,7 @@ __device__ __forceinline__ void stage_slot(BatchLds<TS, K, BOUND> &S, const Slot
     // them is searched in global memory
     int r = find_run(run_prim, n_runs, g);
     if (r < 0 && slow_b) r = -2;
-    S.pr[kk] = make_int2(g, r);
+    S.pr(kk) = make_int2(g, r);
     S.xr[kk] = __float_as_int(P.r3.x);
     S.yr[kk] = __float_as_int(P.r3.y);
 }
@@ -492,7 +524,7 @@ __device__ __forceinline__ void sub_block_masks(const BatchLds<TS, K, true> &S, 
     const int j = c0 + lane, jj = j < K ? j : K - 1;
     const bool in = j < n;
     const int a = S.xr[jj], b = S.yr[jj];
-    const float2 m = S.m[wave][jj];
+    const float2 m = S.m(wave, jj);
     const float4 ex = S.e[jj];
     const float thr = S.c[jj].w;
     // exponents at the sub-block centres (1.5 | 5.5, 1.5 | 5.5) of the wave's block
@@ -650,8 +682,8 @@ __global__ void __launch_bounds__(TS *TS) k_blend_fwd(Consts k, ViewTable vt, St
                         const bool act = mm != 0u;
                         const int kk = c0 + hb + low_bit(mm);
                         mm &= mm - 1u;
-                        const int2 pr = S.pr[kk];
-                        const float2 m = S.m[wave][kk];
+                        const int2 pr = S.pr(kk);
+                        const float2 m = S.m(wave, kk);
                         const float4 ex = S.e[kk];
                         const float4 c = S.c[kk];
                         const int g = pr.x, r = pr.y;  // uniform within the row
@@ -842,10 +874,10 @@ k_blend_bwd(Consts k, ViewTable vt, StatePtrs st, const float *image,
             while (mask) {
                 const int kk = c0 + __ffsll((long long)mask) - 1;  // wave-uniform
                 mask &= mask - 1;
-                const int2 prk = S.pr[kk];
+                const int2 prk = S.pr(kk);
                 const int g = prk.x;
                 const int r = __builtin_amdgcn_readfirstlane(prk.y);
-                const float2 m = S.m[wave][kk];
+                const float2 m = S.m(wave, kk);
                 const float4 ex = S.e[kk];
                 const float4 c = S.c[kk];
                 const bool own = g == h || nob;  // w = 1 for all without coefficients
